@@ -1,0 +1,18 @@
+"""FP64 CPU reference ("oracle") for the bound-propagation hot path.
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline of the benchmark.  It shares no code with the GPU library and is never a
+fallback for it.  Parity status per function:
+
+* crown.relu_relaxation, ibp_next, affine_box, concretize_box, backward,
+  intermediate_bounds, final_bounds, crown: pinned (closed forms, linear and
+  all-stable networks, zero-radius boxes, brute force by pattern enumeration + LP,
+  dense sampling).
+* crown.gradient / evaluate_duals: pinned (central finite differences, and an
+  independent torch-FP64 autograd of the same bound).
+* crown.optimize_duals: pinned (one-neuron and split hand cases, strong duality
+  against the LP optimum, soundness against brute force).
+* tm.reach_dt: pinned (B = 0 closed form A^t x +- |A^t| r, all-stable linear
+  closed loop, dense sampled rollouts).
+"""
+from . import crown, exact, tm  # noqa: F401
