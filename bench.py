@@ -1,0 +1,331 @@
+"""Throughput of the bound-propagation hot path on one MI355X.
+
+Default workload (the headline): batched plain CROWN on the 6-64x3-3 network, 4096
+subdomains with 0-8 ReLU splits each, FP32 matrix-core chains with FP64 concretization
+and rigorous rounding margins.  One step = dr_bound_init (layer-1 bounds, IBP, CROWN
+intermediate bounds, relaxation) + dr_propagate_backward (spec rows) + dr_concretize,
+replayed from a HIP graph with the inputs resident in HBM.
+
+Also measured (reported under "extra", each with its own roofline figure):
+  * alpha/beta projected gradient ascent (20 steps, lr 0.1) on 8-128x4-4, 2048 subdomains;
+  * stepwise linear-TM closed-loop reachability, 12-256x3-4, 8192 boxes, horizon 10;
+  * the mixed persistent batch: 16384 subdomains over three networks, 0-32 splits,
+    plain CROWN + 10 dual steps in one graph;
+  * the FP64-chain variant of the headline workload.
+The FP64 reference is timed on the host on a bounded sample ("cpu_baseline").
+
+Prints ONE JSON line.  Multi-GPU runs are not supported by this build.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
+PEAK_HBM_GBS = 8000.0
+
+
+def chain_flops_per_row(widths, k):
+    """Algorithmic FLOPs (2 per MAC) of one backward chain row that starts at hidden
+    layer k (its first product is a gather of a weight row, 0 FLOPs): the products
+    with W_{k-1} .. W_1."""
+    return sum(2 * widths[j] * widths[j - 1] for j in range(1, k))
+
+
+def final_flops_per_row(widths):
+    L = len(widths) - 1
+    return 2 * widths[L] * widths[L - 1] + chain_flops_per_row(widths, L)
+
+
+def bound_init_flops(nets, net_id, rows):
+    """Intermediate-bound chains actually required: rows[s][k-1] rows at layer k."""
+    tot = 0
+    for s in range(rows.shape[0]):
+        w = nets[int(net_id[s])].widths
+        for k in range(2, len(w) - 1):
+            tot += int(rows[s, k - 1]) * chain_flops_per_row(w, k)
+    return tot
+
+
+def final_flops(nets, net_id, status, R):
+    tot = 0
+    for s in range(len(net_id)):
+        if status[s] & 9:
+            continue
+        tot += R * final_flops_per_row(nets[int(net_id[s])].widths)
+    return tot
+
+
+class KernelTimer:
+    """HIP events around launches on torch's current stream (the stream the library
+    launches on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.ms = []
+
+    def run(self, fn):
+        ev0 = self.torch.cuda.Event(enable_timing=True)
+        ev1 = self.torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        out = fn()
+        ev1.record()
+        self.pending = (ev0, ev1)
+        return out
+
+    def collect(self):
+        ev0, ev1 = self.pending
+        ev1.synchronize()
+        self.ms.append(ev0.elapsed_time(ev1))
+
+
+def time_graph(torch, step, steps, warmup):
+    """Capture `step` into a HIP graph; replay warmup + steps times; return ms/step."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, g
+
+
+def headline(torch, args, precision="f32"):
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(2)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=8)
+    db = DeviceBatch(wl.batch)
+    q, n0 = ctx.q, ctx.n0
+    f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+    aff = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
+    out = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+
+    def step():
+        ctx.dr_bound_init(db)
+        ctx.dr_propagate_backward(aff)
+        ctx.dr_concretize(*aff, out=out)
+
+    ms, graph = time_graph(torch, step, args.steps, args.warmup)
+    # dominant kernel (k_bound_init) timed alone with HIP events on the same stream
+    kt = KernelTimer(torch)
+    for _ in range(max(args.steps, 5)):
+        kt.run(lambda: ctx.dr_bound_init(db))
+        kt.collect()
+    bi_ms = float(np.mean(kt.ms[1:])) if len(kt.ms) > 1 else kt.ms[0]
+    rows = ctx.dr_get_rows().cpu().numpy()
+    status = out[2].cpu().numpy()
+    flops_bi = bound_init_flops(wl.nets, wl.batch.net_id, rows)
+    flops_fin = final_flops(wl.nets, wl.batch.net_id, status, ctx.R)
+    achieved = flops_bi / (bi_ms * 1e-3) / 1e12
+    res = dict(ms=ms, S=S, bi_ms=bi_ms, flops_bi=flops_bi, flops_final=flops_fin, achieved=achieved,
+               step_tflops=(flops_bi + flops_fin) / (ms * 1e-3) / 1e12, infeasible=int(np.sum(status & 1)))
+    ctx.close()
+    return res, wl
+
+
+def dual_ascent(torch, args, precision="f32"):
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(3)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=16)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    q = ctx.q
+    out = (torch.zeros(S, q, dtype=torch.float64, device="cuda"), torch.zeros(S, q, dtype=torch.float64, device="cuda"),
+           torch.zeros(S, dtype=torch.int32, device="cuda"))
+    aff_lb = None
+
+    def step():
+        ctx.dr_optimize_duals(wl.iters, wl.lr, alpha, beta, init_duals=True, out=out)
+
+    ms, _ = time_graph(torch, step, max(2, args.steps // 4), 1)
+    status = out[2].cpu().numpy()
+    live = int(np.sum((status & 9) == 0))
+    # per evaluation: forward chain + adjoint chain (same products transposed)
+    fpr = final_flops_per_row(wl.nets[0].widths)
+    w = wl.nets[0].widths
+    adj = sum(2 * w[j] * w[j - 1] for j in range(1, len(w) - 1))
+    flops = live * ctx.R * ((wl.iters + 1) * fpr + wl.iters * adj)
+    res = dict(ms=ms, S=S, iters=wl.iters, subdomain_iters_per_s=S * wl.iters / (ms * 1e-3),
+               tflops=flops / (ms * 1e-3) / 1e12)
+    ctx.close()
+    return res
+
+
+def tm_reach(torch, args, precision="f32"):
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(4)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S)
+    db = DeviceBatch(wl.batch)
+    boxes = torch.zeros(S, wl.horizon + 1, ctx.n0, 2, dtype=torch.float64, device="cuda")
+
+    def step():
+        ctx.dr_reach_dt(db, wl.horizon, boxes=boxes)
+
+    ms, _ = time_graph(torch, step, max(2, args.steps // 4), 1)
+    rows = ctx.dr_get_rows().cpu().numpy()
+    w = wl.nets[0].widths
+    L = len(w) - 1
+    flops = 0
+    for k in range(2, L):
+        flops += int(rows[:, k - 1].sum()) * chain_flops_per_row(w, k)
+    flops += int(rows[:, L - 1].sum()) * final_flops_per_row(w)
+    res = dict(ms=ms, S=S, horizon=wl.horizon, box_steps_per_s=S * wl.horizon / (ms * 1e-3),
+               tflops=flops / (ms * 1e-3) / 1e12)
+    ctx.close()
+    return res
+
+
+def mixed_batch(torch, args, precision="f32"):
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(5)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=32)
+    db = DeviceBatch(wl.batch)
+    alpha, beta = ctx.new_duals()
+    q, n0 = ctx.q, ctx.n0
+    f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+    aff = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
+    cout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+    dout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+
+    def step():
+        ctx.dr_bound_init(db)
+        ctx.dr_propagate_backward(aff)
+        ctx.dr_concretize(*aff, out=cout)
+        ctx.dr_optimize_duals(wl.iters, wl.lr, alpha, beta, init_duals=True, out=dout)
+
+    ms, _ = time_graph(torch, step, max(2, args.steps // 4), 1)
+    res = dict(ms=ms, S=S, iters=wl.iters, subdomains_per_s=S / (ms * 1e-3))
+    ctx.close()
+    return res
+
+
+def cpu_baseline(wl, budget_s=15.0):
+    """The FP64 reference, as it stands, on a bounded sample of the headline batch."""
+    from oracle import crown
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    n = 0
+    t0 = time.perf_counter()
+    ctxm = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        while time.perf_counter() - t0 < budget_s and n < wl.batch.n_sub:
+            s = n
+            net = wl.nets[int(wl.batch.net_id[s])]
+            crown.crown(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.batch.splits_of(s))
+            n += 1
+    finally:
+        if ctxm is not None:
+            ctxm.__exit__(None, None, None)
+    dt = time.perf_counter() - t0
+    return dict(value=n / dt, unit="subdomains/s", cores=1, kind="oracle",
+                sample=f"first {n} of {wl.batch.n_sub} subdomains of the headline batch, "
+                       f"{dt:.1f} s wall, one thread (numpy FP64)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU scaling is not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    print("bench: headline workload", file=sys.stderr, flush=True)
+    hl, wl = headline(torch, args, "f32")
+    extra = {}
+    if not args.no_extra:
+        print("bench: f64 headline", file=sys.stderr, flush=True)
+        h64, _ = headline(torch, args, "f64")
+        extra["crown_6-64x3-3_S4096_f64"] = dict(
+            subdomains_per_s=h64["S"] / (h64["ms"] * 1e-3), ms_per_step=h64["ms"],
+            roofline=dict(bound="mfma", achieved=h64["achieved"], peak=PEAK_TFLOPS["f64"], unit="TFLOP/s",
+                          frac=h64["achieved"] / PEAK_TFLOPS["f64"]))
+        print("bench: dual ascent", file=sys.stderr, flush=True)
+        da = dual_ascent(torch, args, "f32")
+        extra["abcrown_8-128x4-4_S2048_20it"] = dict(
+            subdomain_iters_per_s=da["subdomain_iters_per_s"], ms_per_call=da["ms"],
+            roofline=dict(bound="mfma", achieved=da["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                          frac=da["tflops"] / PEAK_TFLOPS["f32"]))
+        print("bench: TM reach", file=sys.stderr, flush=True)
+        tr = tm_reach(torch, args, "f32")
+        extra["tmreach_12-256x3-4_S8192_H10"] = dict(
+            box_steps_per_s=tr["box_steps_per_s"], ms_per_call=tr["ms"],
+            roofline=dict(bound="mfma", achieved=tr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                          frac=tr["tflops"] / PEAK_TFLOPS["f32"]))
+        print("bench: mixed batch", file=sys.stderr, flush=True)
+        mb = mixed_batch(torch, args, "f32")
+        extra["mixed_S16384_crown+10it"] = dict(subdomains_per_s=mb["subdomains_per_s"], ms_per_step=mb["ms"])
+    print("bench: cpu baseline", file=sys.stderr, flush=True)
+    cb = cpu_baseline(wl, args.cpu_budget)
+    value = hl["S"] / (hl["ms"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "subdomains/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": hl["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "crown_6-64x3-3_S4096", "network": "6-64-64-64-3", "subdomains": hl["S"],
+                   "splits_per_subdomain": "0-8", "spec": "lower+upper of 3 outputs",
+                   "chain_precision": "f32", "concretize": "f64", "margins": "rigorous",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": hl["achieved"], "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                     "frac": hl["achieved"] / PEAK_TFLOPS["f32"], "traffic": None,
+                     "kernel": "k_bound_init", "kernel_ms": hl["bi_ms"], "flops_per_launch": hl["flops_bi"]},
+        "cpu_baseline": cb,
+        "extra": extra,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

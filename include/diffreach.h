@@ -1,0 +1,197 @@
+/*
+ * diffreach.h -- C-ABI of the gfx950 bound-propagation library (libdiffreach.so).
+ *
+ * Batched CROWN-style linear bound propagation for ReLU networks, alone or in a
+ * closed loop x' = A x + B y, as used by the paper "Parallel Differentiable
+ * Reachability for Learning and Planning with Certified Neural Dynamics and
+ * Controllers":
+ *   - Theorem "CROWN linear bounds of NN": affine lower/upper bounds
+ *       W_lo x + b_lo <= f(x) <= W_hi x + b_hi   over an input box;
+ *   - Algorithm "Reachability of DT Dynamics": CROWN followed by EvalInt (the
+ *     box enclosure) at every step, with the TM--CROWN interface of Theorem
+ *     "CROWN bounds of NN with linear TM input" and the shared-slope constraint;
+ *   - "Gradient" refinement of the table "Refinement strategies": projected
+ *     gradient ascent on the relaxation slopes alpha and split multipliers beta.
+ *
+ * Conventions shared by every entry point
+ *   - All array arguments are DEVICE pointers owned by the caller unless stated
+ *     otherwise; the library never frees them.  Host-side structs (dr_network,
+ *     dr_batch, dr_options) are read during the call only.
+ *   - Every call after dr_create is asynchronous on `stream`, allocates nothing,
+ *     never synchronises and never reads device memory on the host, so a sequence
+ *     of calls can be captured into a HIP graph and replayed.
+ *   - Argument and shape errors are returned synchronously as dr_status (the call
+ *     then launches nothing) and described by dr_last_error.  Numerical trouble is
+ *     never an error: it becomes per-subdomain status bits (DR_RES_*).
+ *   - Network: z_1 = W_1 x + b_1, h_k = relu(z_k), z_{k+1} = W_{k+1} h_k + b_{k+1},
+ *     y = z_L; W_k row-major n_k x n_{k-1}.  Hidden neurons of all layers are
+ *     indexed in one concatenated range [0, H), layer k starting at
+ *     n_1 + ... + n_{k-1}.
+ *   - Spec: q directions c_r over the target (the network output y, or x' in
+ *     the closed loop).  For each direction the library bounds c_r . target from
+ *     below (row r) and from above (row q + r, computed as minus the lower bound
+ *     of -c_r . target).  Default directions are the unit vectors.
+ *   - A subdomain is a box [x_c - x_r, x_c + x_r] plus split constraints
+ *     (hidden layer k, neuron j, sign s): s = +1 means z_k[j] >= 0, s = -1 means
+ *     z_k[j] <= 0, packed as  (k << 24) | ((s > 0) << 16) | j.
+ *   - Arithmetic (dr_options.precision): DR_PREC_F32 runs the coefficient chains
+ *     on FP32 MFMA with FP32 accumulation; DR_PREC_F64 on FP64 MFMA.  Bounds,
+ *     boxes, offsets and concretization are FP64 in both.  Every bound includes
+ *     an outward margin covering the rounding of the chains (a priori error
+ *     bound of the dot products), so it is sound in either precision; the
+ *     margin is exported per result (dr_get_margins).
+ */
+#ifndef DIFFREACH_H
+#define DIFFREACH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dr_ctx dr_ctx;
+
+typedef enum {
+  DR_OK = 0,
+  DR_EINVAL = -1,    /* null pointer, bad option or unsupported combination */
+  DR_ESHAPE = -2,    /* widths/sizes out of the supported range */
+  DR_ENOMEM = -3,    /* device allocation failed (dr_create only) */
+  DR_EDEVICE = -4,   /* a HIP runtime call failed */
+  DR_ECAPACITY = -5  /* batch larger than the context was created for */
+} dr_status;
+
+/* Per-subdomain status bits written to caller buffers. */
+enum {
+  DR_RES_OK = 0,
+  DR_RES_INFEASIBLE = 1, /* split constraints contradict the bounds (some l > u) */
+  DR_RES_NONFINITE = 2,  /* NaN or Inf met in the inputs or the chain */
+  DR_RES_MARGIN = 4,     /* rounding margin larger than the bound's own magnitude */
+  DR_RES_BADSPLIT = 8    /* split list invalid (bad layer/neuron, or too many) */
+};
+
+enum { DR_PREC_F32 = 0, DR_PREC_F64 = 1 };
+enum { DR_DTYPE_F32 = 0, DR_DTYPE_F64 = 1 };
+enum { DR_INTER_CROWN_IBP = 0, DR_INTER_IBP = 1 };
+enum { DR_MARGIN_RIGOROUS = 0, DR_MARGIN_OFF = 1 };
+
+typedef struct {
+  int n_layers;               /* L >= 2 (at least one hidden layer), L <= 8 */
+  const int* widths;          /* HOST array n_0..n_L; hidden n_k <= 256, n_0 <= 64, n_L <= 64 */
+  int wdtype;                 /* DR_DTYPE_F32 or DR_DTYPE_F64: element type of W and b */
+  const void* const* W;       /* HOST array of L device pointers, W_k row-major n_k x n_{k-1} */
+  const void* const* b;       /* HOST array of L device pointers, b_k of n_k */
+  const double* A;            /* device n_state x n_0 (closed loop) or NULL */
+  const double* B;            /* device n_state x n_L (closed loop) or NULL */
+  int n_state;                /* rows of A and B; 0 without closed loop (requires n_0 == n_state) */
+  const double* spec;         /* device q x n_target directions, or NULL for unit vectors */
+  int n_spec;                 /* q (ignored when spec == NULL) */
+} dr_network;
+
+typedef struct {
+  int n_sub;                  /* number of subdomains S */
+  const int* net_id;          /* device S (index into the networks of dr_create), or NULL = all 0 */
+  const double* x_center;     /* device S x n_0 */
+  const double* x_radius;     /* device S x n_0, >= 0 */
+  const int* split_ptr;       /* device S + 1 CSR offsets, or NULL = no splits */
+  const uint32_t* split_packed; /* device split words (see header comment) */
+} dr_batch;
+
+typedef struct {
+  int precision;              /* DR_PREC_F32 or DR_PREC_F64 */
+  int intermediate;           /* DR_INTER_CROWN_IBP (default) or DR_INTER_IBP */
+  int max_sub;                /* capacity: largest batch S for this context */
+  int max_splits;             /* capacity: splits per subdomain (beta columns) */
+  int tile_cfg;               /* 0 = default launch shape; >0 = autotuner config id */
+  int margin_mode;            /* DR_MARGIN_RIGOROUS (default) or DR_MARGIN_OFF (diagnostics only:
+                                 rounding of the chains is then not covered, bounds may be unsound) */
+} dr_options;
+
+/* Create a context for one or more networks sharing n_0 and the spec length.
+ * Copies and re-lays-out the weights (asynchronously on `stream`) and allocates
+ * all scratch for batches of up to opt->max_sub subdomains.  The only call that
+ * allocates device memory.  Returns DR_OK and *ctx, or an error and *ctx = NULL. */
+dr_status dr_create(dr_ctx** ctx, const dr_network* nets, int n_nets, const dr_options* opt,
+                    hipStream_t stream);
+
+/* Steps a1-a4: ingest a batch, compute exact layer-1 bounds, interval (IBP)
+ * bounds, CROWN intermediate bounds of every deeper hidden layer for the neurons
+ * IBP leaves unstable and unsplit (intersected with IBP), clamp split neurons and
+ * detect infeasible subdomains; builds the ReLU relaxation of every hidden
+ * neuron.  Results stay in the context for the calls below.  `status` (device,
+ * S, may be NULL) receives DR_RES_* bits.  The batch arrays must stay valid and
+ * unchanged until the last call that uses this batch has completed. */
+dr_status dr_bound_init(dr_ctx* ctx, const dr_batch* batch, uint32_t* status, hipStream_t stream);
+
+/* Step a5: backward propagation of the spec rows through every layer with the
+ * adaptive slopes (plain CROWN).  Writes the affine bounds of Theorem "CROWN
+ * linear bounds of NN" per subdomain and direction:
+ *   lam_lo . x + acc_lo <= c_r . target(x) <= lam_hi . x + acc_hi  on the box,
+ * lam_* S x q x n_0, acc_* S x q (all FP64, device).  The rounding margin is
+ * already folded into acc_*.  Infeasible subdomains get acc_lo = +inf,
+ * acc_hi = -inf and zero slopes. */
+dr_status dr_propagate_backward(dr_ctx* ctx, double* lam_lo, double* acc_lo, double* lam_hi,
+                                double* acc_hi, hipStream_t stream);
+
+/* Step a6: concretization (EvalInt) of affine bounds over each subdomain's box
+ * in FP64 with outward rounding: lb = acc_lo + lam_lo.x_c - |lam_lo|.x_r,
+ * ub = acc_hi + lam_hi.x_c + |lam_hi|.x_r; lb, ub S x q.  `status` (S, may be
+ * NULL) is OR-ed with DR_RES_NONFINITE / DR_RES_MARGIN where they apply. */
+dr_status dr_concretize(dr_ctx* ctx, const double* lam_lo, const double* acc_lo,
+                        const double* lam_hi, const double* acc_hi, double* lb, double* ub,
+                        uint32_t* status, hipStream_t stream);
+
+/* Step a7: projected gradient ascent on the duals of the final bound with the
+ * intermediate bounds of the last dr_bound_init fixed.  Per subdomain and row
+ * (R = 2q rows: lower rows then upper rows) the parameters are alpha (lower
+ * relaxation slopes of unstable neurons, in [0,1]) and beta (one multiplier per
+ * split, >= 0).  Iterates t = 0..iters: evaluate the bound and, by a
+ * hand-written adjoint, its gradient at (alpha_t, beta_t); for t < iters update
+ *   alpha <- clip(alpha + lr * d/dalpha, 0, 1),  beta <- max(0, beta + lr * d/dbeta).
+ *   alpha   S x R x H_max FP32 (in/out; read unless init_duals, where it starts at
+ *           the adaptive slopes); entries of non-unstable neurons are ignored.
+ *   beta    S x R x max_splits FP32 (in/out; starts at 0 when init_duals).
+ *   lb, ub  S x q best-so-far bounds over t = 0..iters (sound at every t).
+ *   grad_alpha, grad_beta (nullable) gradients at the final iterate, same shapes.
+ * iters = 0 evaluates the bound and gradient at the given duals. */
+dr_status dr_optimize_duals(dr_ctx* ctx, int iters, float lr, int init_duals, float* alpha, float* beta,
+                            double* lb, double* ub, float* grad_alpha, float* grad_beta,
+                            uint32_t* status, hipStream_t stream);
+
+/* Step a8: stepwise closed-loop reachability (Algorithm "Reachability of DT
+ * Dynamics") with linear Taylor models: each box is normalised to the TM
+ * x = c + P z, z in [-1,1]^n; every step certifies the controller with
+ * shared-slope CROWN on the TM input, composes x' = A x + B y in TM arithmetic
+ * and evaluates the box.  Needs a closed-loop network with n_state == n_0 and no
+ * splits.  boxes: S x (horizon+1) x n_0 x 2 FP64 (step 0 is the input box). */
+dr_status dr_reach_dt(dr_ctx* ctx, const dr_batch* batch, int horizon, double* boxes, uint32_t* status,
+                      hipStream_t stream);
+
+/* Diagnostics of the last dr_bound_init / dr_propagate_backward /
+ * dr_optimize_duals / dr_reach_dt on this context (device outputs):
+ *   dr_get_bounds  l, u: S x H_max FP64 pre-activation bounds of hidden neurons;
+ *   dr_get_rows    rows: S x 8 int, CROWN chain rows per layer (index k-1 for the
+ *                  rows of hidden layer k; index L-1 for the spec rows), for
+ *                  algorithmic FLOP accounting (reach_dt: summed over steps);
+ *   dr_get_margins margin: S x 2q FP64, rounding margin of each final row of the
+ *                  last dr_propagate_backward or dr_optimize_duals. */
+dr_status dr_get_bounds(dr_ctx* ctx, double* l, double* u, hipStream_t stream);
+dr_status dr_get_rows(dr_ctx* ctx, int* rows, hipStream_t stream);
+dr_status dr_get_margins(dr_ctx* ctx, double* margin, hipStream_t stream);
+
+/* Shape queries (host). */
+int dr_hidden_max(const dr_ctx* ctx);   /* H_max over the networks */
+int dr_spec_rows(const dr_ctx* ctx);    /* R = 2q */
+
+/* Message of the last error on this context (or of the last failed dr_create
+ * when ctx is NULL); never NULL. */
+const char* dr_last_error(const dr_ctx* ctx);
+
+/* Release the context and its scratch (synchronises the device first). */
+void dr_destroy(dr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DIFFREACH_H */

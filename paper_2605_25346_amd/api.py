@@ -1,0 +1,235 @@
+"""Python front end of the C-ABI, with torch tensors as device memory.
+
+Nothing here computes bounds: the class marshals tensors into the C structs and
+calls the entry points of libdiffreach.so under the same names.  Every call is
+asynchronous on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import binding as B
+from .workloads import Batch, Network, pack_splits
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DeviceBatch:
+    """A batch of subdomains resident in device memory."""
+
+    def __init__(self, batch: Batch, device="cuda"):
+        self.n_sub = batch.n_sub
+        self.x_center = torch.as_tensor(batch.x_center, dtype=torch.float64, device=device).contiguous()
+        self.x_radius = torch.as_tensor(batch.x_radius, dtype=torch.float64, device=device).contiguous()
+        self.net_id = torch.as_tensor(batch.net_id, dtype=torch.int32, device=device).contiguous()
+        if batch.split_layer.size > 0 or np.any(batch.split_ptr):
+            self.split_ptr = torch.as_tensor(batch.split_ptr, dtype=torch.int32, device=device).contiguous()
+            words = pack_splits(batch.split_layer, batch.split_neuron, batch.split_sign).astype(np.int64)
+            self.split_packed = torch.as_tensor(words.astype(np.uint32).view(np.int32), device=device).contiguous()
+        else:
+            self.split_ptr = None
+            self.split_packed = None
+        self.max_splits = int(np.max(np.diff(batch.split_ptr))) if batch.n_sub else 0
+
+    def struct(self) -> B.dr_batch:
+        b = B.dr_batch()
+        b.n_sub = self.n_sub
+        b.net_id = self.net_id.data_ptr()
+        b.x_center = self.x_center.data_ptr()
+        b.x_radius = self.x_radius.data_ptr()
+        b.split_ptr = self.split_ptr.data_ptr() if self.split_ptr is not None else None
+        b.split_packed = self.split_packed.data_ptr() if self.split_packed is not None else None
+        return b
+
+
+class BoundContext:
+    """dr_create + the per-batch entry points, holding the device copies of the
+    networks and the output tensors."""
+
+    def __init__(self, nets: Sequence[Network], *, precision="f32", max_sub=1, max_splits=0,
+                 intermediate="crown_ibp", tile_cfg=0, spec: Optional[np.ndarray] = None, device="cuda",
+                 margins=True):
+        self.lib = B.load()
+        self.device = torch.device(device)
+        self.precision = precision
+        wdt = torch.float32 if precision == "f32" else torch.float64
+        self._keep = []
+        structs = (B.dr_network * len(nets))()
+        for i, net in enumerate(nets):
+            L = net.n_layers
+            widths = (ctypes.c_int * (L + 1))(*net.widths)
+            Ws = [torch.as_tensor(W, dtype=wdt, device=self.device).contiguous() for W in net.Ws]
+            bs = [torch.as_tensor(b, dtype=wdt, device=self.device).contiguous() for b in net.bs]
+            Wp = (ctypes.c_void_p * L)(*[W.data_ptr() for W in Ws])
+            bp = (ctypes.c_void_p * L)(*[b.data_ptr() for b in bs])
+            nw = structs[i]
+            nw.n_layers = L
+            nw.widths = widths
+            nw.wdtype = B.DR_DTYPE_F32 if precision == "f32" else B.DR_DTYPE_F64
+            nw.W = Wp
+            nw.b = bp
+            keep = [widths, Ws, bs, Wp, bp]
+            if net.closed_loop:
+                A = torch.as_tensor(net.A, dtype=torch.float64, device=self.device).contiguous()
+                Bm = torch.as_tensor(net.B, dtype=torch.float64, device=self.device).contiguous()
+                nw.A, nw.B, nw.n_state = A.data_ptr(), Bm.data_ptr(), net.A.shape[0]
+                keep += [A, Bm]
+            if spec is not None:
+                C = torch.as_tensor(np.asarray(spec), dtype=torch.float64, device=self.device).contiguous()
+                nw.spec, nw.n_spec = C.data_ptr(), C.shape[0]
+                keep.append(C)
+            self._keep.append(keep)
+        opt = B.dr_options()
+        opt.precision = B.DR_PREC_F32 if precision == "f32" else B.DR_PREC_F64
+        opt.intermediate = B.DR_INTER_CROWN_IBP if intermediate == "crown_ibp" else B.DR_INTER_IBP
+        opt.max_sub = max_sub
+        opt.max_splits = max_splits
+        opt.tile_cfg = tile_cfg
+        opt.margin_mode = B.DR_MARGIN_RIGOROUS if margins else B.DR_MARGIN_OFF
+        ctx = ctypes.c_void_p()
+        st = self.lib.dr_create(ctypes.byref(ctx), structs, len(nets), ctypes.byref(opt), _stream())
+        B.check(st, None)
+        self.ctx = ctx
+        self.n0 = nets[0].widths[0]
+        self.R = self.lib.dr_spec_rows(ctx)
+        self.q = self.R // 2
+        self.H_max = self.lib.dr_hidden_max(ctx)
+        self.max_splits = max_splits
+        self.n_layers = max(n.n_layers for n in nets)
+        self.batch: Optional[DeviceBatch] = None
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            self.lib.dr_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        B.check(st, self.ctx)
+
+    # ---- entry points ---------------------------------------------------------------
+    def dr_bound_init(self, batch: DeviceBatch) -> torch.Tensor:
+        self.batch = batch
+        status = torch.zeros(max(batch.n_sub, 1), dtype=torch.int32, device=self.device)
+        b = batch.struct()
+        self._batch_struct = b
+        self._check(self.lib.dr_bound_init(self.ctx, ctypes.byref(b), _ptr(status), _stream()))
+        return status[: batch.n_sub]
+
+    def dr_propagate_backward(self, out=None):
+        S, q, n0 = self.batch.n_sub, self.q, self.n0
+        if out is None:
+            f = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
+            out = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
+        lam_lo, acc_lo, lam_hi, acc_hi = out
+        self._check(self.lib.dr_propagate_backward(self.ctx, _ptr(lam_lo), _ptr(acc_lo), _ptr(lam_hi),
+                                                   _ptr(acc_hi), _stream()))
+        return out
+
+    def dr_concretize(self, lam_lo, acc_lo, lam_hi, acc_hi, out=None):
+        S, q = self.batch.n_sub, self.q
+        if out is None:
+            out = (torch.empty(S, q, dtype=torch.float64, device=self.device),
+                   torch.empty(S, q, dtype=torch.float64, device=self.device),
+                   torch.zeros(max(S, 1), dtype=torch.int32, device=self.device))
+        lb, ub, status = out
+        self._check(self.lib.dr_concretize(self.ctx, _ptr(lam_lo), _ptr(acc_lo), _ptr(lam_hi), _ptr(acc_hi),
+                                           _ptr(lb), _ptr(ub), _ptr(status), _stream()))
+        return lb, ub, status[:S]
+
+    def new_duals(self):
+        S, R = self.batch.n_sub, self.R
+        alpha = torch.zeros(S, R, max(self.H_max, 1), dtype=torch.float32, device=self.device)
+        beta = torch.zeros(S, R, max(self.max_splits, 1), dtype=torch.float32, device=self.device)
+        return alpha, beta
+
+    def dr_optimize_duals(self, iters, lr, alpha, beta, init_duals=True, grads=False, out=None):
+        S, q = self.batch.n_sub, self.q
+        if out is None:
+            out = (torch.empty(S, q, dtype=torch.float64, device=self.device),
+                   torch.empty(S, q, dtype=torch.float64, device=self.device),
+                   torch.zeros(max(S, 1), dtype=torch.int32, device=self.device))
+        lb, ub, status = out
+        ga = torch.zeros_like(alpha) if grads else None
+        gb = torch.zeros_like(beta) if grads else None
+        self._check(self.lib.dr_optimize_duals(self.ctx, int(iters), float(lr), int(bool(init_duals)), _ptr(alpha),
+                                               _ptr(beta), _ptr(lb), _ptr(ub), _ptr(ga), _ptr(gb), _ptr(status),
+                                               _stream()))
+        return lb, ub, status[:S], ga, gb
+
+    def dr_reach_dt(self, batch: DeviceBatch, horizon: int, boxes=None):
+        self.batch = batch
+        S = batch.n_sub
+        if boxes is None:
+            boxes = torch.empty(S, horizon + 1, self.n0, 2, dtype=torch.float64, device=self.device)
+        status = torch.zeros(max(S, 1), dtype=torch.int32, device=self.device)
+        b = batch.struct()
+        self._batch_struct = b
+        self._check(self.lib.dr_reach_dt(self.ctx, ctypes.byref(b), int(horizon), _ptr(boxes), _ptr(status),
+                                         _stream()))
+        return boxes, status[:S]
+
+    def dr_get_bounds(self):
+        S = self.batch.n_sub
+        l = torch.empty(S, max(self.H_max, 1), dtype=torch.float64, device=self.device)
+        u = torch.empty_like(l)
+        self._check(self.lib.dr_get_bounds(self.ctx, _ptr(l), _ptr(u), _stream()))
+        return l, u
+
+    def dr_get_rows(self):
+        rows = torch.zeros(self.batch.n_sub, 8, dtype=torch.int32, device=self.device)
+        self._check(self.lib.dr_get_rows(self.ctx, _ptr(rows), _stream()))
+        return rows
+
+    def dr_get_margins(self):
+        m = torch.zeros(self.batch.n_sub, self.R, dtype=torch.float64, device=self.device)
+        self._check(self.lib.dr_get_margins(self.ctx, _ptr(m), _stream()))
+        return m
+
+    # ---- conveniences ----------------------------------------------------------------
+    def crown(self, batch: DeviceBatch):
+        """a1-a6 for a batch: plain CROWN lower/upper bounds and status."""
+        self.dr_bound_init(batch)
+        aff = self.dr_propagate_backward()
+        lb, ub, status = self.dr_concretize(*aff)
+        return lb, ub, status, aff
+
+
+class DualBound(torch.autograd.Function):
+    """Bound of every spec row as a differentiable function of (alpha, beta).
+
+    forward: lower and upper bounds (S x q each) at the given duals, via
+    dr_optimize_duals with iters = 0; backward: the hand-written adjoint's
+    gradients of each row, scaled by the incoming gradient (rows are separable:
+    lower rows use alpha[:, :q], upper rows alpha[:, q:], and ub = -lb_row)."""
+
+    @staticmethod
+    def forward(ctx_, alpha, beta, bctx: BoundContext):
+        a = alpha.detach().clone().contiguous()
+        b = beta.detach().clone().contiguous()
+        lb, ub, status, ga, gb = bctx.dr_optimize_duals(0, 0.0, a, b, init_duals=False, grads=True)
+        ctx_.save_for_backward(ga, gb)
+        ctx_.q = bctx.q
+        return lb, ub
+
+    @staticmethod
+    def backward(ctx_, g_lb, g_ub):
+        ga, gb = ctx_.saved_tensors
+        q = ctx_.q
+        w = torch.cat([g_lb, -g_ub], dim=1).to(ga.dtype)     # d ub = - d lb_row
+        return ga * w[:, :, None], gb * w[:, :, None], None

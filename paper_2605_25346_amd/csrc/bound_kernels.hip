@@ -1,0 +1,1008 @@
+// gfx950 kernels of batched CROWN-style bound propagation.
+//
+// Steps (see the C-ABI header for the contract of each entry point):
+//   k_bound_init   a1-a4: per-subdomain persistent workgroups: exact layer-1 bounds,
+//                  IBP, CROWN intermediate bounds of IBP-unstable neurons on the
+//                  matrix cores, split clamping, ReLU relaxation.
+//   k_final        a5/a7: per-wave persistent tiles of final spec rows; plain CROWN
+//                  (affine bounds out) or alpha/beta projected gradient ascent with a
+//                  hand-written adjoint.
+//   k_concretize   a6: FP64 box concretization with outward rounding.
+//   k_reach_dt     a8: per-box persistent workgroups, stepwise linear-TM closed loop
+//                  with shared-slope CROWN.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "diffreach.h"
+
+namespace dr {
+
+constexpr double kAccEps = 0x1p-42;   // FP64 summation error of offsets (relative to |terms|)
+constexpr double kMargInflate = 1.0 + 0x1p-12;
+
+// ReLU relaxation of one neuron in the chain's arithmetic, with its margin
+// coefficient mu: |a'| mu bounds the rounding introduced by this neuron's product
+// a' W (a priori gamma_{2K} bound with v = |W| H) and by the relaxation product.
+template <typename T>
+__device__ V4<T> build_relax(double l, double u, double v, double bias, bool split, int K, bool shared,
+                             int margin_on) {
+  double M = fmax(fabs(l), fabs(u));
+  T lo, up, t;
+  bool inexact = split;
+  if (!(u > 0.0)) {
+    lo = 0; up = 0; t = 0;
+  } else if (l >= 0.0) {
+    lo = 1; up = 1; t = 0;
+  } else {
+    double s = u / (u - l);
+    T sT = (T)s;
+    double sd = (double)sT;
+    double tt = fmax(-sd * l, u - sd * u);
+    tt += fabs(tt) * 0x1p-50;
+    up = sT;
+    t = rup<T>(tt);
+    lo = shared ? sT : ((u > -l) ? (T)1 : (T)0);
+    inexact = true;
+  }
+  if (!(M < INFINITY)) M = 0.0;  // non-finite bounds are reported through status bits
+  double mu = gamma_n<T>(2 * K) * v + (inexact ? 2.0 * unit_round<T>() * M : 0.0) +
+              kAccEps * (fabs(bias) + M);
+  mu *= 1.0 + 0x1p-40;
+  if (!margin_on) mu = 0.0;
+  V4<T> r;
+  r[0] = lo; r[1] = up; r[2] = t; r[3] = rup<T>(mu);
+  return r;
+}
+
+// Relaxation of one layer applied to g (over h_k) in registers, giving the row
+// multipliers a' over z_k.  Offsets and margin accumulate per lane.
+template <typename T, int NT, bool SHARED>
+__device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4], const V4<T>* rel,
+                                            const T* __restrict__ bias, int gq, double& acc, double& acc2,
+                                            T& marg) {
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      V4<T> r = rel[t * 16 + gq * 4 + i];
+      T gv = g[t][i];
+      T a = (gv >= (T)0 ? r[0] : r[1]) * gv;
+      double bj = (double)bias[t * 16 + nrn<T>(gq, i)];
+      double gt = (double)gv * (double)r[2];
+      if (SHARED) {
+        acc += fmin(gt, 0.0) + (double)a * bj;
+        acc2 += fmax(gt, 0.0) + (double)a * bj;
+      } else {
+        acc += fmin(gt, 0.0) + (double)a * bj;
+      }
+      marg += (a < (T)0 ? -a : a) * r[3];
+      cur[t][i] = a;
+    }
+  }
+}
+
+// Backward chain of one N-tile from hidden layer K-1 down to the input.
+// g: multipliers over h_{K-1} (seed). On return w holds the input coefficients.
+template <typename T, int NT, bool SHARED>
+__device__ __forceinline__ void chain_to_input(const NetDev& net, int K, T (&g)[NT][4], const V4<T>* rel_all,
+                                               double& acc, double& acc2, T& marg, T (&w)[1][4], int lane) {
+  T cur[NT][4];
+  const int gq = lane >> 4;
+  for (int k = K - 1; k >= 1; --k) {
+    relax_layer<T, NT, SHARED>(g, cur, rel_all + (k - 1) * 16 * NT, (const T*)net.bn[k - 1], gq, acc, acc2,
+                               marg);
+    if (k > 1)
+      gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
+    else
+      gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-subdomain shared state of k_bound_init / k_reach_dt (dynamic LDS).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SubLds {
+  V4<T>* rel;     // Hp, permuted
+  double* l;      // Hp natural
+  double* u;      // Hp natural
+  int* slot;      // Hp permuted
+  double* ibl;    // 16 NT
+  double* ibu;
+  double* v;
+  int* U;         // 16 NT
+  double* xc;     // 16
+  double* xr;     // 16
+  int* misc;      // 8 ints: [0] item, [1] flags, [2..5] wave counts
+  __host__ __device__ static size_t bytes(int Hp, int NT) {
+    return (size_t)Hp * (sizeof(V4<T>) + 2 * sizeof(double) + sizeof(int)) +
+           (size_t)16 * NT * (3 * sizeof(double) + sizeof(int)) + 32 * sizeof(double) + 8 * sizeof(int);
+  }
+  __device__ void carve(char* base, int Hp, int NT) {
+    rel = (V4<T>*)base; base += (size_t)Hp * sizeof(V4<T>);
+    l = (double*)base; base += (size_t)Hp * sizeof(double);
+    u = (double*)base; base += (size_t)Hp * sizeof(double);
+    ibl = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    ibu = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    v = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    xc = (double*)base; base += 16 * sizeof(double);
+    xr = (double*)base; base += 16 * sizeof(double);
+    slot = (int*)base; base += (size_t)Hp * sizeof(int);
+    U = (int*)base; base += (size_t)16 * NT * sizeof(int);
+    misc = (int*)base;
+  }
+};
+
+// Compact the flagged neurons of one layer (one thread per neuron, 16 NT <= 256).
+__device__ __forceinline__ int compact_flags(bool flag, int j, int* U, int* wcnt) {
+  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+  unsigned long long m = __ballot(flag);
+  int pre = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) wcnt[wid] = __popcll(m);
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int w = 0; w < kWavesPerWG; ++w) {
+    if (w < wid) base += wcnt[w];
+    tot += wcnt[w];
+  }
+  if (flag) U[base + pre] = j;
+  __syncthreads();
+  return tot;
+}
+
+// Interval (IBP) bound of hidden layer k from the final bounds of layer k-1, with
+// v = |W_k| relu(u_{k-1}) for the margin coefficients; FP64 with outward rounding.
+template <typename T>
+__device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, const double* l_prev,
+                                           const double* u_prev, double& lo, double& hi, double& v) {
+  const int npk = net.np[k - 1];
+  const T* W = (const T*)net.Wn[k - 1] + (size_t)j * npk;
+  double zc = (double)((const T*)net.bn[k - 1])[j], zr = 0.0, za = 0.0;
+  for (int m = 0; m < net.n[k - 1]; ++m) {
+    double hl = fmax(l_prev[m], 0.0), hu = fmax(u_prev[m], 0.0);
+    double c = 0.5 * (hl + hu), r = 0.5 * (hu - hl);
+    double w = (double)W[m];
+    zc += w * c;
+    zr += fabs(w) * r;
+    za += fabs(w) * c;
+  }
+  double e = 0x1p-44 * (za + zr + fabs(zc));
+  lo = zc - zr - e;
+  hi = zc + zr + e;
+  v = za + zr;
+}
+
+// ---------------------------------------------------------------------------
+// a1-a4: intermediate bounds, one workgroup per subdomain, persistent.
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch,
+                                                    Scratch sc, unsigned* queue, int inter_mode, int max_splits) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const NetDev& net = nets[net_index];
+  const int L = net.L, Hp = net.Hp, HpS = sc.Hp_max;
+  SubLds<T> S;
+  S.carve(lds_raw, Hp, NT);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int n0 = net.n[0];
+
+  for (;;) {
+    if (tid == 0) S.misc[0] = (int)atomicAdd(queue, 1u);
+    __syncthreads();
+    const int item = S.misc[0];
+    __syncthreads();
+    if (item >= cnt) break;
+    const int s = sc.order[off + item];
+
+    // ---- a1 ingest: box, splits
+    if (tid < 16) {
+      S.xc[tid] = tid < n0 ? batch.xc[(size_t)s * n0 + tid] : 0.0;
+      S.xr[tid] = tid < n0 ? batch.xr[(size_t)s * n0 + tid] : 0.0;
+    }
+    for (int p = tid; p < Hp; p += kWG) {
+      S.slot[p] = -1;
+      S.l[p] = 0.0;
+      S.u[p] = 0.0;
+    }
+    if (tid == 0) S.misc[1] = 0;
+    if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
+    __syncthreads();
+    if (tid < n0) {
+      double c = S.xc[tid], r = S.xr[tid];
+      if (!(fabs(c) < INFINITY) || !(r < INFINITY) || !(r >= 0.0)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+    }
+    if (batch.sptr) {
+      int a = batch.sptr[s], b = batch.sptr[s + 1];
+      if (b - a > max_splits || b < a) {
+        if (tid == 0) atomicOr(&S.misc[1], DR_RES_BADSPLIT);
+      } else {
+        for (int e = a + tid; e < b; e += kWG) {
+          uint32_t wd = batch.spk[e];
+          int k = (int)(wd >> 24), j = (int)(wd & 0xFFFFu), pos = (int)((wd >> 16) & 1u);
+          if (k < 1 || k > L - 1 || j >= net.n[k]) {
+            atomicOr(&S.misc[1], DR_RES_BADSPLIT);
+          } else {
+            int p = (k - 1) * 16 * NT + (j & ~15) + pos_of<T>(j & 15);
+            S.slot[p] = ((e - a) << 1) | pos;
+          }
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- a2 layer 1: exact bounds of an affine map over the box
+    {
+      const int n1 = net.n[1];
+      for (int j = tid; j < 16 * NT; j += kWG) {
+        const int p = (j & ~15) + pos_of<T>(j & 15);
+        double lo = 0.0, hi = 0.0, v = 0.0, bj = 0.0;
+        bool split = S.slot[p] >= 0;
+        if (j < n1) {
+          const T* W = (const T*)net.Wn[0] + (size_t)j * net.np[0];
+          bj = (double)((const T*)net.bn[0])[j];
+          double zc = bj, zr = 0.0, za = 0.0;
+          for (int m = 0; m < n0; ++m) {
+            double w = (double)W[m];
+            zc += w * S.xc[m];
+            zr += fabs(w) * S.xr[m];
+            za += fabs(w) * fabs(S.xc[m]);
+          }
+          double e = 0x1p-44 * (za + zr + fabs(zc));
+          lo = zc - zr - e;
+          hi = zc + zr + e;
+          v = za + zr;
+          if (split) {
+            if (S.slot[p] & 1) lo = fmax(lo, 0.0); else hi = fmin(hi, 0.0);
+          }
+          if (lo > hi) atomicOr(&S.misc[1], DR_RES_INFEASIBLE);
+          if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+        }
+        S.l[j] = lo;
+        S.u[j] = hi;
+        S.rel[p] = build_relax<T>(lo, hi, v, bj, split, n1, false, sc.margin_on);
+      }
+    }
+    __syncthreads();
+
+    // ---- a3/a4 deeper hidden layers
+    for (int k = 2; k <= L - 1; ++k) {
+      if (S.misc[1] & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT)) break;
+      const int nk = net.n[k];
+      const int base = (k - 1) * 16 * NT, pbase = (k - 2) * 16 * NT;
+      bool flag = false;
+      {
+        const int j = tid;
+        if (j < 16 * NT) {
+          double lo = 0.0, hi = 0.0, v = 0.0;
+          if (j < nk) ibp_neuron<T>(net, k, j, S.l + pbase, S.u + pbase, lo, hi, v);
+          S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
+          S.l[base + j] = lo; S.u[base + j] = hi;
+          const int p = base + (j & ~15) + pos_of<T>(j & 15);
+          flag = (j < nk) && lo < 0.0 && hi > 0.0 && S.slot[p] < 0 && inter_mode == DR_INTER_CROWN_IBP;
+        }
+      }
+      const int nU = compact_flags(flag, tid, S.U, S.misc + 2);
+      const int nrows = 2 * nU;
+      const int ntiles = (nrows + 15) >> 4;
+      for (int tile = wid; tile < ntiles; tile += kWavesPerWG) {
+        const int row = tile * 16 + (lane & 15);
+        const bool valid = row < nrows;
+        const int neuron = valid ? S.U[row >> 1] : 0;
+        const T sgn = (row & 1) ? (T)-1 : (T)1;
+        T g[NT][4];
+        const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
+        const int gq = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g[t][i] = valid ? sgn * Wrow[t * 16 + nrn<T>(gq, i)] : (T)0;
+        // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
+        double acc = (valid && gq == 0) ? (double)sgn * (double)((const T*)net.bn[k - 1])[neuron] : 0.0, acc2 = 0.0;
+        T marg = 0;
+        T w[1][4];
+        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane);
+        double conc = 0.0, wabs = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = nrn<T>(gq, i);
+          double wm = (double)w[0][i];
+          conc += wm * S.xc[m] - fabs(wm) * S.xr[m];
+          wabs += fabs(wm) * (fabs(S.xc[m]) + S.xr[m]);
+        }
+        conc = row_sum(conc);
+        wabs = row_sum(wabs);
+        acc = row_sum(acc);
+        double mg = (double)row_sum(marg) * kMargInflate;
+        double lb = acc + conc - mg - 0x1p-48 * (fabs(acc) + wabs);
+        if (valid && lane < 16) {
+          if (row & 1) S.u[base + neuron] = fmin(S.ibu[neuron], -lb);
+          else S.l[base + neuron] = fmax(S.ibl[neuron], lb);
+        }
+      }
+      __syncthreads();
+      {
+        const int j = tid;
+        if (j < 16 * NT) {
+          const int p = base + (j & ~15) + pos_of<T>(j & 15);
+          double lo = S.l[base + j], hi = S.u[base + j];
+          bool split = S.slot[p] >= 0;
+          double bj = 0.0;
+          if (j < nk) {
+            bj = (double)((const T*)net.bn[k - 1])[j];
+            if (split) {
+              if (S.slot[p] & 1) lo = fmax(lo, 0.0); else hi = fmin(hi, 0.0);
+            }
+            if (lo > hi) atomicOr(&S.misc[1], DR_RES_INFEASIBLE);
+            if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+            S.l[base + j] = lo;
+            S.u[base + j] = hi;
+          }
+          S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, split, nk, false, sc.margin_on);
+        }
+        if (tid == 0) sc.rows[(size_t)s * 8 + (k - 1)] = nrows;
+      }
+      __syncthreads();
+    }
+
+    // ---- write back
+    const size_t so = (size_t)s * HpS;
+    for (int p = tid; p < Hp; p += kWG) {
+      sc.bl[so + p] = S.l[p];
+      sc.bu[so + p] = S.u[p];
+      ((V4<T>*)sc.rel)[so + p] = S.rel[p];
+      sc.slot[so + p] = S.slot[p];
+    }
+    if (tid == 0) {
+      sc.st[s] = (uint32_t)S.misc[1];
+      sc.rows[(size_t)s * 8 + (L - 1)] = net.R;
+    }
+    __syncthreads();
+  }
+  if (wid == 0) {
+    // one worker per workgroup for the queue's completion counter
+    wave_done(queue, gridDim.x);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a5 / a7: final spec rows.  One wave = one N-tile holding P = 16 / R subdomains.
+// ---------------------------------------------------------------------------
+struct FinalArgs {
+  BatchDev batch;
+  Scratch sc;
+  unsigned* queue;
+  // a5 outputs
+  double* lam_lo; double* acc_lo; double* lam_hi; double* acc_hi;
+  // a7
+  int iters; float lr; int init_duals;
+  float* alpha; float* beta; double* lb; double* ub; float* galpha; float* gbeta;
+  uint32_t* status;
+  void* tape;               // per-wave tape of g values (a7)
+  int H_max;                // alpha row stride
+  int max_splits;           // beta row stride
+  int q;
+};
+
+template <typename T, int NT, bool DUALS>
+__global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
+  const NetDev& net = nets[net_index];
+  const Scratch& sc = fa.sc;
+  const int tid = threadIdx.x, lane = tid & 63, gq = lane >> 4, n = lane & 15;
+  const int L = net.L, R = net.R, q = net.q, n0 = net.n[0];
+  const int P = 16 / R;
+  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int n_items = (cnt + P - 1) / P;
+  const int HpS = sc.Hp_max;
+  const unsigned n_workers = gridDim.x * kWavesPerWG;
+  const int wave_global = blockIdx.x * kWavesPerWG + (tid >> 6);
+  T* tape = DUALS ? (T*)fa.tape + (size_t)wave_global * (L - 1) * NT * 256 : nullptr;
+
+  for (;;) {
+    const int item = wave_fetch(fa.queue);
+    if (item >= n_items) break;
+    const int sl = n / R, r = n % R;
+    const int idx = item * P + sl;
+    const bool inrange = (sl < P) && (idx < cnt);
+    const int s = inrange ? sc.order[off + idx] : 0;
+    const uint32_t st = inrange ? sc.st[s] : 0u;
+    const bool live = inrange && !(st & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT));
+    const size_t so = (size_t)s * HpS;
+    const V4<T>* rel = (const V4<T>*)sc.rel + so;
+    const int* slot = sc.slot + so;
+    double xcv[4], xrv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = nrn<T>(gq, i);
+      xcv[i] = (inrange && m < n0) ? fa.batch.xc[(size_t)s * n0 + m] : 0.0;
+      xrv[i] = (inrange && m < n0) ? fa.batch.xr[(size_t)s * n0 + m] : 0.0;
+    }
+    // seed margin: rounding of the FP64 seed g = a_L W_L to the chain type, times |h_{L-1}|
+    const double* seed = net.seedW + (size_t)r * net.np[L - 1];
+    const int lbase = (L - 2) * 16 * NT;
+    const float* arow = DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : nullptr;
+    const float* brow = DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : nullptr;
+    double best = -INFINITY, lbv = 0.0, mgv = 0.0;
+    const int n_eval = DUALS ? fa.iters + 1 : 1;
+    for (int it = 0; it < n_eval; ++it) {
+      T g[NT][4];
+      double acc = (live && gq == 0) ? net.seedB[r] : 0.0, acc2 = 0.0;
+      T marg = 0;
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = t * 16 + nrn<T>(gq, i);
+          double gd = live ? seed[m] : 0.0;
+          T gt = (T)gd;
+          g[t][i] = gt;
+          double hu = live ? fmax(sc.bu[so + lbase + m], 0.0) : 0.0;
+          if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+        }
+      // forward (backward bound propagation) with optional alpha/beta and tape
+      T w[1][4];
+      {
+        T cur[NT][4];
+        for (int k = L - 1; k >= 1; --k) {
+          const V4<T>* rk = rel + (k - 1) * 16 * NT;
+          if (!DUALS) {
+            relax_layer<T, NT, false>(g, cur, rk, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
+          } else {
+            const T* bias = (const T*)net.bn[k - 1];
+            const int hoff = net.hoff[k - 1];
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const int c = t * 16 + nrn<T>(gq, i);
+                V4<T> rr = rk[t * 16 + gq * 4 + i];
+                T gv = g[t][i];
+                tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
+                T lo = rr[0];
+                if (rr[2] > (T)0 && c < net.n[k]) {
+                  float av = (live && !(fa.init_duals && it == 0)) ? arow[hoff + c] : (float)rr[0];
+                  lo = (T)av;
+                }
+                T a = (gv >= (T)0 ? lo : rr[1]) * gv;
+                const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
+                if (sp >= 0) {
+                  float bv = (live && !(fa.init_duals && it == 0)) ? brow[sp >> 1] : 0.0f;
+                  a -= (sp & 1) ? (T)bv : -(T)bv;
+                }
+                double bj = (double)bias[c];
+                acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
+                marg += (a < (T)0 ? -a : a) * rr[3];
+                cur[t][i] = a;
+              }
+          }
+          if (k > 1)
+            gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
+          else
+            gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+        }
+      }
+      double wt[4];
+      double conc = 0.0, wabs = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = nrn<T>(gq, i);
+        wt[i] = (double)w[0][i] + net.skip[(size_t)r * 16 + m];
+        conc += wt[i] * xcv[i] - fabs(wt[i]) * xrv[i];
+        wabs += fabs(wt[i]) * (fabs(xcv[i]) + xrv[i]);
+      }
+      conc = row_sum(conc);
+      wabs = row_sum(wabs);
+      double accs = row_sum(acc);
+      double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs);
+      lbv = accs + conc - mg;
+      mgv = mg;
+      if (!DUALS) {
+        if (live) {
+          // every lane group writes its own input coefficients; lane group 0 the offsets
+          const bool lower = r < q;
+          const int rr = lower ? r : r - q;
+          double* lam = lower ? fa.lam_lo : fa.lam_hi;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = nrn<T>(gq, i);
+            if (m < n0) lam[((size_t)s * q + rr) * n0 + m] = lower ? wt[i] : -wt[i];
+          }
+          if (gq == 0) {
+            double ao = accs - mg;
+            if (lower) fa.acc_lo[(size_t)s * q + rr] = ao;
+            else fa.acc_hi[(size_t)s * q + rr] = -ao;
+            sc.margin[(size_t)s * 16 + r] = mg;
+            if (!(fabs(ao) < INFINITY) || !(mg < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
+            else if (mg > fmax(1.0, fabs(lbv))) atomicOr(&sc.st[s], (uint32_t)DR_RES_MARGIN);
+          }
+        }
+        if (inrange && !live && gq == 0) {
+          const bool lower = r < q;
+          const int rr = lower ? r : r - q;
+          double* lam = lower ? fa.lam_lo : fa.lam_hi;
+          for (int m = 0; m < n0; ++m) lam[((size_t)s * q + rr) * n0 + m] = 0.0;
+          if (lower) fa.acc_lo[(size_t)s * q + rr] = INFINITY;
+          else fa.acc_hi[(size_t)s * q + rr] = -INFINITY;
+          sc.margin[(size_t)s * 16 + r] = 0.0;
+        }
+        break;
+      }
+      best = fmax(best, lbv);
+      const bool last = (it == n_eval - 1);
+      const bool init_now = fa.init_duals && it == 0;
+      if (last && fa.galpha == nullptr && fa.gbeta == nullptr && !init_now) break;
+      // ---- hand-written adjoint of lb = acc + w.xc - |w|.xr w.r.t. alpha, beta
+      T dlt[NT][4];
+      {
+        T dw[1][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          double sg = wt[i] > 0.0 ? 1.0 : (wt[i] < 0.0 ? -1.0 : 0.0);
+          dw[0][i] = (T)(xcv[i] - sg * xrv[i]);
+        }
+        gemm_tiles<T, NT, 1>((const V4<T>*)net.Wa[0], dw, dlt, lane);
+      }
+      for (int k = 1; k <= L - 1; ++k) {
+        const V4<T>* rk = rel + (k - 1) * 16 * NT;
+        const T* bias = (const T*)net.bn[k - 1];
+        const int hoff = net.hoff[k - 1];
+        T e[NT][4];
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int c = t * 16 + nrn<T>(gq, i);
+            T delta = dlt[t][i] + bias[c];          // d lb / d a'^(k)
+            V4<T> rr = rk[t * 16 + gq * 4 + i];
+            T gv = tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane];
+            const bool uns = rr[2] > (T)0 && c < net.n[k];
+            T lo = rr[0];
+            float av = 0.0f;
+            if (uns) {
+              av = (live && !(fa.init_duals && it == 0)) ? arow[hoff + c] : (float)rr[0];
+              lo = (T)av;
+            }
+            T d = gv >= (T)0 ? lo : rr[1];
+            if (uns && live) {
+              T da = gv >= (T)0 ? delta * gv : (T)0;
+              if (!last) {
+                float nv = av + fa.lr * (float)da;
+                nv = fminf(fmaxf(nv, 0.0f), 1.0f);
+                ((float*)arow)[hoff + c] = nv;
+              } else {
+                if (init_now) ((float*)arow)[hoff + c] = av;
+                if (fa.galpha) fa.galpha[((size_t)s * R + r) * fa.H_max + hoff + c] = (float)da;
+              }
+            }
+            const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
+            if (sp >= 0 && live) {
+              T db = (sp & 1) ? -delta : delta;    // -sigma * delta
+              float bv = (fa.init_duals && it == 0) ? 0.0f : brow[sp >> 1];
+              if (!last) {
+                ((float*)brow)[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
+              } else {
+                if (init_now) ((float*)brow)[sp >> 1] = bv;
+                if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
+              }
+            }
+            e[t][i] = delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0);
+          }
+        if (k < L - 1) gemm_tiles<T, NT, NT>((const V4<T>*)net.Wa[k], e, dlt, lane);
+      }
+      if (last) break;
+    }
+    if (DUALS && lane < 16 && inrange) {
+      const bool lower = r < q;
+      const int rr = lower ? r : r - q;
+      double bv = live ? best : INFINITY;
+      if (lower) fa.lb[(size_t)s * q + rr] = bv;
+      else fa.ub[(size_t)s * q + rr] = -bv;
+      sc.margin[(size_t)s * 16 + r] = live ? mgv : 0.0;
+      if (live && !(fabs(best) < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
+    }
+  }
+  wave_done(fa.queue, n_workers);
+}
+
+// ---------------------------------------------------------------------------
+// a6: concretization of affine bounds over the boxes (FP64, outward rounding).
+// ---------------------------------------------------------------------------
+__global__ void k_concretize(int S, int q, int n0, const double* __restrict__ xc, const double* __restrict__ xr,
+                             const double* lam_lo, const double* acc_lo, const double* lam_hi,
+                             const double* acc_hi, double* lb, double* ub, const uint32_t* ctx_st,
+                             uint32_t* status) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= S) return;
+  const uint32_t cst = ctx_st ? ctx_st[s] : 0u;
+  const bool dead = cst & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT);
+  uint32_t bits = cst;
+  for (int r = 0; r < q; ++r) {
+    const size_t i = (size_t)s * q + r;
+    double cl = acc_lo[i], ch = acc_hi[i], al = 0.0, ah = 0.0;
+    for (int m = 0; m < n0; ++m) {
+      double c = xc[(size_t)s * n0 + m], rr = xr[(size_t)s * n0 + m];
+      double wl = lam_lo[i * n0 + m], wh = lam_hi[i * n0 + m];
+      cl += wl * c - fabs(wl) * rr;
+      ch += wh * c + fabs(wh) * rr;
+      al += fabs(wl) * (fabs(c) + rr);
+      ah += fabs(wh) * (fabs(c) + rr);
+    }
+    const double vl = cl - 0x1p-48 * (fabs(acc_lo[i]) + al);
+    const double vh = ch + 0x1p-48 * (fabs(acc_hi[i]) + ah);
+    lb[i] = dead ? INFINITY : vl;
+    ub[i] = dead ? -INFINITY : vh;
+    if (!dead && (!(fabs(vl) < INFINITY) || !(fabs(vh) < INFINITY))) bits |= DR_RES_NONFINITE;
+  }
+  if (status) status[s] = bits;
+}
+
+// ---------------------------------------------------------------------------
+// a8: stepwise closed-loop reachability with linear TMs (one WG per box).
+// ---------------------------------------------------------------------------
+struct ReachArgs {
+  BatchDev batch;
+  Scratch sc;
+  unsigned* queue;
+  int horizon;
+  double* boxes;
+  uint32_t* status;
+};
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const NetDev& net = nets[net_index];
+  const Scratch& sc = ra.sc;
+  const int L = net.L, Hp = net.Hp;
+  SubLds<T> S;
+  S.carve(lds_raw, Hp, NT);
+  // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
+  double* tm = (double*)(lds_raw + SubLds<T>::bytes(Hp, NT) + 64);
+  tm = (double*)(((uintptr_t)tm + 15) & ~(uintptr_t)15);
+  double* c = tm;            // 16
+  double* Pm = tm + 16;      // 256 (row-major n x n)
+  double* Ilo = tm + 272;    // 16
+  double* Ihi = tm + 288;    // 16
+  double* Xab = tm + 304;    // 16: bound on |x_m| over the TM
+  double* nc = tm + 320;     // next state
+  double* nP = tm + 336;
+  double* nIlo = tm + 592;
+  double* nIhi = tm + 608;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, gq = lane >> 4;
+  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int n0 = net.n[0], ns = net.n_state, H = ra.horizon;
+
+  for (;;) {
+    if (tid == 0) S.misc[0] = (int)atomicAdd(ra.queue, 1u);
+    __syncthreads();
+    const int item = S.misc[0];
+    __syncthreads();
+    if (item >= cnt) break;
+    const int s = sc.order[off + item];
+    double* bx = ra.boxes + (size_t)s * (H + 1) * n0 * 2;
+    // TM normalisation of the input box: c = centre, P = diag(radius), I = [0, 0]
+    if (tid < 16) {
+      double cc = tid < n0 ? ra.batch.xc[(size_t)s * n0 + tid] : 0.0;
+      double rr = tid < n0 ? ra.batch.xr[(size_t)s * n0 + tid] : 0.0;
+      c[tid] = cc; Ilo[tid] = 0.0; Ihi[tid] = 0.0;
+      if (tid < n0) { bx[tid * 2 + 0] = cc - rr; bx[tid * 2 + 1] = cc + rr; }
+    }
+    for (int e = tid; e < 256; e += kWG) {
+      int a = e >> 4, b = e & 15;
+      Pm[e] = (a == b && a < n0) ? ra.batch.xr[(size_t)s * n0 + a] : 0.0;
+    }
+    for (int p = tid; p < Hp; p += kWG) S.slot[p] = -1;
+    if (tid == 0) S.misc[1] = 0;
+    if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
+    __syncthreads();
+    for (int step = 0; step < H; ++step) {
+      // |x_m| bound over the TM, and the input-centre/radius for the layer-1 bounds
+      if (tid < 16) {
+        double a = fabs(c[tid]) + fmax(fabs(Ilo[tid]), fabs(Ihi[tid]));
+        for (int z = 0; z < n0; ++z) a += fabs(Pm[tid * 16 + z]);
+        Xab[tid] = tid < n0 ? a : 0.0;
+        S.xc[tid] = 0.0; S.xr[tid] = 0.0;
+      }
+      __syncthreads();
+      // ---- layer 1 on the TM input: exact range of W_1 (c + P z + r) + b_1
+      {
+        const int n1 = net.n[1];
+        for (int j = tid; j < 16 * NT; j += kWG) {
+          const int p = (j & ~15) + pos_of<T>(j & 15);
+          double lo = 0.0, hi = 0.0, v = 0.0, bj = 0.0;
+          if (j < n1) {
+            const T* W = (const T*)net.Wn[0] + (size_t)j * net.np[0];
+            bj = (double)((const T*)net.bn[0])[j];
+            double zc = bj, zr = 0.0, za = 0.0, zab = 0.0;
+            double wp[16];
+            for (int z = 0; z < 16; ++z) wp[z] = 0.0;
+            for (int m = 0; m < n0; ++m) {
+              double w = (double)W[m];
+              zc += w * (c[m] + 0.5 * (Ilo[m] + Ihi[m]));
+              zr += fabs(w) * 0.5 * (Ihi[m] - Ilo[m]);
+              za += fabs(w) * Xab[m];
+              zab += fabs(w) * (fabs(c[m]) + 0.5 * fabs(Ilo[m] + Ihi[m]));
+              for (int z = 0; z < n0; ++z) wp[z] += w * Pm[m * 16 + z];
+            }
+            for (int z = 0; z < n0; ++z) zr += fabs(wp[z]);
+            double e = 0x1p-44 * (za + zab + zr + fabs(zc));
+            lo = zc - zr - e;
+            hi = zc + zr + e;
+            v = za;
+            if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+          }
+          S.l[j] = lo; S.u[j] = hi;
+          S.rel[p] = build_relax<T>(lo, hi, v, bj, false, n1, true, sc.margin_on);
+        }
+      }
+      __syncthreads();
+      // ---- deeper hidden layers: shared-slope CROWN on the TM input, intersected with IBP
+      for (int k = 2; k <= L - 1; ++k) {
+        const int nk = net.n[k];
+        const int base = (k - 1) * 16 * NT, pbase = (k - 2) * 16 * NT;
+        bool flag = false;
+        if (tid < 16 * NT) {
+          const int j = tid;
+          double lo = 0.0, hi = 0.0, v = 0.0;
+          if (j < nk) ibp_neuron<T>(net, k, j, S.l + pbase, S.u + pbase, lo, hi, v);
+          S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
+          S.l[base + j] = lo; S.u[base + j] = hi;
+          flag = (j < nk) && lo < 0.0 && hi > 0.0;
+        }
+        const int nU = compact_flags(flag, tid, S.U, S.misc + 2);
+        const int ntiles = (nU + 15) >> 4;
+        for (int tile = wid; tile < ntiles; tile += kWavesPerWG) {
+          const int row = tile * 16 + (lane & 15);
+          const bool valid = row < nU;
+          const int neuron = valid ? S.U[row] : 0;
+          T g[NT][4];
+          const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g[t][i] = valid ? Wrow[t * 16 + nrn<T>(gq, i)] : (T)0;
+          double acc = (valid && gq == 0) ? (double)((const T*)net.bn[k - 1])[neuron] : 0.0, acc2 = acc;
+          T marg = 0;
+          T w[1][4];
+          chain_to_input<T, NT, true>(net, k, g, S.rel, acc, acc2, marg, w, lane);
+          // TM evaluation of w.x + [acc, acc2] over x = c + P z + r
+          double base_v = 0.0, il = 0.0, ih = 0.0, wabs = 0.0;
+          double wp[16];
+#pragma unroll
+          for (int z = 0; z < 16; ++z) wp[z] = 0.0;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = nrn<T>(gq, i);
+            double wm = (double)w[0][i];
+            base_v += wm * c[m];
+            double a1 = wm * Ilo[m], a2 = wm * Ihi[m];
+            il += fmin(a1, a2); ih += fmax(a1, a2);
+            wabs += fabs(wm) * Xab[m];
+#pragma unroll
+            for (int z = 0; z < 16; ++z) wp[z] += wm * Pm[m * 16 + z];
+          }
+          base_v = row_sum(base_v); il = row_sum(il); ih = row_sum(ih); wabs = row_sum(wabs);
+          double rad = 0.0;
+#pragma unroll
+          for (int z = 0; z < 16; ++z) rad += fabs(row_sum(wp[z]));
+          acc = row_sum(acc); acc2 = row_sum(acc2);
+          double mg = (double)row_sum(marg) * kMargInflate + 0x1p-46 * (wabs + fabs(acc) + fabs(acc2));
+          double lo = acc + base_v - rad + il - mg;
+          double hi = acc2 + base_v + rad + ih + mg;
+          if (valid && lane < 16) {
+            S.l[base + neuron] = fmax(S.ibl[neuron], lo);
+            S.u[base + neuron] = fmin(S.ibu[neuron], hi);
+          }
+        }
+        __syncthreads();
+        if (tid < 16 * NT) {
+          const int j = tid;
+          const int p = base + (j & ~15) + pos_of<T>(j & 15);
+          double lo = S.l[base + j], hi = S.u[base + j], bj = 0.0;
+          if (j < nk) {
+            bj = (double)((const T*)net.bn[k - 1])[j];
+            if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+          }
+          S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, false, nk, true, sc.margin_on);
+        }
+        if (tid == 0) sc.rows[(size_t)s * 8 + (k - 1)] += nU;
+        __syncthreads();
+      }
+      // ---- output rows e_r on x' (r < n_state): multipliers B_r on y, skip A_r
+      if (wid == 0) {
+        const int r = lane & 15;
+        const bool valid = r < ns;
+        const double* seed = net.seedW + (size_t)r * net.np[L - 1];
+        const int lbase = (L - 2) * 16 * NT;
+        T g[NT][4];
+        T marg = 0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = t * 16 + nrn<T>(gq, i);
+            double gd = valid ? seed[m] : 0.0;
+            T gt = (T)gd;
+            g[t][i] = gt;
+            double hu = fmax(S.u[lbase + m], 0.0);
+            if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          }
+        double acc = (valid && gq == 0) ? net.seedB[r] : 0.0, acc2 = acc;
+        T w[1][4];
+        chain_to_input<T, NT, true>(net, L, g, S.rel, acc, acc2, marg, w, lane);
+        // W_r = A_r + w (FP64); new TM row: c' = W c, P' = W P, I' = W (x) I + [acc, acc2] -+ margin
+        double Wr[4];
+        double cpart = 0.0, il = 0.0, ih = 0.0, wabs = 0.0;
+        double pp[16];
+#pragma unroll
+        for (int z = 0; z < 16; ++z) pp[z] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = nrn<T>(gq, i);
+          Wr[i] = valid ? (double)w[0][i] + net.skip[(size_t)r * 16 + m] : 0.0;
+          cpart += Wr[i] * c[m];
+          double a1 = Wr[i] * Ilo[m], a2 = Wr[i] * Ihi[m];
+          il += fmin(a1, a2); ih += fmax(a1, a2);
+          wabs += fabs(Wr[i]) * Xab[m];
+#pragma unroll
+          for (int z = 0; z < 16; ++z) pp[z] += Wr[i] * Pm[m * 16 + z];
+        }
+        cpart = row_sum(cpart); il = row_sum(il); ih = row_sum(ih); wabs = row_sum(wabs);
+        acc = row_sum(acc); acc2 = row_sum(acc2);
+        double mg = (double)row_sum(marg) * kMargInflate + 0x1p-46 * (wabs + fabs(acc) + fabs(acc2));
+        double rad = 0.0;
+#pragma unroll
+        for (int z = 0; z < 16; ++z) {
+          double v = row_sum(pp[z]);
+          pp[z] = v;
+          rad += fabs(v);
+        }
+        if (valid && lane < 16) {
+          nc[r] = cpart;
+          nIlo[r] = il + acc - mg;
+          nIhi[r] = ih + acc2 + mg;
+#pragma unroll
+          for (int z = 0; z < 16; ++z) nP[r * 16 + z] = (z < n0) ? pp[z] : 0.0;
+          double blo = cpart - rad + nIlo[r], bhi = cpart + rad + nIhi[r];
+          double* bo = bx + (size_t)(step + 1) * n0 * 2;
+          bo[r * 2 + 0] = blo;
+          bo[r * 2 + 1] = bhi;
+          if (!(fabs(blo) < INFINITY) || !(fabs(bhi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+        }
+        if (lane == 0) sc.rows[(size_t)s * 8 + (L - 1)] += ns;
+      }
+      __syncthreads();
+      if (tid < 16) {
+        c[tid] = tid < ns ? nc[tid] : 0.0;
+        Ilo[tid] = tid < ns ? nIlo[tid] : 0.0;
+        Ihi[tid] = tid < ns ? nIhi[tid] : 0.0;
+      }
+      for (int e = tid; e < 256; e += kWG) Pm[e] = ((e >> 4) < ns) ? nP[e] : 0.0;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      sc.st[s] = (uint32_t)S.misc[1];
+      if (ra.status) ra.status[s] = (uint32_t)S.misc[1];
+    }
+    __syncthreads();
+  }
+  if (wid == 0) wave_done(ra.queue, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Set-up kernels
+// ---------------------------------------------------------------------------
+// Natural padded copy of W_k (rows np_k, cols np_{k-1}) and b_k in the chain type.
+template <typename T, typename S>
+__global__ void k_copy_weights(const S* __restrict__ W, const S* __restrict__ b, int nk, int nkm1, int npk,
+                               int npkm1, T* Wn, T* bn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < npk * npkm1) {
+    int r = i / npkm1, cc = i % npkm1;
+    Wn[i] = (r < nk && cc < nkm1) ? (T)W[(size_t)r * nkm1 + cc] : (T)0;
+  }
+  if (i < npk) bn[i] = i < nk ? (T)b[i] : (T)0;
+}
+
+// Swizzle into MFMA A-operand order: block (mt, kt), lane l, sub-step i holds
+// A[16 mt + l % 16][16 kt + nrn(l / 16, i)], with A[m][kk] = W[kk][m] (fwd) or W[m][kk] (adj).
+template <typename T>
+__global__ void k_swizzle(const T* __restrict__ Wn, int npk, int npkm1, int adjoint, T* out) {
+  const int MT = (adjoint ? npk : npkm1) / 16, KT = (adjoint ? npkm1 : npk) / 16;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = MT * KT * 64 * 4;
+  if (e >= total) return;
+  const int i = e & 3, lane = (e >> 2) & 63, blk = e >> 8;
+  const int mt = blk / KT, kt = blk % KT;
+  const int m = mt * 16 + (lane & 15), kk = kt * 16 + nrn<T>(lane >> 4, i);
+  out[e] = adjoint ? Wn[(size_t)m * npkm1 + kk] : Wn[(size_t)kk * npkm1 + m];
+}
+
+// Seeds of the final rows [c; -c]: a_L = c (or c B), g = a_L W_L, acc = a_L . b_L, skip = c A.
+template <typename T>
+__global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npL, int npLm1,
+                        const double* __restrict__ C, int q, int n_target, const double* __restrict__ A,
+                        const double* __restrict__ B, int n0, double* seedW, double* seedB, double* skip) {
+  const int R = 2 * q;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= R * npLm1) return;
+  const int r = e / npLm1, m = e % npLm1;
+  const int rr = r < q ? r : r - q;
+  const double sg = r < q ? 1.0 : -1.0;
+  // multipliers on the network output
+  double g = 0.0, acc = 0.0;
+  for (int o = 0; o < nL; ++o) {
+    double a = 0.0;
+    if (B) {
+      for (int t = 0; t < n_target; ++t) a += C[(size_t)rr * n_target + t] * B[(size_t)t * nL + o];
+    } else {
+      a = C[(size_t)rr * n_target + o];
+    }
+    a *= sg;
+    g += a * (double)WL[(size_t)o * npLm1 + m];
+    acc += a * (double)bL[o];
+  }
+  seedW[(size_t)r * npLm1 + m] = g;
+  if (m == 0) seedB[r] = acc;
+  if (m < 16) {
+    double sk = 0.0;
+    if (A && m < n0)
+      for (int t = 0; t < n_target; ++t) sk += C[(size_t)rr * n_target + t] * A[(size_t)t * n0 + m];
+    skip[(size_t)r * 16 + m] = sg * sk;
+  }
+}
+
+// Counting sort of the batch by network id (one workgroup).
+__global__ void k_order(int S, const int* __restrict__ net_id, int n_nets, int* order, int* net_cnt,
+                        int* net_off, uint32_t* st) {
+  __shared__ int cnt[kMaxNets], cur[kMaxNets];
+  const int tid = threadIdx.x;
+  if (tid < kMaxNets) cnt[tid] = 0;
+  __syncthreads();
+  for (int s = tid; s < S; s += blockDim.x) {
+    int id = net_id ? net_id[s] : 0;
+    if (id >= 0 && id < n_nets) atomicAdd(&cnt[id], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int o = 0;
+    for (int i = 0; i < kMaxNets; ++i) {
+      net_off[i] = o;
+      cur[i] = o;
+      net_cnt[i] = i < n_nets ? cnt[i] : 0;
+      o += i < n_nets ? cnt[i] : 0;
+    }
+  }
+  __syncthreads();
+  for (int s = tid; s < S; s += blockDim.x) {
+    int id = net_id ? net_id[s] : 0;
+    if (id >= 0 && id < n_nets) {
+      order[atomicAdd(&cur[id], 1)] = s;
+      st[s] = 0u;
+    } else {
+      st[s] = DR_RES_BADSPLIT;
+    }
+  }
+}
+
+__global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __restrict__ nets, const int* net_id,
+                                const double* bl, const double* bu, double* l, double* u) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= S * H_max) return;
+  const int s = e / H_max, h = e % H_max;
+  const NetDev& net = nets[net_id ? net_id[s] : 0];
+  double lo = NAN, hi = NAN;
+  if (h < net.H) {
+    int k = 1, hh = h;
+    while (k < net.L - 1 && hh >= net.n[k]) { hh -= net.n[k]; ++k; }
+    const size_t p = (size_t)s * Hp_max + (size_t)(k - 1) * 16 * net.NT + hh;
+    lo = bl[p];
+    hi = bu[p];
+  }
+  l[e] = lo;
+  u[e] = hi;
+}
+
+}  // namespace dr

@@ -1,0 +1,505 @@
+// Host side of the C-ABI (libdiffreach.so): validation, context set-up, launches.
+// The kernels live in bound_kernels.hip, compiled into this translation unit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bound_kernels.hip"
+#include "diffreach.h"
+
+using dr::kMaxL;
+using dr::kMaxNets;
+using dr::kWG;
+
+namespace {
+thread_local std::string g_create_error;
+enum { Q_BOUND = 0, Q_FINAL = 1, Q_DUAL = 2, Q_REACH = 3, Q_KINDS = 4 };
+constexpr int kSupportedNT[] = {2, 4, 8, 16};
+int pad16(int n) { return (n + 15) / 16 * 16; }
+}  // namespace
+
+struct dr_ctx {
+  int dev = 0;
+  int prec = DR_PREC_F32;
+  int inter = DR_INTER_CROWN_IBP;
+  int max_sub = 0, max_splits = 0, tile_cfg = 0;
+  int n_nets = 0, n0 = 0, q = 0, R = 0, H_max = 0, Hp_max = 0;
+  bool closed = false;
+  bool has_spec = false;
+  dr::NetDev hnet[kMaxNets];
+  dr::NetDev* dnet = nullptr;
+  std::vector<void*> allocs;
+  dr::Scratch sc{};
+  unsigned* queues = nullptr;
+  void* tape = nullptr;
+  int cus = 0;
+  int grid[Q_KINDS][kMaxNets] = {};
+  size_t lds[Q_KINDS][kMaxNets] = {};
+  dr::BatchDev batch{};
+  bool have_batch = false;
+  std::string err;
+};
+
+namespace {
+
+dr_status fail(dr_ctx* c, dr_status st, const std::string& msg) {
+  if (c) c->err = msg; else g_create_error = msg;
+  return st;
+}
+
+dr_status hip_fail(dr_ctx* c, hipError_t e, const char* what) {
+  return fail(c, DR_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename P>
+hipError_t ctx_alloc(dr_ctx* c, P** p, size_t bytes) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(bytes, 16));
+  if (e == hipSuccess) c->allocs.push_back(v);
+  *p = (P*)v;
+  return e;
+}
+
+// ---- kernel instance selection -------------------------------------------------
+template <typename T, int NT>
+struct Inst {
+  static const void* bound() { return (const void*)&dr::k_bound_init<T, NT>; }
+  static const void* final_() { return (const void*)&dr::k_final<T, NT, false>; }
+  static const void* dual() { return (const void*)&dr::k_final<T, NT, true>; }
+  static const void* reach() { return (const void*)&dr::k_reach_dt<T, NT>; }
+};
+
+template <typename T>
+const void* kernel_of(int kind, int NT) {
+#define DR_CASE(N)                                  \
+  case N:                                           \
+    switch (kind) {                                 \
+      case Q_BOUND: return Inst<T, N>::bound();     \
+      case Q_FINAL: return Inst<T, N>::final_();    \
+      case Q_DUAL: return Inst<T, N>::dual();       \
+      default: return Inst<T, N>::reach();          \
+    }
+  switch (NT) {
+    DR_CASE(2) DR_CASE(4) DR_CASE(8) DR_CASE(16)
+    default: return nullptr;
+  }
+#undef DR_CASE
+}
+
+const void* kernel_for(const dr_ctx* c, int kind, int NT) {
+  return c->prec == DR_PREC_F64 ? kernel_of<double>(kind, NT) : kernel_of<float>(kind, NT);
+}
+
+size_t reach_extra_lds() { return 64 + 16 + 640 * sizeof(double); }
+
+size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
+  size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
+  if (kind == Q_BOUND) return b;
+  if (kind == Q_REACH) return b + reach_extra_lds();
+  return 0;
+}
+
+// Launch shape of a persistent kernel: workgroups per CU from the occupancy
+// calculator, optionally capped by the tile configuration (autotuner id:
+// tile_cfg = 1 + (wgs_per_cu - 1), 0 = as many as fit).
+int persistent_grid(dr_ctx* c, const void* fn, size_t lds) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWG, lds) != hipSuccess || nb < 1) nb = 1;
+  if (c->tile_cfg > 0) nb = std::min(nb, c->tile_cfg);
+  return std::max(1, nb * c->cus);
+}
+
+dr_status launch(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, hipStream_t stream) {
+  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWG), args, lds, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  return DR_OK;
+}
+
+unsigned* queue_of(dr_ctx* c, int kind, int net) { return c->queues + ((size_t)kind * kMaxNets + net) * 2; }
+
+dr_status check_batch(dr_ctx* c, const dr_batch* b) {
+  if (!b) return fail(c, DR_EINVAL, "batch is NULL");
+  if (b->n_sub < 0) return fail(c, DR_ESHAPE, "n_sub < 0");
+  if (b->n_sub > c->max_sub) return fail(c, DR_ECAPACITY, "n_sub exceeds the context capacity max_sub");
+  if (b->n_sub > 0 && (!b->x_center || !b->x_radius)) return fail(c, DR_EINVAL, "x_center/x_radius is NULL");
+  if (b->split_ptr && !b->split_packed) return fail(c, DR_EINVAL, "split_ptr without split_packed");
+  if (c->n_nets > 1 && !b->net_id && b->n_sub > 0) return fail(c, DR_EINVAL, "net_id required with several networks");
+  return DR_OK;
+}
+
+template <typename T>
+dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStream_t stream) {
+  const int L = nw.n_layers;
+  for (int k = 1; k <= L; ++k) {
+    const int npk = nd.np[k], npkm1 = nd.np[k - 1];
+    T *Wn, *bn, *Wf, *Wa;
+    hipError_t e;
+    if ((e = ctx_alloc(c, &Wn, sizeof(T) * npk * npkm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &bn, sizeof(T) * npk)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    const int total = npk * npkm1;
+    const int blocks = (std::max(total, npk) + 255) / 256;
+    if (nw.wdtype == DR_DTYPE_F64)
+      hipLaunchKernelGGL((dr::k_copy_weights<T, double>), dim3(blocks), dim3(256), 0, stream,
+                         (const double*)nw.W[k - 1], (const double*)nw.b[k - 1], nd.n[k], nd.n[k - 1], npk, npkm1,
+                         Wn, bn);
+    else
+      hipLaunchKernelGGL((dr::k_copy_weights<T, float>), dim3(blocks), dim3(256), 0, stream,
+                         (const float*)nw.W[k - 1], (const float*)nw.b[k - 1], nd.n[k], nd.n[k - 1], npk, npkm1,
+                         Wn, bn);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "weight copy");
+    if ((e = ctx_alloc(c, &Wf, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &Wa, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    hipLaunchKernelGGL((dr::k_swizzle<T>), dim3((total + 255) / 256), dim3(256), 0, stream, Wn, npk, npkm1, 0, Wf);
+    hipLaunchKernelGGL((dr::k_swizzle<T>), dim3((total + 255) / 256), dim3(256), 0, stream, Wn, npk, npkm1, 1, Wa);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "weight swizzle");
+    nd.Wn[k - 1] = Wn; nd.bn[k - 1] = bn; nd.Wf[k - 1] = Wf; nd.Wa[k - 1] = Wa;
+  }
+  // seeds of the final rows
+  const int npLm1 = nd.np[L - 1];
+  double *seedW, *seedB, *skip, *C;
+  hipError_t e;
+  if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+  if ((e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+  if ((e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+  const int n_target = nw.A ? nw.n_state : nd.n[L];
+  const double* Cdev = nw.spec;
+  if (!Cdev) {
+    std::vector<double> I((size_t)nd.q * n_target, 0.0);
+    for (int i = 0; i < nd.q; ++i) I[(size_t)i * n_target + i] = 1.0;
+    if ((e = ctx_alloc(c, &C, sizeof(double) * I.size())) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = hipMemcpy(C, I.data(), sizeof(double) * I.size(), hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(c, e, "hipMemcpy");
+    Cdev = C;
+  }
+  const int tot = nd.R * npLm1;
+  hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
+                     (const T*)nd.bn[L - 1], nd.n[L], nd.np[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0],
+                     seedW, seedB, skip);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
+  nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip;
+  return DR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_options* opt, hipStream_t stream) {
+  if (!out) return fail(nullptr, DR_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (!nets || !opt) return fail(nullptr, DR_EINVAL, "nets/opt is NULL");
+  if (n_nets < 1 || n_nets > kMaxNets) return fail(nullptr, DR_ESHAPE, "n_nets must be in 1..8");
+  if (opt->precision != DR_PREC_F32 && opt->precision != DR_PREC_F64) return fail(nullptr, DR_EINVAL, "bad precision");
+  if (opt->intermediate != DR_INTER_CROWN_IBP && opt->intermediate != DR_INTER_IBP)
+    return fail(nullptr, DR_EINVAL, "bad intermediate mode");
+  if (opt->max_sub < 1 || opt->max_splits < 0 || opt->max_splits > 4096)
+    return fail(nullptr, DR_ESHAPE, "max_sub must be >= 1 and max_splits in 0..4096");
+  dr_ctx* c = new (std::nothrow) dr_ctx();
+  if (!c) return fail(nullptr, DR_ENOMEM, "host allocation failed");
+  c->prec = opt->precision;
+  c->inter = opt->intermediate;
+  c->max_sub = opt->max_sub;
+  c->max_splits = opt->max_splits;
+  c->tile_cfg = opt->tile_cfg;
+  c->n_nets = n_nets;
+  if (opt->margin_mode != DR_MARGIN_RIGOROUS && opt->margin_mode != DR_MARGIN_OFF) {
+    delete c;
+    return fail(nullptr, DR_EINVAL, "bad margin_mode");
+  }
+  auto bail = [&](dr_status st) {
+    g_create_error = c->err;
+    dr_destroy(c);
+    return st;
+  };
+  hipError_t e;
+  if ((e = hipGetDevice(&c->dev)) != hipSuccess) return bail(hip_fail(c, e, "hipGetDevice"));
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, c->dev)) != hipSuccess) return bail(hip_fail(c, e, "hipGetDeviceProperties"));
+  c->cus = prop.multiProcessorCount;
+  for (int i = 0; i < n_nets; ++i) {
+    const dr_network& nw = nets[i];
+    const int L = nw.n_layers;
+    if (L < 2 || L > kMaxL) return bail(fail(c, DR_ESHAPE, "n_layers must be in 2..8"));
+    if (!nw.widths || !nw.W || !nw.b) return bail(fail(c, DR_EINVAL, "network arrays are NULL"));
+    if (nw.wdtype != DR_DTYPE_F32 && nw.wdtype != DR_DTYPE_F64) return bail(fail(c, DR_EINVAL, "bad wdtype"));
+    if (nw.wdtype == DR_DTYPE_F64 && c->prec == DR_PREC_F32)
+      return bail(fail(c, DR_EINVAL, "FP64 weights need precision DR_PREC_F64 (the network is its weights)"));
+    dr::NetDev& nd = c->hnet[i];
+    std::memset(&nd, 0, sizeof(nd));
+    nd.L = L;
+    int wmax = 0;
+    for (int k = 0; k <= L; ++k) {
+      nd.n[k] = nw.widths[k];
+      if (nd.n[k] < 1) return bail(fail(c, DR_ESHAPE, "widths must be >= 1"));
+      if (k >= 1 && k <= L - 1) wmax = std::max(wmax, nd.n[k]);
+      if (!nw.W[std::max(k - 1, 0)] || !nw.b[std::max(k - 1, 0)]) return bail(fail(c, DR_EINVAL, "W/b pointer NULL"));
+    }
+    if (nd.n[0] > 16) return bail(fail(c, DR_ESHAPE, "n_0 must be <= 16"));
+    if (nd.n[L] > 64) return bail(fail(c, DR_ESHAPE, "n_L must be <= 64"));
+    if (wmax > 256) return bail(fail(c, DR_ESHAPE, "hidden widths must be <= 256"));
+    int NT = 2;
+    while (NT * 16 < wmax) NT *= 2;
+    nd.NT = NT;
+    nd.np[0] = 16;
+    for (int k = 1; k <= L - 1; ++k) nd.np[k] = 16 * NT;
+    nd.np[L] = pad16(nd.n[L]);
+    nd.H = 0;
+    for (int k = 1; k <= L - 1; ++k) { nd.hoff[k - 1] = nd.H; nd.H += nd.n[k]; }
+    nd.Hp = (L - 1) * 16 * NT;
+    const bool closed = nw.A != nullptr || nw.B != nullptr;
+    if (closed && (!nw.A || !nw.B)) return bail(fail(c, DR_EINVAL, "closed loop needs both A and B"));
+    if (closed && (nw.n_state < 1 || nw.n_state > 16 || nw.n_state != nd.n[0]))
+      return bail(fail(c, DR_ESHAPE, "closed loop needs n_state == n_0 <= 16"));
+    nd.A = nw.A;
+    nd.n_state = closed ? nw.n_state : 0;
+    const int n_target = closed ? nw.n_state : nd.n[L];
+    nd.q = nw.spec ? nw.n_spec : n_target;
+    if (nw.spec) c->has_spec = true;
+    if (nd.q < 1 || nd.q > 8) return bail(fail(c, DR_ESHAPE, "spec directions q must be in 1..8"));
+    nd.R = 2 * nd.q;
+    if (i == 0) {
+      c->n0 = nd.n[0]; c->q = nd.q; c->R = nd.R; c->closed = closed;
+    } else if (nd.n[0] != c->n0 || nd.q != c->q || closed != c->closed) {
+      return bail(fail(c, DR_ESHAPE, "all networks of a context need the same n_0, spec length and loop type"));
+    }
+    c->H_max = std::max(c->H_max, nd.H);
+    c->Hp_max = std::max(c->Hp_max, nd.Hp);
+    dr_status st = c->prec == DR_PREC_F64 ? setup_weights<double>(c, nw, nd, stream) : setup_weights<float>(c, nw, nd, stream);
+    if (st != DR_OK) return bail(st);
+  }
+  if ((e = ctx_alloc(c, &c->dnet, sizeof(dr::NetDev) * n_nets)) != hipSuccess) return bail(hip_fail(c, e, "hipMalloc"));
+  if ((e = hipMemcpyAsync(c->dnet, c->hnet, sizeof(dr::NetDev) * n_nets, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    return bail(hip_fail(c, e, "hipMemcpyAsync"));
+  // scratch
+  const size_t S = (size_t)c->max_sub, Hp = (size_t)c->Hp_max;
+  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
+  dr::Scratch& sc = c->sc;
+  sc.Hp_max = c->Hp_max;
+  sc.margin_on = opt->margin_mode == DR_MARGIN_RIGOROUS ? 1 : 0;
+  if ((e = ctx_alloc(c, &sc.bl, sizeof(double) * S * Hp)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.bu, sizeof(double) * S * Hp)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.rel, 4 * tsz * S * Hp)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.slot, sizeof(int) * S * Hp)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.st, sizeof(uint32_t) * S)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.rows, sizeof(int) * S * 8)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.margin, sizeof(double) * S * 16)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.order, sizeof(int) * S)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.net_cnt, sizeof(int) * kMaxNets)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.net_off, sizeof(int) * kMaxNets)) != hipSuccess ||
+      (e = ctx_alloc(c, &c->queues, sizeof(unsigned) * 2 * Q_KINDS * kMaxNets)) != hipSuccess)
+    return bail(hip_fail(c, e, "hipMalloc scratch"));
+  if ((e = hipMemsetAsync(c->queues, 0, sizeof(unsigned) * 2 * Q_KINDS * kMaxNets, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(sc.rows, 0, sizeof(int) * S * 8, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(sc.margin, 0, sizeof(double) * S * 16, stream)) != hipSuccess)
+    return bail(hip_fail(c, e, "hipMemsetAsync"));
+  // launch shapes and the per-wave tape of the dual ascent
+  size_t tape_bytes = 0;
+  for (int i = 0; i < n_nets; ++i) {
+    const dr::NetDev& nd = c->hnet[i];
+    for (int kind = 0; kind < Q_KINDS; ++kind) {
+      const void* fn = kernel_for(c, kind, nd.NT);
+      if (!fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
+      const size_t lds = lds_bytes(c, kind, nd);
+      if (lds > 0) {
+        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+      }
+      c->lds[kind][i] = lds;
+      c->grid[kind][i] = persistent_grid(c, fn, lds);
+    }
+    const size_t waves = (size_t)c->grid[Q_DUAL][i] * dr::kWavesPerWG;
+    tape_bytes = std::max(tape_bytes, waves * (size_t)(nd.L - 1) * nd.NT * 256 * tsz);
+  }
+  if ((e = ctx_alloc(c, &c->tape, tape_bytes)) != hipSuccess) return bail(hip_fail(c, e, "hipMalloc tape"));
+  if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(c, e, "set-up"));
+  *out = c;
+  return DR_OK;
+}
+
+dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  dr_status st = check_batch(c, b);
+  if (st != DR_OK) return st;
+  c->batch.n_sub = b->n_sub;
+  c->batch.net_id = b->net_id;
+  c->batch.xc = b->x_center;
+  c->batch.xr = b->x_radius;
+  c->batch.sptr = b->split_ptr;
+  c->batch.spk = b->split_packed;
+  c->have_batch = true;
+  if (b->n_sub == 0) return DR_OK;
+  hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
+                     c->sc.net_cnt, c->sc.net_off, c->sc.st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  for (int i = 0; i < c->n_nets; ++i) {
+    const dr::NetDev& nd = c->hnet[i];
+    const void* fn = kernel_for(c, Q_BOUND, nd.NT);
+    int net_index = i, inter = c->inter, ms = c->max_splits;
+    dr::BatchDev bd = c->batch;
+    dr::Scratch sc = c->sc;
+    unsigned* q = queue_of(c, Q_BOUND, i);
+    void* args[] = {&c->dnet, &net_index, &bd, &sc, &q, &inter, &ms};
+    if ((st = launch(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, stream)) != DR_OK) return st;
+  }
+  if (status) {
+    e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * b->n_sub, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "status copy");
+  }
+  return DR_OK;
+}
+
+static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t stream) {
+  fa.batch = c->batch;
+  fa.sc = c->sc;
+  fa.tape = c->tape;
+  fa.H_max = c->H_max;
+  fa.max_splits = std::max(c->max_splits, 1);
+  fa.q = c->q;
+  for (int i = 0; i < c->n_nets; ++i) {
+    const dr::NetDev& nd = c->hnet[i];
+    const int kind = duals ? Q_DUAL : Q_FINAL;
+    const void* fn = kernel_for(c, kind, nd.NT);
+    fa.queue = queue_of(c, kind, i);
+    int net_index = i;
+    void* args[] = {&c->dnet, &net_index, &fa};
+    dr_status st = launch(c, fn, c->grid[kind][i], 0, args, stream);
+    if (st != DR_OK) return st;
+  }
+  return DR_OK;
+}
+
+dr_status dr_propagate_backward(dr_ctx* c, double* lam_lo, double* acc_lo, double* lam_hi, double* acc_hi,
+                                hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
+  if (c->batch.n_sub == 0) return DR_OK;
+  if (!lam_lo || !acc_lo || !lam_hi || !acc_hi) return fail(c, DR_EINVAL, "output pointer is NULL");
+  dr::FinalArgs fa{};
+  fa.lam_lo = lam_lo; fa.acc_lo = acc_lo; fa.lam_hi = lam_hi; fa.acc_hi = acc_hi;
+  return run_final(c, false, fa, stream);
+}
+
+dr_status dr_concretize(dr_ctx* c, const double* lam_lo, const double* acc_lo, const double* lam_hi,
+                        const double* acc_hi, double* lb, double* ub, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
+  if (c->batch.n_sub == 0) return DR_OK;
+  if (!lam_lo || !acc_lo || !lam_hi || !acc_hi || !lb || !ub) return fail(c, DR_EINVAL, "array pointer is NULL");
+  const int S = c->batch.n_sub;
+  hipLaunchKernelGGL(dr::k_concretize, dim3((S + 255) / 256), dim3(256), 0, stream, S, c->q, c->n0, c->batch.xc,
+                     c->batch.xr, lam_lo, acc_lo, lam_hi, acc_hi, lb, ub, c->sc.st, status);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "concretize kernel");
+  return DR_OK;
+}
+
+dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, float* alpha, float* beta, double* lb,
+                            double* ub, float* grad_alpha, float* grad_beta, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
+  if (iters < 0 || iters > 100000) return fail(c, DR_EINVAL, "iters must be in 0..100000");
+  if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(c, DR_EINVAL, "lr must be finite and >= 0");
+  if (c->batch.n_sub == 0) return DR_OK;
+  if (!alpha || !beta || !lb || !ub) return fail(c, DR_EINVAL, "alpha/beta/lb/ub is NULL");
+  dr::FinalArgs fa{};
+  fa.iters = iters; fa.lr = lr; fa.init_duals = init_duals ? 1 : 0;
+  fa.alpha = alpha; fa.beta = beta; fa.lb = lb; fa.ub = ub; fa.galpha = grad_alpha; fa.gbeta = grad_beta;
+  dr_status st = run_final(c, true, fa, stream);
+  if (st != DR_OK) return st;
+  if (status) {
+    hipError_t e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * c->batch.n_sub, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "status copy");
+  }
+  return DR_OK;
+}
+
+dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->closed) return fail(c, DR_EINVAL, "reach_dt needs a closed-loop network");
+  if (c->has_spec) return fail(c, DR_EINVAL, "reach_dt bounds every state: create the context without a spec");
+  if (horizon < 0 || horizon > 10000) return fail(c, DR_EINVAL, "horizon must be in 0..10000");
+  dr_status st = check_batch(c, b);
+  if (st != DR_OK) return st;
+  if (b->split_ptr) return fail(c, DR_EINVAL, "reach_dt takes no split constraints");
+  if (!boxes) return fail(c, DR_EINVAL, "boxes is NULL");
+  c->batch.n_sub = b->n_sub;
+  c->batch.net_id = b->net_id;
+  c->batch.xc = b->x_center;
+  c->batch.xr = b->x_radius;
+  c->batch.sptr = nullptr;
+  c->batch.spk = nullptr;
+  c->have_batch = false;  // bound_init state is not valid for this batch
+  if (b->n_sub == 0) return DR_OK;
+  hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
+                     c->sc.net_cnt, c->sc.net_off, c->sc.st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  for (int i = 0; i < c->n_nets; ++i) {
+    const dr::NetDev& nd = c->hnet[i];
+    const void* fn = kernel_for(c, Q_REACH, nd.NT);
+    dr::ReachArgs ra{};
+    ra.batch = c->batch; ra.sc = c->sc; ra.queue = queue_of(c, Q_REACH, i);
+    ra.horizon = horizon; ra.boxes = boxes; ra.status = status;
+    int net_index = i;
+    void* args[] = {&c->dnet, &net_index, &ra};
+    if ((st = launch(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, stream)) != DR_OK) return st;
+  }
+  return DR_OK;
+}
+
+dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!l || !u) return fail(c, DR_EINVAL, "l/u is NULL");
+  const int S = c->batch.n_sub;
+  if (S == 0 || c->H_max == 0) return DR_OK;
+  const int tot = S * c->H_max;
+  hipLaunchKernelGGL(dr::k_export_bounds, dim3((tot + 255) / 256), dim3(256), 0, stream, S, c->Hp_max, c->H_max,
+                     c->dnet, c->batch.net_id, c->sc.bl, c->sc.bu, l, u);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "export kernel");
+  return DR_OK;
+}
+
+dr_status dr_get_rows(dr_ctx* c, int* rows, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!rows) return fail(c, DR_EINVAL, "rows is NULL");
+  if (c->batch.n_sub == 0) return DR_OK;
+  hipError_t e = hipMemcpyAsync(rows, c->sc.rows, sizeof(int) * 8 * c->batch.n_sub, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "rows copy");
+  return DR_OK;
+}
+
+dr_status dr_get_margins(dr_ctx* c, double* margin, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!margin) return fail(c, DR_EINVAL, "margin is NULL");
+  const int S = c->batch.n_sub;
+  if (S == 0) return DR_OK;
+  hipError_t e = hipMemcpy2DAsync(margin, sizeof(double) * c->R, c->sc.margin, sizeof(double) * 16,
+                                  sizeof(double) * c->R, S, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return hip_fail(c, e, "margin copy");
+  return DR_OK;
+}
+
+int dr_hidden_max(const dr_ctx* c) { return c ? c->H_max : 0; }
+int dr_spec_rows(const dr_ctx* c) { return c ? c->R : 0; }
+
+const char* dr_last_error(const dr_ctx* c) {
+  if (!c) return g_create_error.c_str();
+  return c->err.c_str();
+}
+
+void dr_destroy(dr_ctx* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Device building blocks of the bound-propagation kernels (gfx950, wave64).
+//
+// Data layout of a chain of backward bound propagation on one wavefront:
+//   The wave owns an N-tile of 16 rows (row multipliers Lambda).  The product
+//   Lambda . W_k is computed transposed, D^T = W_k^T Lambda^T, on the 16x16x4 MFMA:
+//   the A operand is a 16x4 slice of W (pre-swizzled in global memory so that a
+//   lane fetches its four A values of one K-tile with one vector load) and the B
+//   operand is Lambda^T.  The D layout of one product is exactly the B layout of
+//   the next one up to a fixed permutation of the summation index, so a whole
+//   chain stays in registers: register cur[t][i] of lane l holds row (l % 16),
+//   neuron 16 t + nrn(l / 16, i) of the current layer.
+//   The permutation differs between the f32 and f64 MFMA output layouts (verified
+//   on the device): f32 D[4 g + i][n], f64 D[4 i + g][n] for lane group g.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dr {
+
+constexpr int kMaxL = 8;         // affine layers per network
+constexpr int kMaxNets = 8;
+constexpr int kWG = 256;         // threads per workgroup (4 waves)
+constexpr int kWavesPerWG = kWG / 64;
+
+template <typename T> struct Vec4T;
+template <> struct Vec4T<float> { typedef float v __attribute__((ext_vector_type(4))); };
+template <> struct Vec4T<double> { typedef double v __attribute__((ext_vector_type(4))); };
+template <typename T> using V4 = typename Vec4T<T>::v;
+
+__device__ __forceinline__ V4<float> mfma16(float a, float b, V4<float> c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ V4<double> mfma16(double a, double b, V4<double> c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Neuron (within a 16-tile) held by lane group g in accumulator register i.
+template <typename T> __host__ __device__ constexpr int nrn(int g, int i) {
+  return sizeof(T) == 4 ? 4 * g + i : 4 * i + g;
+}
+// Position (within a 16-tile, permuted storage) of neuron c: inverse of nrn.
+template <typename T> __host__ __device__ constexpr int pos_of(int c) {
+  return sizeof(T) == 4 ? c : (c & 3) * 4 + (c >> 2);
+}
+
+// Unit roundoff of the chain arithmetic.
+template <typename T> __host__ __device__ constexpr double unit_round() {
+  return sizeof(T) == 4 ? 0x1p-24 : 0x1p-53;
+}
+// gamma_n = n u / (1 - n u) (Higham, dot-product error bound, any summation order).
+template <typename T> __host__ __device__ inline double gamma_n(int n) {
+  double nu = n * unit_round<T>();
+  return nu / (1.0 - nu);
+}
+
+// Smallest float >= f (for finite f); used to round margins and intercepts outward.
+__device__ __forceinline__ float next_up(float f) {
+  if (!(f < __builtin_huge_valf())) return f;
+  if (f == 0.0f) return 0x1p-149f;
+  unsigned u = __float_as_uint(f);
+  return __uint_as_float(f > 0.0f ? u + 1u : u - 1u);
+}
+__device__ __forceinline__ float round_up_to(float*, double x) {
+  float f = (float)x;
+  if ((double)f < x) f = next_up(f);
+  return f;
+}
+__device__ __forceinline__ double round_up_to(double*, double x) { return x; }
+template <typename T> __device__ __forceinline__ T rup(double x) { return round_up_to((T*)nullptr, x); }
+
+// Per-network description in device memory (all arrays owned by the context,
+// every dimension padded to a multiple of 16 with zeros).
+struct NetDev {
+  int L;                     // affine layers
+  int NT;                    // 16-tiles of every hidden layer (hidden widths padded to 16 NT)
+  int n[kMaxL + 1];          // true widths n_0..n_L
+  int H;                     // true hidden count
+  int Hp;                    // padded hidden count = (L - 1) * 16 NT
+  int hoff[kMaxL];           // natural offset of hidden layer k (index k-1) in [0, H)
+  const void* Wn[kMaxL];     // natural row-major, padded rows/cols: rows np_k, cols np_{k-1}
+  const void* bn[kMaxL];     // padded biases
+  const void* Wf[kMaxL];     // forward swizzle: A[m][kk] = W_k[kk][m]
+  const void* Wa[kMaxL];     // adjoint swizzle: A[m][kk] = W_k[m][kk]
+  int np[kMaxL + 1];         // padded widths (hidden: 16 NT; input/output: multiple of 16)
+  const double* seedW;       // R x np_{L-1}: g = a_L W_L of every final row (FP64)
+  const double* seedB;       // R: a_L . b_L
+  const double* skip;        // R x 16: (+-c) A for the closed loop, zeros otherwise
+  const double* A;           // n_state x n_0 (closed loop) or null
+  int n_state;
+  int q;                     // spec directions
+  int R;                     // 2q rows
+};
+
+// Scratch and outputs shared by the kernels of one context.
+struct Scratch {
+  double* bl;                // S x Hp_max lower pre-activation bounds (natural order)
+  double* bu;                // S x Hp_max upper
+  void* rel;                 // S x Hp_max x 4 T relaxation (lo, up, t, mu), permuted order
+  int* slot;                 // S x Hp_max split slot (-1 or idx << 1 | positive), permuted
+  uint32_t* st;              // S status bits
+  int* rows;                 // S x 8 chain rows
+  double* margin;            // S x 16 margin of final rows
+  int* order;                // S subdomains sorted by network
+  int* net_cnt;              // kMaxNets counts
+  int* net_off;              // kMaxNets offsets into order
+  int Hp_max;
+  int margin_on;             // 1: rigorous rounding margins, 0: off (diagnostics)
+};
+
+struct BatchDev {
+  int n_sub;
+  const int* net_id;
+  const double* xc;
+  const double* xr;
+  const int* sptr;
+  const uint32_t* spk;
+};
+
+// ---------------------------------------------------------------------------
+// Work queue of a persistent launch: a counter of handed-out items and a counter
+// of finished workers; the last worker to finish resets both, so the next launch
+// (also a graph replay) starts from zero without any host-side reset.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int wave_fetch(unsigned* q) {
+  int lane = threadIdx.x & 63;
+  int v = 0;
+  if (lane == 0) v = (int)atomicAdd(q, 1u);
+  return __shfl(v, 0);
+}
+__device__ __forceinline__ void wave_done(unsigned* q, unsigned n_workers) {
+  int lane = threadIdx.x & 63;
+  if (lane == 0) {
+    __threadfence();
+    unsigned d = atomicAdd(q + 1, 1u);
+    if (d == n_workers - 1) {
+      atomicExch(q, 0u);
+      atomicExch(q + 1, 0u);
+    }
+  }
+}
+
+// Sum over the four lane groups holding the same row (lanes n, n+16, n+32, n+48).
+template <typename S> __device__ __forceinline__ S row_sum(S v) {
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Products on the matrix cores.
+// ---------------------------------------------------------------------------
+// nxt[mt] = sum_kt A(mt, kt) cur[kt] for MT x KT tiles (compile-time shape: the
+// unrolled body is straight-line so loads can be hoisted ahead of the MFMAs).
+template <typename T, int MT, int KT>
+__device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw, const T (&cur)[KT][4],
+                                           T (&nxt)[MT][4], int lane) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    V4<T> acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      V4<T> a = Wsw[(mt * KT + kt) * 64 + lane];
+      acc = mfma16(a[0], cur[kt][0], acc);
+      acc = mfma16(a[1], cur[kt][1], acc);
+      acc = mfma16(a[2], cur[kt][2], acc);
+      acc = mfma16(a[3], cur[kt][3], acc);
+    }
+    nxt[mt][0] = acc[0]; nxt[mt][1] = acc[1]; nxt[mt][2] = acc[2]; nxt[mt][3] = acc[3];
+  }
+}
+
+}  // namespace dr

@@ -1,0 +1,386 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances:
+  * DR_PREC_F64 (FP64 MFMA chains, rigorous margins): 1e-9 relative to max(1, |b|);
+    the margins themselves are ~1e-13 relative, so this is far inside the 1e-5 target.
+  * DR_PREC_F32 with margins off (the FP32 arithmetic itself): 1e-5 relative, the
+    target tolerance.
+  * DR_PREC_F32 with rigorous margins: sound side only (GPU lower bounds below the
+    oracle's, upper above) plus sampled soundness; the gap is reported.
+Subdomains whose oracle bounds sit within 1e-4 of a floating-point decision (an
+adaptive slope tie u = -l or a stability boundary) are checked for soundness only.
+"""
+import numpy as np
+import pytest
+
+from oracle import crown, exact, tm
+from paper_2605_25346_amd.workloads import config_workload, random_duals
+from tests.gpu_helpers import near_tie, oracle_subset, print_stats, rel_gap, require_gpu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(wl, precision, S, margins=True, **kw):
+    from paper_2605_25346_amd.api import BoundContext
+    ms = int(np.max(np.diff(wl.batch.split_ptr))) if wl.batch.n_sub else 0
+    return BoundContext(wl.nets, precision=precision, max_sub=max(S, 1), max_splits=max(ms, kw.pop("max_splits", 0)),
+                        margins=margins, **kw)
+
+
+def _run_crown(wl, precision, margins=True):
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    S = wl.batch.n_sub
+    ctx = _ctx(wl, precision, S, margins)
+    db = DeviceBatch(wl.batch)
+    lb, ub, status, aff = ctx.crown(db)
+    l, u = ctx.dr_get_bounds()
+    rows = ctx.dr_get_rows()
+    marg = ctx.dr_get_margins()
+    torch.cuda.synchronize()
+    res = dict(lb=lb.cpu().numpy(), ub=ub.cpu().numpy(), status=status.cpu().numpy(), l=l.cpu().numpy(),
+               u=u.cpu().numpy(), rows=rows.cpu().numpy(), margin=marg.cpu().numpy(), ctx=ctx, db=db)
+    return res
+
+
+def _compare(wl, res, idx, tol, tag, sound_side_only=False, sound_side=True):
+    ref = oracle_subset(wl, idx)
+    gaps, skipped = [], 0
+    for ii, s in enumerate(idx):
+        o = ref[ii]
+        assert (res["status"][s] & 1) == (o["status"] & 1), f"infeasibility differs at {s}"
+        if o["status"]:
+            assert np.all(np.isposinf(res["lb"][s])) and np.all(np.isneginf(res["ub"][s]))
+            continue
+        tie = near_tie(o["bounds"])
+        slack = 1e-9 * np.maximum(1, np.abs(o["lb"]))
+        if not tie and sound_side:
+            assert np.all(res["lb"][s] <= o["lb"] + slack), (tag, s, res["lb"][s], o["lb"])
+            assert np.all(res["ub"][s] >= o["ub"] - slack), (tag, s, res["ub"][s], o["ub"])
+        if tie or sound_side_only:
+            skipped += tie
+            gaps.append(np.concatenate([rel_gap(res["lb"][s], o["lb"]), rel_gap(res["ub"][s], o["ub"])]))
+            continue
+        g = np.concatenate([rel_gap(res["lb"][s], o["lb"]), rel_gap(res["ub"][s], o["ub"])])
+        assert np.all(g <= tol), (tag, s, g.max())
+        gaps.append(g)
+    print_stats(f"{tag} (tie-flagged {skipped})", gaps)
+    return ref
+
+
+@pytest.mark.parametrize("precision", ["f64"])
+def test_cfg1_closed_loop_full(precision):
+    wl = config_workload(1)
+    res = _run_crown(wl, precision)
+    _compare(wl, res, range(wl.batch.n_sub), 1e-9, "cfg1 f64 closed loop")
+
+
+def test_cfg2_f64_intermediate_bounds_and_rows():
+    wl = config_workload(2, n_sub=96)
+    res = _run_crown(wl, "f64")
+    ref = _compare(wl, res, range(96), 1e-9, "cfg2 f64")
+    for s in range(96):
+        o = ref[s]
+        if o["status"]:
+            continue
+        ol = np.concatenate([b[0] for b in o["bounds"]]); ou = np.concatenate([b[1] for b in o["bounds"]])
+        H = ol.size
+        assert np.all(rel_gap(res["l"][s, :H], ol) <= 1e-9)
+        assert np.all(rel_gap(res["u"][s, :H], ou) <= 1e-9)
+        # chain rows per hidden layer: 2 x (IBP-unstable, unsplit neurons), bit-exact
+        L = wl.nets[0].n_layers
+        assert list(res["rows"][s, :L - 1]) == list(o["rows"]), (s, res["rows"][s], o["rows"])
+        assert res["rows"][s, L - 1] == 2 * 3
+
+
+def test_cfg2_f32_arithmetic_parity():
+    wl = config_workload(2, n_sub=128)
+    res = _run_crown(wl, "f32", margins=False)
+    _compare(wl, res, range(128), 1e-5, "cfg2 f32 no-margin", sound_side=False)
+
+
+def test_cfg2_f32_rigorous_sound():
+    wl = config_workload(2, n_sub=64)
+    res = _run_crown(wl, "f32", margins=True)
+    ref = _compare(wl, res, range(64), None, "cfg2 f32 rigorous", sound_side_only=True)
+    spec = np.eye(3)
+    for s in range(0, 64, 4):
+        if ref[s]["status"]:
+            continue
+        net = wl.nets[0]
+        smin, smax = exact.sampled_extrema(net, wl.batch.x_center[s], wl.batch.x_radius[s], spec,
+                                           wl.batch.splits_of(s), n=4000, seed=s)
+        if smin is None:
+            continue
+        assert np.all(res["lb"][s] <= smin) and np.all(res["ub"][s] >= smax)
+    m = res["margin"][res["status"] == 0]
+    print_stats("cfg2 f32 margin (abs)", m)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_cfg2_full_size_sampled(precision):
+    """BASELINE size (4096 subdomains) in the benchmark's launch shape; 40 sampled
+    subdomains against the oracle."""
+    wl = config_workload(2)
+    res = _run_crown(wl, precision, margins=(precision == "f64"))
+    idx = np.random.default_rng(0).choice(wl.batch.n_sub, size=40, replace=False)
+    _compare(wl, res, idx, 1e-9 if precision == "f64" else 1e-5, f"cfg2 full {precision}",
+             sound_side=(precision == "f64"))
+    assert np.all((res["status"] & ~1) == 0)
+
+
+def test_cfg3_duals_and_gradient_at_random_point():
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(3, n_sub=24)
+    net = wl.nets[0]
+    S, R, H = 24, 8, sum(net.hidden)
+    ms = int(np.max(np.diff(wl.batch.split_ptr)))
+    for precision, tol in (("f64", 1e-9), ("f32", 1e-5)):
+        ctx = _ctx(wl, precision, S, margins=(precision == "f64"))
+        db = DeviceBatch(wl.batch)
+        ctx.dr_bound_init(db)
+        al, be = random_duals(11, S, R, H, max(ms, 1), beta_scale=0.5)
+        alpha = torch.tensor(al, dtype=torch.float32, device="cuda")
+        beta = torch.tensor(be, dtype=torch.float32, device="cuda")
+        lb, ub, st, ga, gb = ctx.dr_optimize_duals(0, 0.0, alpha, beta, init_duals=False, grads=True)
+        torch.cuda.synchronize()
+        lb, ub, ga, gb = lb.cpu().numpy(), ub.cpu().numpy(), ga.cpu().numpy(), gb.cpu().numpy()
+        gl, gg = [], []
+        for s in range(S):
+            sp = wl.batch.splits_of(s)
+            bounds, _, status = crown.intermediate_bounds(net, wl.batch.x_center[s], wl.batch.x_radius[s], sp)
+            if status or near_tie(bounds):
+                continue
+            rowlb, dal, dbe, out = crown.evaluate_duals(net, bounds, wl.batch.x_center[s], wl.batch.x_radius[s],
+                                                        al[s], be[s, :, :len(sp)], sp)
+            g = np.concatenate([rel_gap(lb[s], rowlb[:4]), rel_gap(-ub[s], rowlb[4:])])
+            assert np.all(g <= tol), (precision, s, g.max())
+            gl.append(g)
+            # gradients: skip rows with a branch within 1e-6 of its kink
+            kink = np.zeros(R, bool)
+            for t in out["res"]["tape"]:
+                sc = np.maximum(np.abs(t["g"]).max(axis=1, keepdims=True), 1e-300)
+                kink |= np.any(np.abs(t["g"]) <= 1e-6 * sc, axis=1)
+            w = out["res"]["w"]
+            kink |= np.any(np.abs(w) <= 1e-6 * np.maximum(np.abs(w).max(axis=1, keepdims=True), 1e-300), axis=1)
+            unst = np.concatenate([crown.relu_relaxation(*b)[0] == crown.UNSTABLE for b in bounds])
+            gtol = max(50 * tol, 1e-6)   # gradients are returned in FP32
+            for r in np.nonzero(~kink)[0]:
+                scale = max(1.0, np.abs(dal[r]).max())
+                err = np.abs(ga[s, r, :H][unst] - dal[r][unst])
+                assert np.all(err <= gtol * scale), (precision, s, r, err.max(), scale)
+                if sp:
+                    sb = max(1.0, np.abs(dbe[r]).max())
+                    assert np.all(np.abs(gb[s, r, :len(sp)] - dbe[r]) <= gtol * sb)
+                gg.append(np.abs(ga[s, r, :H][unst] - dal[r][unst]).max() / scale)
+        print_stats(f"cfg3 {precision} bound at random duals", gl)
+        print_stats(f"cfg3 {precision} gradient (rel to max)", gg)
+        assert len(gl) >= 12
+        ctx.close()
+
+
+def _traj_kink(net, bounds, xc, xr, sp, iters, lr):
+    """Run the oracle ascent and report rows whose trajectory passes within 1e-6 of a
+    kink (a g or w component changing sign), where FP rounding may pick a branch."""
+    res = crown.optimize_duals(net, bounds, xc, xr, sp, iters=iters, lr=lr)
+    # re-walk the iterates to find near-kinks
+    R = res["traj"].shape[1]
+    unstable = np.concatenate([crown.relu_relaxation(*bk)[0] == crown.UNSTABLE for bk in bounds])
+    alpha = crown.default_alpha(net, bounds, R); beta = np.zeros((R, len(sp)))
+    kink = np.zeros(R, bool)
+    for t in range(iters + 1):
+        lb, dal, dbe, out = crown.evaluate_duals(net, bounds, xc, xr, alpha, beta, sp)
+        for tp in out["res"]["tape"]:
+            sc = np.maximum(np.abs(tp["g"]).max(axis=1, keepdims=True), 1e-300)
+            kink |= np.any((np.abs(tp["g"]) <= 1e-6 * sc) & (np.abs(tp["g"]) > 0), axis=1)
+        w = out["res"]["w"]
+        kink |= np.any(np.abs(w) <= 1e-6 * np.maximum(np.abs(w).max(axis=1, keepdims=True), 1e-300), axis=1)
+        if t == iters:
+            break
+        alpha = np.where(unstable[None, :], np.clip(alpha + lr * dal, 0, 1), alpha)
+        if beta.size:
+            beta = np.maximum(0, beta + lr * dbe)
+    return res, kink
+
+
+@pytest.mark.parametrize("cfg,n_sub", [(3, 16), (5, 24)])
+def test_pga_trajectory_f64(cfg, n_sub):
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(cfg, n_sub=n_sub)
+    ctx = _ctx(wl, "f64", n_sub)
+    db = DeviceBatch(wl.batch)
+    lb0, ub0, st0, _ = ctx.crown(db)
+    alpha, beta = ctx.new_duals()
+    lb, ub, st, _, _ = ctx.dr_optimize_duals(wl.iters, wl.lr, alpha, beta, init_duals=True)
+    torch.cuda.synchronize()
+    lb, ub, lb0, ub0 = lb.cpu().numpy(), ub.cpu().numpy(), lb0.cpu().numpy(), ub0.cpu().numpy()
+    q = lb.shape[1]
+    gaps, flagged = [], 0
+    for s in range(n_sub):
+        net = wl.nets[int(wl.batch.net_id[s])]
+        xc, xr, sp = wl.batch.x_center[s], wl.batch.x_radius[s], wl.batch.splits_of(s)
+        bounds, _, status = crown.intermediate_bounds(net, xc, xr, sp)
+        if status:
+            continue
+        assert np.all(lb[s] >= lb0[s] - 1e-12) and np.all(ub[s] <= ub0[s] + 1e-12)
+        if near_tie(bounds):
+            flagged += 1
+            continue
+        res, kink = _traj_kink(net, bounds, xc, xr, sp, wl.iters, wl.lr)
+        for r in range(2 * q):
+            got = lb[s, r] if r < q else -ub[s, r - q]
+            if kink[r]:
+                flagged += 1
+                continue
+            g = rel_gap(got, res["best"][r])
+            assert g <= 1e-7, (cfg, s, r, got, res["best"][r])
+            gaps.append(g)
+    print_stats(f"cfg{cfg} f64 PGA best-so-far ({flagged} kink/tie rows skipped)", gaps)
+    assert len(gaps) >= n_sub
+
+
+def test_cfg4_tm_reach():
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(4, n_sub=6)
+    net = wl.nets[0]
+    for precision, margins in (("f64", True), ("f32", True), ("f32", False)):
+        ctx = _ctx(wl, precision, 6, margins=margins)
+        db = DeviceBatch(wl.batch)
+        boxes, st = ctx.dr_reach_dt(db, wl.horizon)
+        torch.cuda.synchronize()
+        boxes = boxes.cpu().numpy()
+        gaps = []
+        for s in range(6):
+            ob, info = tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.horizon)
+            g = rel_gap(boxes[s], ob)
+            gaps.append(g)
+            if margins:
+                assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
+                assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
+            if precision == "f64":
+                assert np.all(g <= 1e-9), (s, g.max())
+            elif not margins:
+                assert np.all(g <= 1e-5), (s, g.max())
+        print_stats(f"cfg4 TM {precision} margins={margins}", gaps)
+        ctx.close()
+
+
+def test_cfg5_mixed_networks_crown():
+    wl = config_workload(5, n_sub=96)
+    res = _run_crown(wl, "f64")
+    _compare(wl, res, range(96), 1e-9, "cfg5 f64 mixed")
+    res32 = _run_crown(wl, "f32", margins=False)
+    _compare(wl, res32, range(96), 1e-5, "cfg5 f32 no-margin", sound_side=False)
+
+
+def test_edge_cases():
+    from paper_2605_25346_amd import binding as B
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import Batch, Network
+    require_gpu()
+    # tiny net: z = x (two neurons), y = h1 + h2
+    net = Network([np.array([[1.0], [1.0]]), np.array([[1.0, 1.0]])], [np.zeros(2), np.zeros(1)])
+    xc = np.array([[-1.5], [0.5], [np.nan], [0.0]])
+    xr = np.array([[0.5], [1.5], [0.1], [0.0]])
+    # subdomain 0: split z >= 0 on x in [-2,-1] (infeasible); 2: NaN box; 3: zero radius
+    batch = Batch(xc, xr, np.array([0, 1, 1, 1, 2], np.int32), np.array([1, 1], np.int32),
+                  np.array([0, 9], np.int32), np.array([1, -1], np.int32), np.zeros(4, np.int32))
+    ctx = BoundContext([net], precision="f64", max_sub=4, max_splits=1)
+    lb, ub, status, _ = ctx.crown(DeviceBatch(batch))
+    torch.cuda.synchronize()
+    st = status.cpu().numpy(); lb = lb.cpu().numpy(); ub = ub.cpu().numpy()
+    assert st[0] & B.DR_RES_INFEASIBLE and np.isposinf(lb[0, 0]) and np.isneginf(ub[0, 0])
+    assert st[1] == 0 and lb[1, 0] == pytest.approx(-0.0, abs=1e-12) and ub[1, 0] == pytest.approx(4.0, abs=1e-12)
+    assert st[2] & B.DR_RES_NONFINITE
+    assert st[3] & B.DR_RES_BADSPLIT          # neuron 9 does not exist
+    # empty batch is a no-op
+    empty = Batch(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros(1, np.int32), np.zeros(0, np.int32),
+                  np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    ctx.dr_bound_init(DeviceBatch(empty))
+    # capacity
+    big = Batch(np.zeros((5, 1)), np.zeros((5, 1)), np.zeros(6, np.int32), np.zeros(0, np.int32),
+                np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(5, np.int32))
+    with pytest.raises(B.DrError) as ei:
+        ctx.dr_bound_init(DeviceBatch(big))
+    assert ei.value.status == B.DR_ECAPACITY
+    ctx.close()
+
+
+def test_autograd_function_matches_oracle_gradient():
+    from paper_2605_25346_amd.api import DeviceBatch, DualBound
+    require_gpu()
+    wl = config_workload(2, n_sub=6)
+    net = wl.nets[0]
+    ctx = _ctx(wl, "f64", 6)
+    ctx.dr_bound_init(DeviceBatch(wl.batch))
+    S, R, H = 6, 6, sum(net.hidden)
+    ms = max(int(np.max(np.diff(wl.batch.split_ptr))), 1)
+    al, be = random_duals(3, S, R, H, ms, 0.3)
+    alpha = torch.tensor(al, dtype=torch.float32, device="cuda", requires_grad=True)
+    beta = torch.tensor(be, dtype=torch.float32, device="cuda", requires_grad=True)
+    lb, ub = DualBound.apply(alpha, beta, ctx)
+    (lb.sum() - ub.sum()).backward()
+    torch.cuda.synchronize()
+    gA = alpha.grad.cpu().numpy()
+    for s in range(S):
+        sp = wl.batch.splits_of(s)
+        bounds, _, status = crown.intermediate_bounds(net, wl.batch.x_center[s], wl.batch.x_radius[s], sp)
+        if status or near_tie(bounds):
+            continue
+        al32 = alpha.detach().cpu().numpy()[s].astype(np.float64)
+        rowlb, dal, dbe, _ = crown.evaluate_duals(net, bounds, wl.batch.x_center[s], wl.batch.x_radius[s],
+                                                  al32, beta.detach().cpu().numpy()[s, :, :len(sp)].astype(np.float64), sp)
+        np.testing.assert_allclose(lb.detach().cpu().numpy()[s], rowlb[:3], rtol=1e-9, atol=1e-9)
+        unst = np.concatenate([crown.relu_relaxation(*b)[0] == crown.UNSTABLE for b in bounds])
+        # d(sum lb - sum ub)/d alpha = dalpha of every row (ub = -lb_row)
+        np.testing.assert_allclose(gA[s][:, :H][:, unst], dal[:, unst], rtol=1e-5, atol=1e-6)
+    ctx.close()
+
+
+def test_graph_capture_replay():
+    """bound_init -> propagate -> concretize -> 3 dual steps captured in one graph;
+    replays (with eager work between them) reproduce the eager results exactly."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(3, n_sub=32)
+    ctx = _ctx(wl, "f32", 32)
+    db = DeviceBatch(wl.batch)
+    alpha, beta = ctx.new_duals()
+    S, q = 32, ctx.q
+    f = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")
+    aff = (f(S, q, 8), f(S, q), f(S, q, 8), f(S, q))
+    cout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+    dout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+
+    def step():
+        ctx.dr_bound_init(db)
+        ctx.dr_propagate_backward(aff)
+        ctx.dr_concretize(*aff, out=cout)
+        ctx.dr_optimize_duals(3, 0.1, alpha, beta, init_duals=True, out=dout)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (*cout[:2], *dout[:2])]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        for t in (*cout[:2], *dout[:2]):
+            t.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = [t.clone() for t in (*cout[:2], *dout[:2])]
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b), f"replay {rep} differs"
+        step()   # eager work between replays
+        torch.cuda.synchronize()
+    ctx.close()
