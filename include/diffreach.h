@@ -78,7 +78,7 @@ enum { DR_MARGIN_RIGOROUS = 0, DR_MARGIN_OFF = 1 };
 
 typedef struct {
   int n_layers;               /* L >= 2 (at least one hidden layer), L <= 8 */
-  const int* widths;          /* HOST array n_0..n_L; hidden n_k <= 256, n_0 <= 64, n_L <= 64 */
+  const int* widths;          /* HOST array n_0..n_L; hidden n_k <= 256, n_0 <= 16, n_L <= 64 */
   int wdtype;                 /* DR_DTYPE_F32 or DR_DTYPE_F64: element type of W and b */
   const void* const* W;       /* HOST array of L device pointers, W_k row-major n_k x n_{k-1} */
   const void* const* b;       /* HOST array of L device pointers, b_k of n_k */
@@ -86,7 +86,8 @@ typedef struct {
   const double* B;            /* device n_state x n_L (closed loop) or NULL */
   int n_state;                /* rows of A and B; 0 without closed loop (requires n_0 == n_state) */
   const double* spec;         /* device q x n_target directions, or NULL for unit vectors */
-  int n_spec;                 /* q (ignored when spec == NULL) */
+  int n_spec;                 /* q <= 16 (ignored when spec == NULL); the spec chains and the dual
+                                 ascent need 2q <= 16, dr_reach_dt needs n_state <= 16 */
 } dr_network;
 
 typedef struct {

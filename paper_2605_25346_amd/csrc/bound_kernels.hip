@@ -58,10 +58,11 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
 
 // Relaxation of one layer applied to g (over h_k) in registers, giving the row
 // multipliers a' over z_k.  Offsets and margin accumulate per lane.
-template <typename T, int NT, bool SHARED>
-__device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4], const V4<T>* rel,
-                                            const T* __restrict__ bias, int gq, double& acc, double& acc2,
+template <typename T, int NT, bool SHARED, typename RelPtr>
+__device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4], RelPtr rel,
+                                            const T* __restrict__ bias_, int gq, double& acc, double& acc2,
                                             T& marg) {
+  gconst<T> bias = as_global(bias_);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -80,6 +81,7 @@ __device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4]
       marg += (a < (T)0 ? -a : a) * r[3];
       cur[t][i] = a;
     }
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -295,12 +297,14 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         T g[NT][4];
         const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
         const int gq = lane >> 4;
+        const T sg = valid ? sgn : (T)0;
+        gconst<T> Wr = as_global(Wrow);
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) g[t][i] = valid ? sgn * Wrow[t * 16 + nrn<T>(gq, i)] : (T)0;
+          for (int i = 0; i < 4; ++i) g[t][i] = sg * Wr[t * 16 + nrn<T>(gq, i)];
         // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
-        double acc = (valid && gq == 0) ? (double)sgn * (double)((const T*)net.bn[k - 1])[neuron] : 0.0, acc2 = 0.0;
+        double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = 0.0;
         T marg = 0;
         T w[1][4];
         chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane);
@@ -398,7 +402,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
   const int HpS = sc.Hp_max;
   const unsigned n_workers = gridDim.x * kWavesPerWG;
   const int wave_global = blockIdx.x * kWavesPerWG + (tid >> 6);
-  T* tape = DUALS ? (T*)fa.tape + (size_t)wave_global * (L - 1) * NT * 256 : nullptr;
+  gmut<T> tape = as_global_mut(DUALS ? (T*)fa.tape + (size_t)wave_global * (L - 1) * NT * 256 : (T*)nullptr);
 
   for (;;) {
     const int item = wave_fetch(fa.queue);
@@ -410,35 +414,46 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     const uint32_t st = inrange ? sc.st[s] : 0u;
     const bool live = inrange && !(st & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT));
     const size_t so = (size_t)s * HpS;
-    const V4<T>* rel = (const V4<T>*)sc.rel + so;
-    const int* slot = sc.slot + so;
+    gconst<V4<T>> rel = as_global((const V4<T>*)sc.rel + so);
+    gconst<int> slot = as_global(sc.slot + so);
+    // loads below are unconditional (addresses are clamped into range) and masked
+    // by selects, so the wave runs straight-line code
     double xcv[4], xrv[4];
+    gconst<double> xcp = as_global(fa.batch.xc + (size_t)s * n0);
+    gconst<double> xrp = as_global(fa.batch.xr + (size_t)s * n0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = nrn<T>(gq, i);
-      xcv[i] = (inrange && m < n0) ? fa.batch.xc[(size_t)s * n0 + m] : 0.0;
-      xrv[i] = (inrange && m < n0) ? fa.batch.xr[(size_t)s * n0 + m] : 0.0;
+      const bool ok = inrange && m < n0;
+      const int mm = m < n0 ? m : 0;
+      const double xv = xcp[mm], rv = xrp[mm];
+      xcv[i] = ok ? xv : 0.0;
+      xrv[i] = ok ? rv : 0.0;
     }
+    const double liveD = live ? 1.0 : 0.0;
     // seed margin: rounding of the FP64 seed g = a_L W_L to the chain type, times |h_{L-1}|
-    const double* seed = net.seedW + (size_t)r * net.np[L - 1];
+    gconst<double> seed = as_global(net.seedW + (size_t)r * net.np[L - 1]);
     const int lbase = (L - 2) * 16 * NT;
-    const float* arow = DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : nullptr;
-    const float* brow = DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : nullptr;
+    gmut<float> arow = as_global_mut(DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : (float*)nullptr);
+    gmut<float> brow = as_global_mut(DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : (float*)nullptr);
+    gconst<double> bu = as_global(sc.bu + so + lbase);
     double best = -INFINITY, lbv = 0.0, mgv = 0.0;
     const int n_eval = DUALS ? fa.iters + 1 : 1;
     for (int it = 0; it < n_eval; ++it) {
+      // read the caller's duals unless they are initialised here (first iteration)
+      const bool use_in = live && !(fa.init_duals && it == 0);
       T g[NT][4];
-      double acc = (live && gq == 0) ? net.seedB[r] : 0.0, acc2 = 0.0;
+      double acc = net.seedB[r] * ((gq == 0) ? liveD : 0.0), acc2 = 0.0;
       T marg = 0;
 #pragma unroll
       for (int t = 0; t < NT; ++t)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = t * 16 + nrn<T>(gq, i);
-          double gd = live ? seed[m] : 0.0;
+          double gd = seed[m] * liveD;
           T gt = (T)gd;
           g[t][i] = gt;
-          double hu = live ? fmax(sc.bu[so + lbase + m], 0.0) : 0.0;
+          double hu = fmax(bu[m], 0.0) * liveD;
           if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
         }
       // forward (backward bound propagation) with optional alpha/beta and tape
@@ -446,11 +461,11 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       {
         T cur[NT][4];
         for (int k = L - 1; k >= 1; --k) {
-          const V4<T>* rk = rel + (k - 1) * 16 * NT;
+          gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
           if (!DUALS) {
             relax_layer<T, NT, false>(g, cur, rk, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
           } else {
-            const T* bias = (const T*)net.bn[k - 1];
+            gconst<T> bias = as_global((const T*)net.bn[k - 1]);
             const int hoff = net.hoff[k - 1];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -460,21 +475,19 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 V4<T> rr = rk[t * 16 + gq * 4 + i];
                 T gv = g[t][i];
                 tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
-                T lo = rr[0];
-                if (rr[2] > (T)0 && c < net.n[k]) {
-                  float av = (live && !(fa.init_duals && it == 0)) ? arow[hoff + c] : (float)rr[0];
-                  lo = (T)av;
-                }
+                const bool uns = rr[2] > (T)0 && c < net.n[k];
+                const float aload = arow[uns ? hoff + c : 0];
+                const T lo = uns ? (use_in ? (T)aload : rr[0]) : rr[0];
                 T a = (gv >= (T)0 ? lo : rr[1]) * gv;
                 const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
-                if (sp >= 0) {
-                  float bv = (live && !(fa.init_duals && it == 0)) ? brow[sp >> 1] : 0.0f;
-                  a -= (sp & 1) ? (T)bv : -(T)bv;
-                }
+                const float bload = brow[sp >= 0 ? (sp >> 1) : 0];
+                const T bv = (sp >= 0 && use_in) ? (T)bload : (T)0;
+                a -= (sp & 1) ? bv : -bv;
                 double bj = (double)bias[c];
                 acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
                 marg += (a < (T)0 ? -a : a) * rr[3];
                 cur[t][i] = a;
+                if (i == 3) __builtin_amdgcn_sched_barrier(0);
               }
           }
           if (k > 1)
@@ -513,7 +526,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
             double ao = accs - mg;
             if (lower) fa.acc_lo[(size_t)s * q + rr] = ao;
             else fa.acc_hi[(size_t)s * q + rr] = -ao;
-            sc.margin[(size_t)s * 16 + r] = mg;
+            sc.margin[(size_t)s * 32 + r] = mg;
             if (!(fabs(ao) < INFINITY) || !(mg < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
             else if (mg > fmax(1.0, fabs(lbv))) atomicOr(&sc.st[s], (uint32_t)DR_RES_MARGIN);
           }
@@ -525,7 +538,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
           for (int m = 0; m < n0; ++m) lam[((size_t)s * q + rr) * n0 + m] = 0.0;
           if (lower) fa.acc_lo[(size_t)s * q + rr] = INFINITY;
           else fa.acc_hi[(size_t)s * q + rr] = -INFINITY;
-          sc.margin[(size_t)s * 16 + r] = 0.0;
+          sc.margin[(size_t)s * 32 + r] = 0.0;
         }
         break;
       }
@@ -545,8 +558,8 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         gemm_tiles<T, NT, 1>((const V4<T>*)net.Wa[0], dw, dlt, lane);
       }
       for (int k = 1; k <= L - 1; ++k) {
-        const V4<T>* rk = rel + (k - 1) * 16 * NT;
-        const T* bias = (const T*)net.bn[k - 1];
+        gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
+        gconst<T> bias = as_global((const T*)net.bn[k - 1]);
         const int hoff = net.hoff[k - 1];
         T e[NT][4];
 #pragma unroll
@@ -558,36 +571,34 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
             V4<T> rr = rk[t * 16 + gq * 4 + i];
             T gv = tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane];
             const bool uns = rr[2] > (T)0 && c < net.n[k];
-            T lo = rr[0];
-            float av = 0.0f;
-            if (uns) {
-              av = (live && !(fa.init_duals && it == 0)) ? arow[hoff + c] : (float)rr[0];
-              lo = (T)av;
-            }
+            const float aload = arow[uns ? hoff + c : 0];
+            const float av = use_in ? aload : (float)rr[0];
+            const T lo = uns ? (T)av : rr[0];
             T d = gv >= (T)0 ? lo : rr[1];
             if (uns && live) {
               T da = gv >= (T)0 ? delta * gv : (T)0;
               if (!last) {
                 float nv = av + fa.lr * (float)da;
                 nv = fminf(fmaxf(nv, 0.0f), 1.0f);
-                ((float*)arow)[hoff + c] = nv;
+                arow[hoff + c] = nv;
               } else {
-                if (init_now) ((float*)arow)[hoff + c] = av;
+                if (init_now) arow[hoff + c] = av;
                 if (fa.galpha) fa.galpha[((size_t)s * R + r) * fa.H_max + hoff + c] = (float)da;
               }
             }
             const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
             if (sp >= 0 && live) {
               T db = (sp & 1) ? -delta : delta;    // -sigma * delta
-              float bv = (fa.init_duals && it == 0) ? 0.0f : brow[sp >> 1];
+              float bv = use_in ? brow[sp >> 1] : 0.0f;
               if (!last) {
-                ((float*)brow)[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
+                brow[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
               } else {
-                if (init_now) ((float*)brow)[sp >> 1] = bv;
+                if (init_now) brow[sp >> 1] = bv;
                 if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
               }
             }
             e[t][i] = delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0);
+            if (i == 3) __builtin_amdgcn_sched_barrier(0);
           }
         if (k < L - 1) gemm_tiles<T, NT, NT>((const V4<T>*)net.Wa[k], e, dlt, lane);
       }
@@ -599,7 +610,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       double bv = live ? best : INFINITY;
       if (lower) fa.lb[(size_t)s * q + rr] = bv;
       else fa.ub[(size_t)s * q + rr] = -bv;
-      sc.margin[(size_t)s * 16 + r] = live ? mgv : 0.0;
+      sc.margin[(size_t)s * 32 + r] = live ? mgv : 0.0;
       if (live && !(fabs(best) < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
     }
   }
@@ -759,11 +770,13 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
           const int neuron = valid ? S.U[row] : 0;
           T g[NT][4];
           const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
+          const T sg = valid ? (T)1 : (T)0;
+          gconst<T> Wr = as_global(Wrow);
 #pragma unroll
           for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g[t][i] = valid ? Wrow[t * 16 + nrn<T>(gq, i)] : (T)0;
-          double acc = (valid && gq == 0) ? (double)((const T*)net.bn[k - 1])[neuron] : 0.0, acc2 = acc;
+            for (int i = 0; i < 4; ++i) g[t][i] = sg * Wr[t * 16 + nrn<T>(gq, i)];
+          double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = acc;
           T marg = 0;
           T w[1][4];
           chain_to_input<T, NT, true>(net, k, g, S.rel, acc, acc2, marg, w, lane);
@@ -814,7 +827,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
       if (wid == 0) {
         const int r = lane & 15;
         const bool valid = r < ns;
-        const double* seed = net.seedW + (size_t)r * net.np[L - 1];
+        gconst<double> seed = as_global(net.seedW + (size_t)(valid ? r : 0) * net.np[L - 1]);
         const int lbase = (L - 2) * 16 * NT;
         T g[NT][4];
         T marg = 0;
@@ -823,13 +836,13 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int m = t * 16 + nrn<T>(gq, i);
-            double gd = valid ? seed[m] : 0.0;
+            double gd = seed[m] * (valid ? 1.0 : 0.0);
             T gt = (T)gd;
             g[t][i] = gt;
             double hu = fmax(S.u[lbase + m], 0.0);
             if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
           }
-        double acc = (valid && gq == 0) ? net.seedB[r] : 0.0, acc2 = acc;
+        double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
         T w[1][4];
         chain_to_input<T, NT, true>(net, L, g, S.rel, acc, acc2, marg, w, lane);
         // W_r = A_r + w (FP64); new TM row: c' = W c, P' = W P, I' = W (x) I + [acc, acc2] -+ margin
@@ -841,7 +854,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = nrn<T>(gq, i);
-          Wr[i] = valid ? (double)w[0][i] + net.skip[(size_t)r * 16 + m] : 0.0;
+          Wr[i] = ((double)w[0][i] + net.skip[(size_t)(valid ? r : 0) * 16 + m]) * (valid ? 1.0 : 0.0);
           cpart += Wr[i] * c[m];
           double a1 = Wr[i] * Ilo[m], a2 = Wr[i] * Ihi[m];
           il += fmin(a1, a2); ih += fmax(a1, a2);

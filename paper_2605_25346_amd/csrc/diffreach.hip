@@ -261,7 +261,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     const int n_target = closed ? nw.n_state : nd.n[L];
     nd.q = nw.spec ? nw.n_spec : n_target;
     if (nw.spec) c->has_spec = true;
-    if (nd.q < 1 || nd.q > 8) return bail(fail(c, DR_ESHAPE, "spec directions q must be in 1..8"));
+    if (nd.q < 1 || nd.q > 16) return bail(fail(c, DR_ESHAPE, "spec directions q must be in 1..16"));
     nd.R = 2 * nd.q;
     if (i == 0) {
       c->n0 = nd.n[0]; c->q = nd.q; c->R = nd.R; c->closed = closed;
@@ -288,7 +288,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       (e = ctx_alloc(c, &sc.slot, sizeof(int) * S * Hp)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.st, sizeof(uint32_t) * S)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.rows, sizeof(int) * S * 8)) != hipSuccess ||
-      (e = ctx_alloc(c, &sc.margin, sizeof(double) * S * 16)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.margin, sizeof(double) * S * 32)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.order, sizeof(int) * S)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.net_cnt, sizeof(int) * kMaxNets)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.net_off, sizeof(int) * kMaxNets)) != hipSuccess ||
@@ -296,7 +296,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     return bail(hip_fail(c, e, "hipMalloc scratch"));
   if ((e = hipMemsetAsync(c->queues, 0, sizeof(unsigned) * 2 * Q_KINDS * kMaxNets, stream)) != hipSuccess ||
       (e = hipMemsetAsync(sc.rows, 0, sizeof(int) * S * 8, stream)) != hipSuccess ||
-      (e = hipMemsetAsync(sc.margin, 0, sizeof(double) * S * 16, stream)) != hipSuccess)
+      (e = hipMemsetAsync(sc.margin, 0, sizeof(double) * S * 32, stream)) != hipSuccess)
     return bail(hip_fail(c, e, "hipMemsetAsync"));
   // launch shapes and the per-wave tape of the dual ascent
   size_t tape_bytes = 0;
@@ -381,6 +381,7 @@ dr_status dr_propagate_backward(dr_ctx* c, double* lam_lo, double* acc_lo, doubl
   if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
   if (c->batch.n_sub == 0) return DR_OK;
   if (!lam_lo || !acc_lo || !lam_hi || !acc_hi) return fail(c, DR_EINVAL, "output pointer is NULL");
+  if (c->R > 16) return fail(c, DR_ESHAPE, "spec rows 2q must be <= 16 for the spec chains");
   dr::FinalArgs fa{};
   fa.lam_lo = lam_lo; fa.acc_lo = acc_lo; fa.lam_hi = lam_hi; fa.acc_hi = acc_hi;
   return run_final(c, false, fa, stream);
@@ -408,6 +409,11 @@ dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, floa
   if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(c, DR_EINVAL, "lr must be finite and >= 0");
   if (c->batch.n_sub == 0) return DR_OK;
   if (!alpha || !beta || !lb || !ub) return fail(c, DR_EINVAL, "alpha/beta/lb/ub is NULL");
+  if (c->R > 16) return fail(c, DR_ESHAPE, "spec rows 2q must be <= 16 for the dual ascent");
+  for (int i = 0; i < c->n_nets; ++i)
+    if (c->prec == DR_PREC_F64 && c->hnet[i].NT > 8)
+      return fail(c, DR_ESHAPE,
+                  "FP64 dual ascent supports hidden widths <= 128 (wider chains do not fit the register file)");
   dr::FinalArgs fa{};
   fa.iters = iters; fa.lr = lr; fa.init_duals = init_duals ? 1 : 0;
   fa.alpha = alpha; fa.beta = beta; fa.lb = lb; fa.ub = ub; fa.galpha = grad_alpha; fa.gbeta = grad_beta;
@@ -481,7 +487,7 @@ dr_status dr_get_margins(dr_ctx* c, double* margin, hipStream_t stream) {
   if (!margin) return fail(c, DR_EINVAL, "margin is NULL");
   const int S = c->batch.n_sub;
   if (S == 0) return DR_OK;
-  hipError_t e = hipMemcpy2DAsync(margin, sizeof(double) * c->R, c->sc.margin, sizeof(double) * 16,
+  hipError_t e = hipMemcpy2DAsync(margin, sizeof(double) * c->R, c->sc.margin, sizeof(double) * 32,
                                   sizeof(double) * c->R, S, hipMemcpyDeviceToDevice, stream);
   if (e != hipSuccess) return hip_fail(c, e, "margin copy");
   return DR_OK;

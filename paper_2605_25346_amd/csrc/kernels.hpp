@@ -151,9 +151,26 @@ template <typename S> __device__ __forceinline__ S row_sum(S v) {
 // ---------------------------------------------------------------------------
 // nxt[mt] = sum_kt A(mt, kt) cur[kt] for MT x KT tiles (compile-time shape: the
 // unrolled body is straight-line so loads can be hoisted ahead of the MFMAs).
+// Global-memory views: loads and stores through these pointers are emitted as
+// global (not flat) memory instructions with a scalar base where the base is uniform.
+template <typename T> using gconst = const T __attribute__((address_space(1)))*;
+template <typename T> using gmut = T __attribute__((address_space(1)))*;
+template <typename T> __device__ __forceinline__ gconst<T> as_global(const T* p) { return (gconst<T>)p; }
+template <typename T> __device__ __forceinline__ gmut<T> as_global_mut(T* p) { return (gmut<T>)p; }
+
+// A pointer that is the same for every lane, moved to scalar registers so that
+// loads through it use a scalar base and 32-bit lane offsets.
+template <typename P> __device__ __forceinline__ P uniform_ptr(P p) {
+  uint64_t v = (uint64_t)p;
+  uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (P)(((uint64_t)hi << 32) | lo);
+}
+
 template <typename T, int MT, int KT>
-__device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw, const T (&cur)[KT][4],
+__device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw_, const T (&cur)[KT][4],
                                            T (&nxt)[MT][4], int lane) {
+  gconst<V4<T>> Wsw = as_global(uniform_ptr(Wsw_));
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     V4<T> acc = {0, 0, 0, 0};
@@ -166,6 +183,8 @@ __device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw, const 
       acc = mfma16(a[3], cur[kt][3], acc);
     }
     nxt[mt][0] = acc[0]; nxt[mt][1] = acc[1]; nxt[mt][2] = acc[2]; nxt[mt][3] = acc[3];
+    // keep each output tile's loads within its own tile: bounds register pressure
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 

@@ -19,16 +19,17 @@ def rel_gap(a, b):
     return np.abs(a - b) / np.maximum(1.0, np.abs(b))
 
 
-def near_tie(bounds, tol=1e-4):
-    """True if some unstable neuron's adaptive-slope decision (u > -l) or stability
-    decision (l < 0 < u) is within tol of flipping: those are decisions taken by
-    floating point, where several results are valid."""
+def near_tie(bounds, tol=1e-4, slope=True):
+    """True if some unstable neuron's adaptive-slope decision (u > -l, only when
+    ``slope``) or stability decision (l < 0 < u) is within tol of flipping: those are
+    decisions taken by floating point, where several results are valid."""
     for (l, u) in bounds:
         scale = np.maximum(np.maximum(np.abs(l), np.abs(u)), 1e-300)
         uns = (l < 0) & (u > 0)
-        if np.any(uns & (np.abs(u + l) <= tol * scale)):
+        if slope and np.any(uns & (np.abs(u + l) <= tol * scale)):
             return True
-        if np.any((np.abs(l) <= tol * scale) | (np.abs(u) <= tol * scale)):
+        # exact zeros come from split clamping on both sides: not a floating-point decision
+        if np.any(((np.abs(l) <= tol * scale) & (l != 0)) | ((np.abs(u) <= tol * scale) & (u != 0))):
             return True
     return False
 
