@@ -231,6 +231,85 @@ def mixed_batch(torch, args, precision="f32"):
     return res
 
 
+def split_boxes(batch, k):
+    """Input splitting: bisect the k widest input dimensions of every box (round robin
+    from the widest), 2^k sub-boxes per subdomain, each inheriting the split set."""
+    from paper_2605_25346_amd.workloads import Batch
+    S, n0 = batch.x_center.shape
+    xc, xr = batch.x_center.copy(), batch.x_radius.copy()
+    parent = np.arange(S)
+    for j in range(k):
+        dim = np.argsort(-xr, axis=1, kind="stable")[:, 0]
+        half = xr[np.arange(xr.shape[0]), dim] / 2.0
+        lo_c, hi_c = xc.copy(), xc.copy()
+        lo_c[np.arange(xc.shape[0]), dim] -= half
+        hi_c[np.arange(xc.shape[0]), dim] += half
+        xr2 = xr.copy(); xr2[np.arange(xr.shape[0]), dim] = half
+        xc = np.concatenate([lo_c, hi_c]); xr = np.concatenate([xr2, xr2]); parent = np.concatenate([parent, parent])
+    sub = batch.subset(parent)
+    sub.x_center, sub.x_radius = xc, xr
+    return sub, parent
+
+
+def equal_tightness(torch, args, precision="f32", max_k=8):
+    """Plain CROWN + input splitting vs alpha/beta ascent at equal tightness: the mean
+    width-sum volume proxy V = sum_j (ub_j - lb_j) (the paper's tube-volume proxy for one
+    step) of the ascent's bounds is the target; the number of sub-boxes per subdomain is
+    doubled until plain CROWN reaches it.  Both sides run the same kernels and are
+    timed as graph replays with inputs resident."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(3)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=16)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    q = ctx.q
+    f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+    dout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+
+    def step_ab():
+        ctx.dr_bound_init(db)
+        ctx.dr_optimize_duals(wl.iters, wl.lr, alpha, beta, init_duals=True, out=dout)
+
+    ms_ab, _ = time_graph(torch, step_ab, max(2, args.steps // 10), 1)
+    lb, ub, st = (t.cpu().numpy() for t in dout)
+    live = (st & 9) == 0
+    V_ab = float(np.mean((ub - lb).sum(axis=1)[live]))
+    ctx.close()
+    curve = []
+    for k in range(0, max_k + 1):
+        sub, parent = split_boxes(wl.batch, k)
+        Sk = sub.n_sub
+        ck = BoundContext(wl.nets, precision=precision, max_sub=Sk, max_splits=16)
+        dk = DeviceBatch(sub)
+        aff = (f(Sk, q, ctx.n0), f(Sk, q), f(Sk, q, ctx.n0), f(Sk, q))
+        cout = (f(Sk, q), f(Sk, q), torch.zeros(Sk, dtype=torch.int32, device="cuda"))
+
+        def step_crown():
+            ck.dr_bound_init(dk)
+            ck.dr_propagate_backward(aff)
+            ck.dr_concretize(*aff, out=cout)
+
+        ms_k, _ = time_graph(torch, step_crown, max(2, args.steps // 10), 1)
+        slb, sub_ub, sst = (t.cpu().numpy() for t in cout)
+        ok = (sst & 9) == 0
+        ulb = np.full((S, q), np.inf); uub = np.full((S, q), -np.inf)
+        np.minimum.at(ulb, parent[ok], slb[ok]); np.maximum.at(uub, parent[ok], sub_ub[ok])
+        feas = live & np.isfinite(ulb).all(axis=1)
+        V_k = float(np.mean((uub - ulb).sum(axis=1)[feas]))
+        curve.append(dict(k=k, sub_boxes=2 ** k, V=V_k, ms=ms_k))
+        ck.close()
+        del dk, aff, cout
+        torch.cuda.empty_cache()
+        if V_k <= V_ab:
+            break
+    reached = curve[-1]["V"] <= V_ab
+    return dict(V_alpha_beta=V_ab, ms_alpha_beta=ms_ab, curve=curve, reached=reached,
+                speedup_vs_plain_crown=(curve[-1]["ms"] / ms_ab) if reached else None)
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 reference, as it stands, on a bounded sample of the headline batch."""
     from oracle import crown
@@ -263,6 +342,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU scaling is not part of it",
@@ -273,6 +354,15 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
+        return
     print("bench: headline workload", file=sys.stderr, flush=True)
     hl, wl = headline(torch, args, "f32")
     extra = {}
@@ -295,6 +385,8 @@ def main():
             box_steps_per_s=tr["box_steps_per_s"], ms_per_call=tr["ms"],
             roofline=dict(bound="mfma", achieved=tr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=tr["tflops"] / PEAK_TFLOPS["f32"]))
+        print("bench: equal tightness", file=sys.stderr, flush=True)
+        extra["equal_tightness_abcrown_vs_crown_input_splitting"] = equal_tightness(torch, args, "f32")
         print("bench: mixed batch", file=sys.stderr, flush=True)
         mb = mixed_batch(torch, args, "f32")
         extra["mixed_S16384_crown+10it"] = dict(subdomains_per_s=mb["subdomains_per_s"], ms_per_step=mb["ms"])

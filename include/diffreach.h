@@ -104,7 +104,9 @@ typedef struct {
   int intermediate;           /* DR_INTER_CROWN_IBP (default) or DR_INTER_IBP */
   int max_sub;                /* capacity: largest batch S for this context */
   int max_splits;             /* capacity: splits per subdomain (beta columns) */
-  int tile_cfg;               /* 0 = default launch shape; >0 = autotuner config id */
+  int tile_cfg;               /* launch configuration: 4-bit cap of workgroups per CU per kernel kind
+                                 (bits 0-3 bound_init, 4-7 spec chains, 8-11 dual ascent, 12-15
+                                 reach_dt; 0 = as many as fit), as chosen by the autotuner */
   int margin_mode;            /* DR_MARGIN_RIGOROUS (default) or DR_MARGIN_OFF (diagnostics only:
                                  rounding of the chains is then not covered, bounds may be unsound) */
 } dr_options;

@@ -94,7 +94,10 @@ class BoundContext:
         opt.intermediate = B.DR_INTER_CROWN_IBP if intermediate == "crown_ibp" else B.DR_INTER_IBP
         opt.max_sub = max_sub
         opt.max_splits = max_splits
-        opt.tile_cfg = tile_cfg
+        if tile_cfg == "auto":
+            from .autotune import lookup
+            tile_cfg = lookup(nets, precision)
+        opt.tile_cfg = int(tile_cfg)
         opt.margin_mode = B.DR_MARGIN_RIGOROUS if margins else B.DR_MARGIN_OFF
         ctx = ctypes.c_void_p()
         st = self.lib.dr_create(ctypes.byref(ctx), structs, len(nets), ctypes.byref(opt), _stream())

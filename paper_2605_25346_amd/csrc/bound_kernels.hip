@@ -87,18 +87,40 @@ __device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4]
 
 // Backward chain of one N-tile from hidden layer K-1 down to the input.
 // g: multipliers over h_{K-1} (seed). On return w holds the input coefficients.
+// With lds_w != null the products read the LDS copy of the forward-swizzled weights.
 template <typename T, int NT, bool SHARED>
 __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, T (&g)[NT][4], const V4<T>* rel_all,
-                                               double& acc, double& acc2, T& marg, T (&w)[1][4], int lane) {
+                                               double& acc, double& acc2, T& marg, T (&w)[1][4], int lane,
+                                               const V4<T>* lds_w = nullptr) {
   T cur[NT][4];
   const int gq = lane >> 4;
   for (int k = K - 1; k >= 1; --k) {
     relax_layer<T, NT, SHARED>(g, cur, rel_all + (k - 1) * 16 * NT, (const T*)net.bn[k - 1], gq, acc, acc2,
                                marg);
-    if (k > 1)
-      gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
-    else
-      gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+    if (lds_w) {
+      lconst<V4<T>> Wl = (lconst<V4<T>>)(lds_w + lds_w_offset(k, NT));
+      if (k > 1)
+        gemm_tiles_p<T, NT, NT>(Wl, cur, g, lane);
+      else
+        gemm_tiles_p<T, 1, NT>(Wl, cur, w, lane);
+    } else {
+      if (k > 1)
+        gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
+      else
+        gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+    }
+  }
+}
+
+// Stage the forward-swizzled weights of layers 1..L-1 into LDS (once per workgroup).
+template <typename T>
+__device__ void stage_weights(const NetDev& net, V4<T>* dst) {
+  const int NT = net.NT;
+  for (int k = 1; k <= net.L - 1; ++k) {
+    const int n = (k == 1 ? NT : NT * NT) * 64;
+    gconst<V4<T>> src = as_global((const V4<T>*)net.Wf[k - 1]);
+    V4<T>* d = dst + lds_w_offset(k, NT);
+    for (int e = threadIdx.x; e < n; e += kWG) d[e] = src[e];
   }
 }
 
@@ -179,7 +201,7 @@ __device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, cons
 // ---------------------------------------------------------------------------
 // a1-a4: intermediate bounds, one workgroup per subdomain, persistent.
 // ---------------------------------------------------------------------------
-template <typename T, int NT>
+template <typename T, int NT, bool WLDS>
 __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch,
                                                     Scratch sc, unsigned* queue, int inter_mode, int max_splits) {
   extern __shared__ __align__(16) char lds_raw[];
@@ -187,6 +209,12 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
   const int L = net.L, Hp = net.Hp, HpS = sc.Hp_max;
   SubLds<T> S;
   S.carve(lds_raw, Hp, NT);
+  V4<T>* lds_w = nullptr;
+  if (WLDS) {
+    lds_w = (V4<T>*)(lds_raw + ((SubLds<T>::bytes(Hp, NT) + 63) & ~(size_t)63));
+    stage_weights<T>(net, lds_w);
+    __syncthreads();
+  }
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
   const int n0 = net.n[0];
@@ -307,7 +335,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = 0.0;
         T marg = 0;
         T w[1][4];
-        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane);
+        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_w);
         double conc = 0.0, wabs = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {

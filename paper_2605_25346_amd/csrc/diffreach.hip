@@ -69,18 +69,22 @@ hipError_t ctx_alloc(dr_ctx* c, P** p, size_t bytes) {
 // ---- kernel instance selection -------------------------------------------------
 template <typename T, int NT>
 struct Inst {
-  static const void* bound() { return (const void*)&dr::k_bound_init<T, NT>; }
+  static const void* bound() { return (const void*)&dr::k_bound_init<T, NT, false>; }
+  static const void* bound_lds() {
+    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, true>;
+    return nullptr;
+  }
   static const void* final_() { return (const void*)&dr::k_final<T, NT, false>; }
   static const void* dual() { return (const void*)&dr::k_final<T, NT, true>; }
   static const void* reach() { return (const void*)&dr::k_reach_dt<T, NT>; }
 };
 
 template <typename T>
-const void* kernel_of(int kind, int NT) {
+const void* kernel_of(int kind, int NT, bool wlds) {
 #define DR_CASE(N)                                  \
   case N:                                           \
     switch (kind) {                                 \
-      case Q_BOUND: return Inst<T, N>::bound();     \
+      case Q_BOUND: return wlds ? Inst<T, N>::bound_lds() : Inst<T, N>::bound(); \
       case Q_FINAL: return Inst<T, N>::final_();    \
       case Q_DUAL: return Inst<T, N>::dual();       \
       default: return Inst<T, N>::reach();          \
@@ -92,26 +96,38 @@ const void* kernel_of(int kind, int NT) {
 #undef DR_CASE
 }
 
-const void* kernel_for(const dr_ctx* c, int kind, int NT) {
-  return c->prec == DR_PREC_F64 ? kernel_of<double>(kind, NT) : kernel_of<float>(kind, NT);
+const void* kernel_for(const dr_ctx* c, int kind, int NT, bool wlds = false) {
+  return c->prec == DR_PREC_F64 ? kernel_of<double>(kind, NT, wlds) : kernel_of<float>(kind, NT, wlds);
+}
+
+// Small networks keep their forward-swizzled weights in LDS inside k_bound_init.
+constexpr size_t kLdsWeightBudget = 48 * 1024;
+size_t lds_weight_bytes(const dr_ctx* c, const dr::NetDev& n) {
+  const size_t v4 = c->prec == DR_PREC_F64 ? 32 : 16;
+  return (size_t)dr::lds_w_count(n.L, n.NT) * v4;
+}
+bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
+  return n.NT <= 4 && lds_weight_bytes(c, n) <= kLdsWeightBudget;
 }
 
 size_t reach_extra_lds() { return 64 + 16 + 640 * sizeof(double); }
 
 size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
-  if (kind == Q_BOUND) return b;
+  if (kind == Q_BOUND) return use_lds_weights(c, n) ? ((b + 63) & ~(size_t)63) + lds_weight_bytes(c, n) : b;
   if (kind == Q_REACH) return b + reach_extra_lds();
   return 0;
 }
 
 // Launch shape of a persistent kernel: workgroups per CU from the occupancy
-// calculator, optionally capped by the tile configuration (autotuner id:
-// tile_cfg = 1 + (wgs_per_cu - 1), 0 = as many as fit).
-int persistent_grid(dr_ctx* c, const void* fn, size_t lds) {
+// calculator, optionally capped by the launch configuration chosen by the autotuner:
+// tile_cfg holds one 4-bit cap per kernel kind (bits 4*kind .. 4*kind+3; 0 = as many
+// workgroups per CU as fit).
+int persistent_grid(dr_ctx* c, const void* fn, size_t lds, int kind) {
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWG, lds) != hipSuccess || nb < 1) nb = 1;
-  if (c->tile_cfg > 0) nb = std::min(nb, c->tile_cfg);
+  const int cap = (c->tile_cfg >> (4 * kind)) & 15;
+  if (cap > 0) nb = std::min(nb, cap);
   return std::max(1, nb * c->cus);
 }
 
@@ -303,7 +319,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   for (int i = 0; i < n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     for (int kind = 0; kind < Q_KINDS; ++kind) {
-      const void* fn = kernel_for(c, kind, nd.NT);
+      const void* fn = kernel_for(c, kind, nd.NT, kind == Q_BOUND && use_lds_weights(c, nd));
       if (!fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
       const size_t lds = lds_bytes(c, kind, nd);
       if (lds > 0) {
@@ -311,7 +327,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
         if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
       }
       c->lds[kind][i] = lds;
-      c->grid[kind][i] = persistent_grid(c, fn, lds);
+      c->grid[kind][i] = persistent_grid(c, fn, lds, kind);
     }
     const size_t waves = (size_t)c->grid[Q_DUAL][i] * dr::kWavesPerWG;
     tape_bytes = std::max(tape_bytes, waves * (size_t)(nd.L - 1) * nd.NT * 256 * tsz);
@@ -340,7 +356,7 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
   if (e != hipSuccess) return hip_fail(c, e, "order kernel");
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
-    const void* fn = kernel_for(c, Q_BOUND, nd.NT);
+    const void* fn = kernel_for(c, Q_BOUND, nd.NT, use_lds_weights(c, nd));
     int net_index = i, inter = c->inter, ms = c->max_splits;
     dr::BatchDev bd = c->batch;
     dr::Scratch sc = c->sc;

@@ -167,10 +167,11 @@ template <typename P> __device__ __forceinline__ P uniform_ptr(P p) {
   return (P)(((uint64_t)hi << 32) | lo);
 }
 
-template <typename T, int MT, int KT>
-__device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw_, const T (&cur)[KT][4],
-                                           T (&nxt)[MT][4], int lane) {
-  gconst<V4<T>> Wsw = as_global(uniform_ptr(Wsw_));
+template <typename T> using lconst = const T __attribute__((address_space(3)))*;
+
+// P: gconst<V4<T>> (swizzled weights in global memory) or lconst<V4<T>> (an LDS copy).
+template <typename T, int MT, int KT, typename P>
+__device__ __forceinline__ void gemm_tiles_p(P Wsw, const T (&cur)[KT][4], T (&nxt)[MT][4], int lane) {
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     V4<T> acc = {0, 0, 0, 0};
@@ -187,5 +188,18 @@ __device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw_, const
     __builtin_amdgcn_sched_barrier(0);
   }
 }
+
+template <typename T, int MT, int KT>
+__device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw_, const T (&cur)[KT][4],
+                                           T (&nxt)[MT][4], int lane) {
+  gemm_tiles_p<T, MT, KT>(as_global(uniform_ptr(Wsw_)), cur, nxt, lane);
+}
+
+// Forward-swizzled weights of hidden-side layers 1..L-1 staged in LDS (small networks):
+// V4 offset of layer k (1-based) inside the staged block.
+__host__ __device__ inline int lds_w_offset(int k, int NT) {
+  return k <= 1 ? 0 : NT * 64 + (k - 2) * NT * NT * 64;
+}
+__host__ __device__ inline int lds_w_count(int L, int NT) { return lds_w_offset(L, NT); }
 
 }  // namespace dr
