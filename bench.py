@@ -31,6 +31,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain
+# copy of known size (see profiles/); valid only for the kernel sources they were taken with.
+TRAFFIC = {"src_sha": "be24bd1bfc4fda98", "k_bound_init_bytes": 2.39e6 + 28.72e6}
+
+
+def kernel_src_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("bound_kernels.hip", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_25346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
 PEAK_HBM_GBS = 8000.0
 
@@ -212,6 +224,7 @@ def mixed_batch(torch, args, precision="f32"):
     S = wl.batch.n_sub
     ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=32)
     db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
     alpha, beta = ctx.new_duals()
     q, n0 = ctx.q, ctx.n0
     f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
@@ -365,30 +378,37 @@ def main():
         return
     print("bench: headline workload", file=sys.stderr, flush=True)
     hl, wl = headline(torch, args, "f32")
+    print(f"bench: headline {hl}", file=sys.stderr, flush=True)
     extra = {}
     if not args.no_extra:
         print("bench: f64 headline", file=sys.stderr, flush=True)
         h64, _ = headline(torch, args, "f64")
+        print(f"bench: f64 headline {h64}", file=sys.stderr, flush=True)
         extra["crown_6-64x3-3_S4096_f64"] = dict(
             subdomains_per_s=h64["S"] / (h64["ms"] * 1e-3), ms_per_step=h64["ms"],
             roofline=dict(bound="mfma", achieved=h64["achieved"], peak=PEAK_TFLOPS["f64"], unit="TFLOP/s",
                           frac=h64["achieved"] / PEAK_TFLOPS["f64"]))
         print("bench: dual ascent", file=sys.stderr, flush=True)
         da = dual_ascent(torch, args, "f32")
+        print(f"bench: dual ascent {da}", file=sys.stderr, flush=True)
         extra["abcrown_8-128x4-4_S2048_20it"] = dict(
             subdomain_iters_per_s=da["subdomain_iters_per_s"], ms_per_call=da["ms"],
             roofline=dict(bound="mfma", achieved=da["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=da["tflops"] / PEAK_TFLOPS["f32"]))
         print("bench: TM reach", file=sys.stderr, flush=True)
         tr = tm_reach(torch, args, "f32")
+        print(f"bench: TM reach {tr}", file=sys.stderr, flush=True)
         extra["tmreach_12-256x3-4_S8192_H10"] = dict(
             box_steps_per_s=tr["box_steps_per_s"], ms_per_call=tr["ms"],
             roofline=dict(bound="mfma", achieved=tr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=tr["tflops"] / PEAK_TFLOPS["f32"]))
         print("bench: equal tightness", file=sys.stderr, flush=True)
         extra["equal_tightness_abcrown_vs_crown_input_splitting"] = equal_tightness(torch, args, "f32")
+        print(f"bench: equal tightness {extra['equal_tightness_abcrown_vs_crown_input_splitting']}", file=sys.stderr,
+              flush=True)
         print("bench: mixed batch", file=sys.stderr, flush=True)
         mb = mixed_batch(torch, args, "f32")
+        print(f"bench: mixed batch {mb}", file=sys.stderr, flush=True)
         extra["mixed_S16384_crown+10it"] = dict(subdomains_per_s=mb["subdomains_per_s"], ms_per_step=mb["ms"])
     print("bench: cpu baseline", file=sys.stderr, flush=True)
     cb = cpu_baseline(wl, args.cpu_budget)
@@ -411,7 +431,8 @@ def main():
                    "chain_precision": "f32", "concretize": "f64", "margins": "rigorous",
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": hl["achieved"], "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
-                     "frac": hl["achieved"] / PEAK_TFLOPS["f32"], "traffic": None,
+                     "frac": hl["achieved"] / PEAK_TFLOPS["f32"],
+                     "traffic": TRAFFIC["k_bound_init_bytes"] if kernel_src_sha() == TRAFFIC["src_sha"] else None,
                      "kernel": "k_bound_init", "kernel_ms": hl["bi_ms"], "flops_per_launch": hl["flops_bi"]},
         "cpu_baseline": cb,
         "extra": extra,
