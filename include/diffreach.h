@@ -92,7 +92,8 @@ typedef struct {
 
 typedef struct {
   int n_sub;                  /* number of subdomains S */
-  const int* net_id;          /* device S (index into the networks of dr_create), or NULL = all 0 */
+  const int* net_id;          /* device S (index into the networks of dr_create), or NULL = all 0;
+                                 ignored when the context has a single network */
   const double* x_center;     /* device S x n_0 */
   const double* x_radius;     /* device S x n_0, >= 0 */
   const int* split_ptr;       /* device S + 1 CSR offsets, or NULL = no splits */
@@ -109,6 +110,9 @@ typedef struct {
                                  reach_dt; 0 = as many as fit), as chosen by the autotuner */
   int margin_mode;            /* DR_MARGIN_RIGOROUS (default) or DR_MARGIN_OFF (diagnostics only:
                                  rounding of the chains is then not covered, bounds may be unsound) */
+  int fuse_spec;              /* 1: dr_bound_init also runs the plain-CROWN spec rows while each
+                                 subdomain's relaxation is on chip, and dr_propagate_backward only
+                                 lays them out; 0: dr_propagate_backward runs the spec chains */
 } dr_options;
 
 /* Create a context for one or more networks sharing n_0 and the spec length.

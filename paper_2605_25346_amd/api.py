@@ -58,7 +58,7 @@ class BoundContext:
 
     def __init__(self, nets: Sequence[Network], *, precision="f32", max_sub=1, max_splits=0,
                  intermediate="crown_ibp", tile_cfg=0, spec: Optional[np.ndarray] = None, device="cuda",
-                 margins=True):
+                 margins=True, fuse_spec=True):
         self.lib = B.load()
         self.device = torch.device(device)
         self.precision = precision
@@ -99,6 +99,7 @@ class BoundContext:
             tile_cfg = lookup(nets, precision)
         opt.tile_cfg = int(tile_cfg)
         opt.margin_mode = B.DR_MARGIN_RIGOROUS if margins else B.DR_MARGIN_OFF
+        opt.fuse_spec = 1 if fuse_spec else 0
         ctx = ctypes.c_void_p()
         st = self.lib.dr_create(ctypes.byref(ctx), structs, len(nets), ctypes.byref(opt), _stream())
         B.check(st, None)

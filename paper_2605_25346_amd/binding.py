@@ -62,6 +62,7 @@ class dr_options(ctypes.Structure):
         ("max_splits", ctypes.c_int),
         ("tile_cfg", ctypes.c_int),
         ("margin_mode", ctypes.c_int),
+        ("fuse_spec", ctypes.c_int),
     ]
 
 

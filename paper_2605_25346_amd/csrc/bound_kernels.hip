@@ -56,19 +56,19 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
   return r;
 }
 
-// Relaxation of one layer applied to g (over h_k) in registers, giving the row
-// multipliers a' over z_k.  Offsets and margin accumulate per lane.
-template <typename T, int NT, bool SHARED, typename RelPtr>
-__device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4], RelPtr rel,
-                                            const T* __restrict__ bias_, int gq, double& acc, double& acc2,
-                                            T& marg) {
+// Relaxation of one layer applied in place to the chain state st: the multipliers g
+// over h_k become the row multipliers a' over z_k.  Offsets and margin accumulate
+// per lane.
+template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage>
+__device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, const T* __restrict__ bias_, int gq,
+                                            double& acc, double& acc2, T& marg) {
   gconst<T> bias = as_global(bias_);
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       V4<T> r = rel[t * 16 + gq * 4 + i];
-      T gv = g[t][i];
+      T gv = st.get(t, i);
       T a = (gv >= (T)0 ? r[0] : r[1]) * gv;
       double bj = (double)bias[t * 16 + nrn<T>(gq, i)];
       double gt = (double)gv * (double)r[2];
@@ -79,35 +79,47 @@ __device__ __forceinline__ void relax_layer(const T (&g)[NT][4], T (&cur)[NT][4]
         acc += fmin(gt, 0.0) + (double)a * bj;
       }
       marg += (a < (T)0 ? -a : a) * r[3];
-      cur[t][i] = a;
+      st.set(t, i, a);
     }
     __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Backward chain of one N-tile from hidden layer K-1 down to the input.
-// g: multipliers over h_{K-1} (seed). On return w holds the input coefficients.
-// With lds_w != null the products read the LDS copy of the forward-swizzled weights.
-template <typename T, int NT, bool SHARED>
-__device__ __forceinline__ void chain_to_input(const NetDev& net, int K, T (&g)[NT][4], const V4<T>* rel_all,
+// st <- A st for NT x NT tiles of swizzled weights (the products finish before the
+// state is overwritten).
+template <typename T, int NT, typename P, typename Stage>
+__device__ __forceinline__ void gemm_inplace(P Wsw, Stage& st, int lane) {
+  T nxt[NT][4];
+  gemm_k<T, NT, NT>(Wsw, st, nxt, lane);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) st.set(t, i, nxt[t][i]);
+}
+
+// Backward chain of one N-tile from hidden layer K-1 down to the input.  st holds
+// the seed multipliers over h_{K-1} (in registers or in the wavefront's LDS stage,
+// see stage_in_lds); on return w holds the input coefficients.  With lds_w != null
+// the products read the LDS copy of the forward-swizzled weights.
+template <typename T, int NT, bool SHARED, typename Stage>
+__device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& st, const V4<T>* rel_all,
                                                double& acc, double& acc2, T& marg, T (&w)[1][4], int lane,
                                                const V4<T>* lds_w = nullptr) {
-  T cur[NT][4];
   const int gq = lane >> 4;
   for (int k = K - 1; k >= 1; --k) {
-    relax_layer<T, NT, SHARED>(g, cur, rel_all + (k - 1) * 16 * NT, (const T*)net.bn[k - 1], gq, acc, acc2,
-                               marg);
+    relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
     if (lds_w) {
       lconst<V4<T>> Wl = (lconst<V4<T>>)(lds_w + lds_w_offset(k, NT));
       if (k > 1)
-        gemm_tiles_p<T, NT, NT>(Wl, cur, g, lane);
+        gemm_inplace<T, NT>(Wl, st, lane);
       else
-        gemm_tiles_p<T, 1, NT>(Wl, cur, w, lane);
+        gemm_k<T, 1, NT>(Wl, st, w, lane);
     } else {
+      gconst<V4<T>> Wg = as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1]));
       if (k > 1)
-        gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
+        gemm_inplace<T, NT>(Wg, st, lane);
       else
-        gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+        gemm_k<T, 1, NT>(Wg, st, w, lane);
     }
   }
 }
@@ -136,13 +148,16 @@ struct SubLds {
   double* ibl;    // 16 NT
   double* ibu;
   double* v;
+  double* hc;     // 16 NT: centre of relu(h) of the previous layer
+  double* hr;     // 16 NT: radius
   int* U;         // 16 NT
   double* xc;     // 16
   double* xr;     // 16
   int* misc;      // 8 ints: [0] item, [1] flags, [2..5] wave counts
   __host__ __device__ static size_t bytes(int Hp, int NT) {
-    return (size_t)Hp * (sizeof(V4<T>) + 2 * sizeof(double) + sizeof(int)) +
-           (size_t)16 * NT * (3 * sizeof(double) + sizeof(int)) + 32 * sizeof(double) + 8 * sizeof(int);
+    size_t b = (size_t)Hp * (sizeof(V4<T>) + 2 * sizeof(double) + sizeof(int)) +
+               (size_t)16 * NT * (5 * sizeof(double) + sizeof(int)) + 32 * sizeof(double) + 8 * sizeof(int);
+    return (b + 63) & ~(size_t)63;
   }
   __device__ void carve(char* base, int Hp, int NT) {
     rel = (V4<T>*)base; base += (size_t)Hp * sizeof(V4<T>);
@@ -151,6 +166,8 @@ struct SubLds {
     ibl = (double*)base; base += (size_t)16 * NT * sizeof(double);
     ibu = (double*)base; base += (size_t)16 * NT * sizeof(double);
     v = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    hc = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    hr = (double*)base; base += (size_t)16 * NT * sizeof(double);
     xc = (double*)base; base += 16 * sizeof(double);
     xr = (double*)base; base += 16 * sizeof(double);
     slot = (int*)base; base += (size_t)Hp * sizeof(int);
@@ -159,126 +176,191 @@ struct SubLds {
   }
 };
 
-// Compact the flagged neurons of one layer (one thread per neuron, 16 NT <= 256).
-__device__ __forceinline__ int compact_flags(bool flag, int j, int* U, int* wcnt) {
-  const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
-  unsigned long long m = __ballot(flag);
-  int pre = __popcll(m & ((1ull << lane) - 1ull));
-  if (lane == 0) wcnt[wid] = __popcll(m);
-  __syncthreads();
-  int base = 0, tot = 0;
-  for (int w = 0; w < kWavesPerWG; ++w) {
-    if (w < wid) base += wcnt[w];
-    tot += wcnt[w];
+// Synchronisation of the threads that share one subdomain: the whole workgroup
+// (TPS = 256) or one wavefront (TPS = 64, where LDS operations of the wave are
+// processed in order and only compiler reordering must be prevented).
+template <int TPS> __device__ __forceinline__ void sub_sync() {
+  if (TPS == 64) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __syncthreads();
   }
-  if (flag) U[base + pre] = j;
-  __syncthreads();
-  return tot;
 }
 
-// Interval (IBP) bound of hidden layer k from the final bounds of layer k-1, with
-// v = |W_k| relu(u_{k-1}) for the margin coefficients; FP64 with outward rounding.
+// Compact the flagged neurons j < n (flag(j) evaluated by the caller's lambda) into
+// U; returns the count.  TPS threads take 16 NT neurons in chunks of TPS.
+template <int TPS, typename F>
+__device__ __forceinline__ int compact_flags(int n16, F flag_of, int* U, int* wcnt) {
+  const int t = threadIdx.x & (TPS - 1), lane = threadIdx.x & 63;
+  int total = 0;
+  for (int c0 = 0; c0 < n16; c0 += TPS) {
+    const int j = c0 + t;
+    const bool flag = j < n16 && flag_of(j);
+    unsigned long long m = __ballot(flag);
+    int pre = __popcll(m & ((1ull << lane) - 1ull));
+    if (TPS == 64) {
+      if (flag) U[total + pre] = j;
+      total += __popcll(m);
+    } else {
+      const int wid = t >> 6;
+      if (lane == 0) wcnt[wid] = __popcll(m);
+      __syncthreads();
+      int base = total, tot = 0;
+      for (int w = 0; w < TPS / 64; ++w) {
+        if (w < wid) base += wcnt[w];
+        tot += wcnt[w];
+      }
+      if (flag) U[base + pre] = j;
+      total += tot;
+      __syncthreads();
+    }
+  }
+  sub_sync<TPS>();
+  return total;
+}
+
+// Interval (IBP) bound of neuron j of hidden layer k from the centre/radius of
+// relu(h_{k-1}) (hc, hr, zero-padded to np_{k-1}), with v = |W_k| relu(u_{k-1}) for the
+// margin coefficients; FP64 with outward rounding.  Four partial sums, vector loads.
 template <typename T>
-__device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, const double* l_prev,
-                                           const double* u_prev, double& lo, double& hi, double& v) {
+__device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, const double* hc, const double* hr,
+                                           double& lo, double& hi, double& v) {
   const int npk = net.np[k - 1];
-  const T* W = (const T*)net.Wn[k - 1] + (size_t)j * npk;
-  double zc = (double)((const T*)net.bn[k - 1])[j], zr = 0.0, za = 0.0;
-  for (int m = 0; m < net.n[k - 1]; ++m) {
-    double hl = fmax(l_prev[m], 0.0), hu = fmax(u_prev[m], 0.0);
-    double c = 0.5 * (hl + hu), r = 0.5 * (hu - hl);
-    double w = (double)W[m];
-    zc += w * c;
-    zr += fabs(w) * r;
-    za += fabs(w) * c;
+  gconst<V4<T>> W = as_global((const V4<T>*)((const T*)net.Wn[k - 1] + (size_t)j * npk));
+  double zc[4] = {0, 0, 0, 0}, zr[4] = {0, 0, 0, 0}, za[4] = {0, 0, 0, 0};
+  for (int m4 = 0; m4 < npk / 4; ++m4) {
+    V4<T> w4 = W[m4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double w = (double)w4[i], c = hc[m4 * 4 + i], r = hr[m4 * 4 + i];
+      zc[i] += w * c;
+      zr[i] += fabs(w) * r;
+      za[i] += fabs(w) * c;
+    }
   }
-  double e = 0x1p-44 * (za + zr + fabs(zc));
-  lo = zc - zr - e;
-  hi = zc + zr + e;
-  v = za + zr;
+  const double zcs = (double)((const T*)net.bn[k - 1])[j] + ((zc[0] + zc[1]) + (zc[2] + zc[3]));
+  const double zrs = (zr[0] + zr[1]) + (zr[2] + zr[3]);
+  const double zas = (za[0] + za[1]) + (za[2] + za[3]);
+  double e = 0x1p-44 * (zas + zrs + fabs(zcs));
+  lo = zcs - zrs - e;
+  hi = zcs + zrs + e;
+  v = zas + zrs;
+}
+
+// relu(h) centre/radius of hidden layer k (for the next layer's IBP), zero-padded.
+template <int TPS>
+__device__ __forceinline__ void relu_box(const double* l, const double* u, int n16, double* hc, double* hr) {
+  const int t = threadIdx.x & (TPS - 1);
+  for (int m = t; m < n16; m += TPS) {
+    const double a = fmax(l[m], 0.0), b = fmax(u[m], 0.0);
+    hc[m] = 0.5 * (a + b);
+    hr[m] = 0.5 * (b - a);
+  }
 }
 
 // ---------------------------------------------------------------------------
-// a1-a4: intermediate bounds, one workgroup per subdomain, persistent.
+// a1-a4: intermediate bounds, persistent.  TPS threads own one subdomain at a time:
+// a whole workgroup (TPS = 256, wide networks: the chain tiles of a layer are spread
+// over its four waves) or one wavefront (TPS = 64, narrow networks: four subdomains
+// per workgroup progress independently, no workgroup barriers).
 // ---------------------------------------------------------------------------
-template <typename T, int NT, bool WLDS>
+template <typename T, int NT, bool WLDS, int TPS>
 __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch,
                                                     Scratch sc, unsigned* queue, int inter_mode, int max_splits) {
   extern __shared__ __align__(16) char lds_raw[];
   const NetDev& net = nets[net_index];
   const int L = net.L, Hp = net.Hp, HpS = sc.Hp_max;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int t = tid & (TPS - 1);                       // thread index within the subdomain's team
+  const int n_team_waves = TPS / 64;
+  const int wave_in_team = (TPS == 64) ? 0 : wid;
+  const size_t sub_bytes = SubLds<T>::bytes(Hp, NT);
+  // dynamic LDS: per-wave chain stages, then the subdomain state(s), then staged weights
+  char* stage = lds_raw + (size_t)wid * stage_bytes<T, NT>();
+  char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
   SubLds<T> S;
-  S.carve(lds_raw, Hp, NT);
+  S.carve(lds_base + (TPS == 64 ? (size_t)wid * sub_bytes : 0), Hp, NT);
   V4<T>* lds_w = nullptr;
   if (WLDS) {
-    lds_w = (V4<T>*)(lds_raw + ((SubLds<T>::bytes(Hp, NT) + 63) & ~(size_t)63));
+    lds_w = (V4<T>*)(lds_base + (TPS == 64 ? kWavesPerWG : 1) * sub_bytes);
     stage_weights<T>(net, lds_w);
     __syncthreads();
   }
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0];
+  const int n16 = 16 * NT;
 
   for (;;) {
-    if (tid == 0) S.misc[0] = (int)atomicAdd(queue, 1u);
-    __syncthreads();
-    const int item = S.misc[0];
-    __syncthreads();
+    int item;
+    if (TPS == 64) {
+      item = wave_fetch(queue);
+    } else {
+      if (tid == 0) S.misc[0] = (int)atomicAdd(queue, 1u);
+      __syncthreads();
+      item = S.misc[0];
+      __syncthreads();
+    }
     if (item >= cnt) break;
-    const int s = sc.order[off + item];
+    const int s = subdomain_of(sc, net_index, item);
 
     // ---- a1 ingest: box, splits
-    if (tid < 16) {
-      S.xc[tid] = tid < n0 ? batch.xc[(size_t)s * n0 + tid] : 0.0;
-      S.xr[tid] = tid < n0 ? batch.xr[(size_t)s * n0 + tid] : 0.0;
+    if (t < 16) {
+      S.xc[t] = t < n0 ? batch.xc[(size_t)s * n0 + t] : 0.0;
+      S.xr[t] = t < n0 ? batch.xr[(size_t)s * n0 + t] : 0.0;
     }
-    for (int p = tid; p < Hp; p += kWG) {
+    for (int p = t; p < Hp; p += TPS) {
       S.slot[p] = -1;
       S.l[p] = 0.0;
       S.u[p] = 0.0;
     }
-    if (tid == 0) S.misc[1] = 0;
-    if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
-    __syncthreads();
-    if (tid < n0) {
-      double c = S.xc[tid], r = S.xr[tid];
+    if (t == 0) S.misc[1] = 0;
+    if (t < 8) sc.rows[(size_t)s * 8 + t] = 0;
+    sub_sync<TPS>();
+    if (t < n0) {
+      double c = S.xc[t], r = S.xr[t];
       if (!(fabs(c) < INFINITY) || !(r < INFINITY) || !(r >= 0.0)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
     }
     if (batch.sptr) {
       int a = batch.sptr[s], b = batch.sptr[s + 1];
       if (b - a > max_splits || b < a) {
-        if (tid == 0) atomicOr(&S.misc[1], DR_RES_BADSPLIT);
+        if (t == 0) atomicOr(&S.misc[1], DR_RES_BADSPLIT);
       } else {
-        for (int e = a + tid; e < b; e += kWG) {
+        for (int e = a + t; e < b; e += TPS) {
           uint32_t wd = batch.spk[e];
           int k = (int)(wd >> 24), j = (int)(wd & 0xFFFFu), pos = (int)((wd >> 16) & 1u);
           if (k < 1 || k > L - 1 || j >= net.n[k]) {
             atomicOr(&S.misc[1], DR_RES_BADSPLIT);
           } else {
-            int p = (k - 1) * 16 * NT + (j & ~15) + pos_of<T>(j & 15);
+            int p = (k - 1) * n16 + (j & ~15) + pos_of<T>(j & 15);
             S.slot[p] = ((e - a) << 1) | pos;
           }
         }
       }
     }
-    __syncthreads();
+    sub_sync<TPS>();
 
     // ---- a2 layer 1: exact bounds of an affine map over the box
     {
       const int n1 = net.n[1];
-      for (int j = tid; j < 16 * NT; j += kWG) {
+      for (int j = t; j < n16; j += TPS) {
         const int p = (j & ~15) + pos_of<T>(j & 15);
         double lo = 0.0, hi = 0.0, v = 0.0, bj = 0.0;
         bool split = S.slot[p] >= 0;
         if (j < n1) {
-          const T* W = (const T*)net.Wn[0] + (size_t)j * net.np[0];
+          gconst<V4<T>> W = as_global((const V4<T>*)((const T*)net.Wn[0] + (size_t)j * net.np[0]));
           bj = (double)((const T*)net.bn[0])[j];
           double zc = bj, zr = 0.0, za = 0.0;
-          for (int m = 0; m < n0; ++m) {
-            double w = (double)W[m];
-            zc += w * S.xc[m];
-            zr += fabs(w) * S.xr[m];
-            za += fabs(w) * fabs(S.xc[m]);
+#pragma unroll
+          for (int m4 = 0; m4 < 4; ++m4) {
+            V4<T> w4 = W[m4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double w = (double)w4[i];
+              zc += w * S.xc[m4 * 4 + i];
+              zr += fabs(w) * S.xr[m4 * 4 + i];
+              za += fabs(w) * fabs(S.xc[m4 * 4 + i]);
+            }
           }
           double e = 0x1p-44 * (za + zr + fabs(zc));
           lo = zc - zr - e;
@@ -295,42 +377,43 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         S.rel[p] = build_relax<T>(lo, hi, v, bj, split, n1, false, sc.margin_on);
       }
     }
-    __syncthreads();
+    sub_sync<TPS>();
 
     // ---- a3/a4 deeper hidden layers
     for (int k = 2; k <= L - 1; ++k) {
       if (S.misc[1] & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT)) break;
       const int nk = net.n[k];
-      const int base = (k - 1) * 16 * NT, pbase = (k - 2) * 16 * NT;
-      bool flag = false;
-      {
-        const int j = tid;
-        if (j < 16 * NT) {
-          double lo = 0.0, hi = 0.0, v = 0.0;
-          if (j < nk) ibp_neuron<T>(net, k, j, S.l + pbase, S.u + pbase, lo, hi, v);
-          S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
-          S.l[base + j] = lo; S.u[base + j] = hi;
-          const int p = base + (j & ~15) + pos_of<T>(j & 15);
-          flag = (j < nk) && lo < 0.0 && hi > 0.0 && S.slot[p] < 0 && inter_mode == DR_INTER_CROWN_IBP;
-        }
+      const int base = (k - 1) * n16, pbase = (k - 2) * n16;
+      relu_box<TPS>(S.l + pbase, S.u + pbase, n16, S.hc, S.hr);
+      sub_sync<TPS>();
+      for (int j = t; j < n16; j += TPS) {
+        double lo = 0.0, hi = 0.0, v = 0.0;
+        if (j < nk) ibp_neuron<T>(net, k, j, S.hc, S.hr, lo, hi, v);
+        S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
+        S.l[base + j] = lo; S.u[base + j] = hi;
       }
-      const int nU = compact_flags(flag, tid, S.U, S.misc + 2);
+      sub_sync<TPS>();
+      auto unstable = [&](int j) {
+        const int p = base + (j & ~15) + pos_of<T>(j & 15);
+        return j < nk && S.ibl[j] < 0.0 && S.ibu[j] > 0.0 && S.slot[p] < 0 && inter_mode == DR_INTER_CROWN_IBP;
+      };
+      const int nU = compact_flags<TPS>(n16, unstable, S.U, S.misc + 2);
       const int nrows = 2 * nU;
       const int ntiles = (nrows + 15) >> 4;
-      for (int tile = wid; tile < ntiles; tile += kWavesPerWG) {
+      for (int tile = wave_in_team; tile < ntiles; tile += n_team_waves) {
         const int row = tile * 16 + (lane & 15);
         const bool valid = row < nrows;
         const int neuron = valid ? S.U[row >> 1] : 0;
         const T sgn = (row & 1) ? (T)-1 : (T)1;
-        T g[NT][4];
+        auto g = make_stage<T, NT>(stage, lane);
         const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
         const int gq = lane >> 4;
         const T sg = valid ? sgn : (T)0;
         gconst<T> Wr = as_global(Wrow);
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) g[t][i] = sg * Wr[t * 16 + nrn<T>(gq, i)];
+          for (int i = 0; i < 4; ++i) g.set(tt, i, sg * Wr[tt * 16 + nrn<T>(gq, i)]);
         // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
         double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = 0.0;
         T marg = 0;
@@ -354,46 +437,101 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
           else S.l[base + neuron] = fmax(S.ibl[neuron], lb);
         }
       }
-      __syncthreads();
-      {
-        const int j = tid;
-        if (j < 16 * NT) {
-          const int p = base + (j & ~15) + pos_of<T>(j & 15);
-          double lo = S.l[base + j], hi = S.u[base + j];
-          bool split = S.slot[p] >= 0;
-          double bj = 0.0;
-          if (j < nk) {
-            bj = (double)((const T*)net.bn[k - 1])[j];
-            if (split) {
-              if (S.slot[p] & 1) lo = fmax(lo, 0.0); else hi = fmin(hi, 0.0);
-            }
-            if (lo > hi) atomicOr(&S.misc[1], DR_RES_INFEASIBLE);
-            if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
-            S.l[base + j] = lo;
-            S.u[base + j] = hi;
+      sub_sync<TPS>();
+      for (int j = t; j < n16; j += TPS) {
+        const int p = base + (j & ~15) + pos_of<T>(j & 15);
+        double lo = S.l[base + j], hi = S.u[base + j];
+        bool split = S.slot[p] >= 0;
+        double bj = 0.0;
+        if (j < nk) {
+          bj = (double)((const T*)net.bn[k - 1])[j];
+          if (split) {
+            if (S.slot[p] & 1) lo = fmax(lo, 0.0); else hi = fmin(hi, 0.0);
           }
-          S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, split, nk, false, sc.margin_on);
+          if (lo > hi) atomicOr(&S.misc[1], DR_RES_INFEASIBLE);
+          if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+          S.l[base + j] = lo;
+          S.u[base + j] = hi;
         }
-        if (tid == 0) sc.rows[(size_t)s * 8 + (k - 1)] = nrows;
+        S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, split, nk, false, sc.margin_on);
       }
-      __syncthreads();
+      if (t == 0) sc.rows[(size_t)s * 8 + (k - 1)] = nrows;
+      sub_sync<TPS>();
     }
+
+    // ---- a5 fused: plain-CROWN spec rows of this subdomain while its relaxation is in LDS
+    if (sc.fuse && wave_in_team == 0) {
+      const bool live = !(S.misc[1] & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT));
+      const int r = lane & 15, gq = lane >> 4;
+      const bool valid = live && r < net.R;
+      const int rr = r < net.R ? r : 0;
+      gconst<double> seed = as_global(net.seedW + (size_t)rr * net.np[L - 1]);
+      const int lbase = (L - 2) * n16;
+      auto g = make_stage<T, NT>(stage, lane);
+      T marg = 0;
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = tt * 16 + nrn<T>(gq, i);
+          const double gd = seed[m] * (valid ? 1.0 : 0.0);
+          const T gt = (T)gd;
+          g.set(tt, i, gt);
+          const double hu = fmax(S.u[lbase + m], 0.0);
+          if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          if (i == 3) __builtin_amdgcn_sched_barrier(0);
+        }
+      double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
+      T w[1][4];
+      chain_to_input<T, NT, false>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_w);
+      double wt[4], conc = 0.0, wabs = 0.0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = nrn<T>(gq, i);
+        wt[i] = (double)w[0][i] + net.skip[(size_t)rr * 16 + m];
+        conc += wt[i] * S.xc[m] - fabs(wt[i]) * S.xr[m];
+        wabs += fabs(wt[i]) * (fabs(S.xc[m]) + S.xr[m]);
+      }
+      conc = row_sum(conc);
+      wabs = row_sum(wabs);
+      const double accs = row_sum(acc);
+      const double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs);
+      if (valid) {
+        double* f = sc.fin + ((size_t)s * 16 + r) * 17;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = nrn<T>(gq, i);
+          if (m < n0) f[m] = wt[i];
+        }
+        if (gq == 0) {
+          const double ao = accs - mg;
+          f[16] = ao;
+          sc.margin[(size_t)s * 32 + r] = mg;
+          if (!(fabs(ao) < INFINITY) || !(mg < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
+          else if (mg > fmax(1.0, fabs(accs + conc - mg))) atomicOr(&S.misc[1], DR_RES_MARGIN);
+        }
+      }
+    }
+    sub_sync<TPS>();
 
     // ---- write back
     const size_t so = (size_t)s * HpS;
-    for (int p = tid; p < Hp; p += kWG) {
+    for (int p = t; p < Hp; p += TPS) {
       sc.bl[so + p] = S.l[p];
       sc.bu[so + p] = S.u[p];
       ((V4<T>*)sc.rel)[so + p] = S.rel[p];
       sc.slot[so + p] = S.slot[p];
     }
-    if (tid == 0) {
+    if (t == 0) {
       sc.st[s] = (uint32_t)S.misc[1];
+      if (sc.st_out) sc.st_out[s] = (uint32_t)S.misc[1];
       sc.rows[(size_t)s * 8 + (L - 1)] = net.R;
     }
-    __syncthreads();
+    sub_sync<TPS>();
   }
-  if (wid == 0) {
+  if (TPS == 64) {
+    wave_done(queue, gridDim.x * kWavesPerWG);
+  } else if (wid == 0) {
     // one worker per workgroup for the queue's completion counter
     wave_done(queue, gridDim.x);
   }
@@ -420,12 +558,14 @@ struct FinalArgs {
 
 template <typename T, int NT, bool DUALS>
 __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
+  extern __shared__ __align__(16) char lds_raw[];
+  char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT>();
   const NetDev& net = nets[net_index];
   const Scratch& sc = fa.sc;
   const int tid = threadIdx.x, lane = tid & 63, gq = lane >> 4, n = lane & 15;
   const int L = net.L, R = net.R, q = net.q, n0 = net.n[0];
   const int P = 16 / R;
-  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int cnt = batch_count(sc, net_index);
   const int n_items = (cnt + P - 1) / P;
   const int HpS = sc.Hp_max;
   const unsigned n_workers = gridDim.x * kWavesPerWG;
@@ -438,7 +578,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     const int sl = n / R, r = n % R;
     const int idx = item * P + sl;
     const bool inrange = (sl < P) && (idx < cnt);
-    const int s = inrange ? sc.order[off + idx] : 0;
+    const int s = inrange ? subdomain_of(sc, net_index, idx) : 0;
     const uint32_t st = inrange ? sc.st[s] : 0u;
     const bool live = inrange && !(st & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT));
     const size_t so = (size_t)s * HpS;
@@ -470,7 +610,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     for (int it = 0; it < n_eval; ++it) {
       // read the caller's duals unless they are initialised here (first iteration)
       const bool use_in = live && !(fa.init_duals && it == 0);
-      T g[NT][4];
+      auto st = make_stage<T, NT>(stage, lane);   // the chain state of this wavefront
       double acc = net.seedB[r] * ((gq == 0) ? liveD : 0.0), acc2 = 0.0;
       T marg = 0;
 #pragma unroll
@@ -480,18 +620,18 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
           const int m = t * 16 + nrn<T>(gq, i);
           double gd = seed[m] * liveD;
           T gt = (T)gd;
-          g[t][i] = gt;
+          st.set(t, i, gt);
           double hu = fmax(bu[m], 0.0) * liveD;
           if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          if (i == 3) __builtin_amdgcn_sched_barrier(0);
         }
       // forward (backward bound propagation) with optional alpha/beta and tape
       T w[1][4];
       {
-        T cur[NT][4];
         for (int k = L - 1; k >= 1; --k) {
           gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
           if (!DUALS) {
-            relax_layer<T, NT, false>(g, cur, rk, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
+            relax_layer<T, NT, false>(st, rk, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
           } else {
             gconst<T> bias = as_global((const T*)net.bn[k - 1]);
             const int hoff = net.hoff[k - 1];
@@ -501,7 +641,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
               for (int i = 0; i < 4; ++i) {
                 const int c = t * 16 + nrn<T>(gq, i);
                 V4<T> rr = rk[t * 16 + gq * 4 + i];
-                T gv = g[t][i];
+                T gv = st.get(t, i);
                 tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
                 const bool uns = rr[2] > (T)0 && c < net.n[k];
                 const float aload = arow[uns ? hoff + c : 0];
@@ -514,14 +654,15 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 double bj = (double)bias[c];
                 acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
                 marg += (a < (T)0 ? -a : a) * rr[3];
-                cur[t][i] = a;
+                st.set(t, i, a);
                 if (i == 3) __builtin_amdgcn_sched_barrier(0);
               }
           }
+          gconst<V4<T>> Wg = as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1]));
           if (k > 1)
-            gemm_tiles<T, NT, NT>((const V4<T>*)net.Wf[k - 1], cur, g, lane);
+            gemm_inplace<T, NT>(Wg, st, lane);
           else
-            gemm_tiles<T, 1, NT>((const V4<T>*)net.Wf[0], cur, w, lane);
+            gemm_k<T, 1, NT>(Wg, st, w, lane);
         }
       }
       double wt[4];
@@ -575,27 +716,30 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       const bool init_now = fa.init_duals && it == 0;
       if (last && fa.galpha == nullptr && fa.gbeta == nullptr && !init_now) break;
       // ---- hand-written adjoint of lb = acc + w.xc - |w|.xr w.r.t. alpha, beta
-      T dlt[NT][4];
+      // the chain state now holds d lb / d(W_k^T a'^(k)) (without the bias term)
       {
-        T dw[1][4];
+        T dw[1][4], dlt[NT][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           double sg = wt[i] > 0.0 ? 1.0 : (wt[i] < 0.0 ? -1.0 : 0.0);
           dw[0][i] = (T)(xcv[i] - sg * xrv[i]);
         }
         gemm_tiles<T, NT, 1>((const V4<T>*)net.Wa[0], dw, dlt, lane);
+#pragma unroll
+        for (int t = 0; t < NT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st.set(t, i, dlt[t][i]);
       }
       for (int k = 1; k <= L - 1; ++k) {
         gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
         gconst<T> bias = as_global((const T*)net.bn[k - 1]);
         const int hoff = net.hoff[k - 1];
-        T e[NT][4];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = t * 16 + nrn<T>(gq, i);
-            T delta = dlt[t][i] + bias[c];          // d lb / d a'^(k)
+            T delta = st.get(t, i) + bias[c];       // d lb / d a'^(k)
             V4<T> rr = rk[t * 16 + gq * 4 + i];
             T gv = tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane];
             const bool uns = rr[2] > (T)0 && c < net.n[k];
@@ -625,10 +769,10 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
               }
             }
-            e[t][i] = delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0);
+            st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
             if (i == 3) __builtin_amdgcn_sched_barrier(0);
           }
-        if (k < L - 1) gemm_tiles<T, NT, NT>((const V4<T>*)net.Wa[k], e, dlt, lane);
+        if (k < L - 1) gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
       }
       if (last) break;
     }
@@ -677,6 +821,23 @@ __global__ void k_concretize(int S, int q, int n0, const double* __restrict__ xc
   if (status) status[s] = bits;
 }
 
+// a5 when fused into k_bound_init: lay the stored final rows out as the affine bounds.
+__global__ void k_copy_final(int S, int q, int n0, const double* __restrict__ fin, const uint32_t* __restrict__ st,
+                             double* lam_lo, double* acc_lo, double* lam_hi, double* acc_hi) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int R = 2 * q;
+  if (e >= S * R) return;
+  const int s = e / R, r = e % R;
+  const bool dead = st[s] & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT);
+  const double* f = fin + ((size_t)s * 16 + r) * 17;
+  const bool lower = r < q;
+  const int rr = lower ? r : r - q;
+  double* lam = (lower ? lam_lo : lam_hi) + ((size_t)s * q + rr) * n0;
+  for (int m = 0; m < n0; ++m) lam[m] = dead ? 0.0 : (lower ? f[m] : -f[m]);
+  if (lower) acc_lo[(size_t)s * q + rr] = dead ? INFINITY : f[16];
+  else acc_hi[(size_t)s * q + rr] = dead ? -INFINITY : -f[16];
+}
+
 // ---------------------------------------------------------------------------
 // a8: stepwise closed-loop reachability with linear TMs (one WG per box).
 // ---------------------------------------------------------------------------
@@ -695,10 +856,14 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   const NetDev& net = nets[net_index];
   const Scratch& sc = ra.sc;
   const int L = net.L, Hp = net.Hp;
+  const int wid_ = threadIdx.x >> 6;
+  // dynamic LDS: per-wave chain stages, the subdomain state, then the TM state
+  char* stage = lds_raw + (size_t)wid_ * stage_bytes<T, NT>();
+  char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
   SubLds<T> S;
-  S.carve(lds_raw, Hp, NT);
+  S.carve(lds_base, Hp, NT);
   // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
-  double* tm = (double*)(lds_raw + SubLds<T>::bytes(Hp, NT) + 64);
+  double* tm = (double*)(lds_base + SubLds<T>::bytes(Hp, NT) + 64);
   tm = (double*)(((uintptr_t)tm + 15) & ~(uintptr_t)15);
   double* c = tm;            // 16
   double* Pm = tm + 16;      // 256 (row-major n x n)
@@ -710,7 +875,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   double* nIlo = tm + 592;
   double* nIhi = tm + 608;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, gq = lane >> 4;
-  const int cnt = sc.net_cnt[net_index], off = sc.net_off[net_index];
+  const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0], ns = net.n_state, H = ra.horizon;
 
   for (;;) {
@@ -719,7 +884,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
     const int item = S.misc[0];
     __syncthreads();
     if (item >= cnt) break;
-    const int s = sc.order[off + item];
+    const int s = subdomain_of(sc, net_index, item);
     double* bx = ra.boxes + (size_t)s * (H + 1) * n0 * 2;
     // TM normalisation of the input box: c = centre, P = diag(radius), I = [0, 0]
     if (tid < 16) {
@@ -781,29 +946,31 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
       for (int k = 2; k <= L - 1; ++k) {
         const int nk = net.n[k];
         const int base = (k - 1) * 16 * NT, pbase = (k - 2) * 16 * NT;
-        bool flag = false;
+        relu_box<kWG>(S.l + pbase, S.u + pbase, 16 * NT, S.hc, S.hr);
+        __syncthreads();
         if (tid < 16 * NT) {
           const int j = tid;
           double lo = 0.0, hi = 0.0, v = 0.0;
-          if (j < nk) ibp_neuron<T>(net, k, j, S.l + pbase, S.u + pbase, lo, hi, v);
+          if (j < nk) ibp_neuron<T>(net, k, j, S.hc, S.hr, lo, hi, v);
           S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
           S.l[base + j] = lo; S.u[base + j] = hi;
-          flag = (j < nk) && lo < 0.0 && hi > 0.0;
         }
-        const int nU = compact_flags(flag, tid, S.U, S.misc + 2);
+        __syncthreads();
+        auto unstable = [&](int j) { return j < nk && S.ibl[j] < 0.0 && S.ibu[j] > 0.0; };
+        const int nU = compact_flags<kWG>(16 * NT, unstable, S.U, S.misc + 2);
         const int ntiles = (nU + 15) >> 4;
         for (int tile = wid; tile < ntiles; tile += kWavesPerWG) {
           const int row = tile * 16 + (lane & 15);
           const bool valid = row < nU;
           const int neuron = valid ? S.U[row] : 0;
-          T g[NT][4];
+          auto g = make_stage<T, NT>(stage, lane);
           const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
           const T sg = valid ? (T)1 : (T)0;
           gconst<T> Wr = as_global(Wrow);
 #pragma unroll
           for (int t = 0; t < NT; ++t)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g[t][i] = sg * Wr[t * 16 + nrn<T>(gq, i)];
+            for (int i = 0; i < 4; ++i) g.set(t, i, sg * Wr[t * 16 + nrn<T>(gq, i)]);
           double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = acc;
           T marg = 0;
           T w[1][4];
@@ -857,7 +1024,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
         const bool valid = r < ns;
         gconst<double> seed = as_global(net.seedW + (size_t)(valid ? r : 0) * net.np[L - 1]);
         const int lbase = (L - 2) * 16 * NT;
-        T g[NT][4];
+        auto g = make_stage<T, NT>(stage, lane);
         T marg = 0;
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -866,9 +1033,10 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
             const int m = t * 16 + nrn<T>(gq, i);
             double gd = seed[m] * (valid ? 1.0 : 0.0);
             T gt = (T)gd;
-            g[t][i] = gt;
+            g.set(t, i, gt);
             double hu = fmax(S.u[lbase + m], 0.0);
             if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+            if (i == 3) __builtin_amdgcn_sched_barrier(0);
           }
         double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
         T w[1][4];
@@ -926,6 +1094,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
     if (tid == 0) {
       sc.st[s] = (uint32_t)S.misc[1];
       if (ra.status) ra.status[s] = (uint32_t)S.misc[1];
+      if (sc.st_out) sc.st_out[s] = (uint32_t)S.misc[1];
     }
     __syncthreads();
   }

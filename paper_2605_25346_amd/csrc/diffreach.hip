@@ -43,6 +43,7 @@ struct dr_ctx {
   size_t lds[Q_KINDS][kMaxNets] = {};
   dr::BatchDev batch{};
   bool have_batch = false;
+  bool fused_ready = false;   // the last dr_bound_init also produced the plain spec rows
   std::string err;
 };
 
@@ -67,11 +68,16 @@ hipError_t ctx_alloc(dr_ctx* c, P** p, size_t bytes) {
 }
 
 // ---- kernel instance selection -------------------------------------------------
+// k_bound_init instances: narrow networks (NT <= 4) run one subdomain per wavefront
+// with the weights staged in LDS when they fit; wider ones one subdomain per workgroup.
 template <typename T, int NT>
 struct Inst {
-  static const void* bound() { return (const void*)&dr::k_bound_init<T, NT, false>; }
+  static const void* bound() {
+    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, false, 64>;
+    return (const void*)&dr::k_bound_init<T, NT, false, 256>;
+  }
   static const void* bound_lds() {
-    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, true>;
+    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, true, 64>;
     return nullptr;
   }
   static const void* final_() { return (const void*)&dr::k_final<T, NT, false>; }
@@ -112,11 +118,18 @@ bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
 
 size_t reach_extra_lds() { return 64 + 16 + 640 * sizeof(double); }
 
+// Dynamic LDS of a launch: one chain stage per wavefront (wide layers keep the B
+// operand of the chain products in LDS), then the kernel's own state.
 size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
+  const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
+  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT);
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
-  if (kind == Q_BOUND) return use_lds_weights(c, n) ? ((b + 63) & ~(size_t)63) + lds_weight_bytes(c, n) : b;
-  if (kind == Q_REACH) return b + reach_extra_lds();
-  return 0;
+  if (kind == Q_BOUND) {
+    const size_t teams = n.NT <= 4 ? dr::kWavesPerWG : 1;   // per-wavefront subdomains for narrow networks
+    return stages + teams * b + (use_lds_weights(c, n) ? lds_weight_bytes(c, n) : 0);
+  }
+  if (kind == Q_REACH) return stages + b + reach_extra_lds();
+  return stages;
 }
 
 // Launch shape of a persistent kernel: workgroups per CU from the occupancy
@@ -298,6 +311,8 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   dr::Scratch& sc = c->sc;
   sc.Hp_max = c->Hp_max;
   sc.margin_on = opt->margin_mode == DR_MARGIN_RIGOROUS ? 1 : 0;
+  sc.fuse = (opt->fuse_spec && c->R <= 16) ? 1 : 0;
+  sc.direct = n_nets == 1 ? 1 : 0;
   if ((e = ctx_alloc(c, &sc.bl, sizeof(double) * S * Hp)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.bu, sizeof(double) * S * Hp)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.rel, 4 * tsz * S * Hp)) != hipSuccess ||
@@ -308,6 +323,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       (e = ctx_alloc(c, &sc.order, sizeof(int) * S)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.net_cnt, sizeof(int) * kMaxNets)) != hipSuccess ||
       (e = ctx_alloc(c, &sc.net_off, sizeof(int) * kMaxNets)) != hipSuccess ||
+      (e = ctx_alloc(c, &sc.fin, sc.fuse ? sizeof(double) * S * 16 * 17 : 16)) != hipSuccess ||
       (e = ctx_alloc(c, &c->queues, sizeof(unsigned) * 2 * Q_KINDS * kMaxNets)) != hipSuccess)
     return bail(hip_fail(c, e, "hipMalloc scratch"));
   if ((e = hipMemsetAsync(c->queues, 0, sizeof(unsigned) * 2 * Q_KINDS * kMaxNets, stream)) != hipSuccess ||
@@ -349,31 +365,41 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
   c->batch.sptr = b->split_ptr;
   c->batch.spk = b->split_packed;
   c->have_batch = true;
+  c->fused_ready = false;
+  c->sc.n_sub = b->n_sub;
   if (b->n_sub == 0) return DR_OK;
-  hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
-                     c->sc.net_cnt, c->sc.net_off, c->sc.st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  hipError_t e;
+  if (!c->sc.direct) {
+    // several networks: counting sort of the batch by network id
+    hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
+                       c->sc.net_cnt, c->sc.net_off, c->sc.st);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  }
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const void* fn = kernel_for(c, Q_BOUND, nd.NT, use_lds_weights(c, nd));
     int net_index = i, inter = c->inter, ms = c->max_splits;
     dr::BatchDev bd = c->batch;
     dr::Scratch sc = c->sc;
+    sc.st_out = status;
     unsigned* q = queue_of(c, Q_BOUND, i);
     void* args[] = {&c->dnet, &net_index, &bd, &sc, &q, &inter, &ms};
     if ((st = launch(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, stream)) != DR_OK) return st;
   }
-  if (status) {
+  if (status && !c->sc.direct) {
+    // subdomains with an invalid network id are not processed by any launch
     e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * b->n_sub, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return hip_fail(c, e, "status copy");
   }
+  c->fused_ready = c->sc.fuse != 0;
   return DR_OK;
 }
 
 static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t stream) {
   fa.batch = c->batch;
   fa.sc = c->sc;
+  fa.sc.st_out = nullptr;
   fa.tape = c->tape;
   fa.H_max = c->H_max;
   fa.max_splits = std::max(c->max_splits, 1);
@@ -385,7 +411,7 @@ static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t 
     fa.queue = queue_of(c, kind, i);
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &fa};
-    dr_status st = launch(c, fn, c->grid[kind][i], 0, args, stream);
+    dr_status st = launch(c, fn, c->grid[kind][i], c->lds[kind][i], args, stream);
     if (st != DR_OK) return st;
   }
   return DR_OK;
@@ -398,6 +424,14 @@ dr_status dr_propagate_backward(dr_ctx* c, double* lam_lo, double* acc_lo, doubl
   if (c->batch.n_sub == 0) return DR_OK;
   if (!lam_lo || !acc_lo || !lam_hi || !acc_hi) return fail(c, DR_EINVAL, "output pointer is NULL");
   if (c->R > 16) return fail(c, DR_ESHAPE, "spec rows 2q must be <= 16 for the spec chains");
+  if (c->fused_ready) {
+    const int S = c->batch.n_sub, tot = S * c->R;
+    hipLaunchKernelGGL(dr::k_copy_final, dim3((tot + 255) / 256), dim3(256), 0, stream, S, c->q, c->n0, c->sc.fin,
+                       c->sc.st, lam_lo, acc_lo, lam_hi, acc_hi);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "copy kernel");
+    return DR_OK;
+  }
   dr::FinalArgs fa{};
   fa.lam_lo = lam_lo; fa.acc_lo = acc_lo; fa.lam_hi = lam_hi; fa.acc_hi = acc_hi;
   return run_final(c, false, fa, stream);
@@ -458,16 +492,20 @@ dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, 
   c->batch.sptr = nullptr;
   c->batch.spk = nullptr;
   c->have_batch = false;  // bound_init state is not valid for this batch
+  c->fused_ready = false;
+  c->sc.n_sub = b->n_sub;
   if (b->n_sub == 0) return DR_OK;
-  hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
-                     c->sc.net_cnt, c->sc.net_off, c->sc.st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  if (!c->sc.direct) {
+    hipLaunchKernelGGL(dr::k_order, dim3(1), dim3(1024), 0, stream, b->n_sub, b->net_id, c->n_nets, c->sc.order,
+                       c->sc.net_cnt, c->sc.net_off, c->sc.st);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "order kernel");
+  }
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const void* fn = kernel_for(c, Q_REACH, nd.NT);
     dr::ReachArgs ra{};
-    ra.batch = c->batch; ra.sc = c->sc; ra.queue = queue_of(c, Q_REACH, i);
+    ra.batch = c->batch; ra.sc = c->sc; ra.sc.st_out = nullptr; ra.queue = queue_of(c, Q_REACH, i);
     ra.horizon = horizon; ra.boxes = boxes; ra.status = status;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};

@@ -105,7 +105,20 @@ struct Scratch {
   int* net_off;              // kMaxNets offsets into order
   int Hp_max;
   int margin_on;             // 1: rigorous rounding margins, 0: off (diagnostics)
+  int direct;                // 1: single network, subdomain s = work item (no sorted order)
+  int n_sub;                 // batch size of the current call
+  uint32_t* st_out;          // caller's status array (nullable), written with st
+  int fuse;                  // 1: k_bound_init also runs the plain spec rows into fin
+  double* fin;               // S x 16 x 17: per final row, input coefficients (16) and offset
 };
+
+// Work items of network `net_index` in the current batch and the subdomain of an item.
+__device__ __forceinline__ int batch_count(const Scratch& sc, int net_index) {
+  return sc.direct ? sc.n_sub : sc.net_cnt[net_index];
+}
+__device__ __forceinline__ int subdomain_of(const Scratch& sc, int net_index, int item) {
+  return sc.direct ? item : sc.order[sc.net_off[net_index] + item];
+}
 
 struct BatchDev {
   int n_sub;
@@ -168,25 +181,83 @@ template <typename P> __device__ __forceinline__ P uniform_ptr(P p) {
 }
 
 template <typename T> using lconst = const T __attribute__((address_space(3)))*;
+template <typename T> using lmut = T __attribute__((address_space(3)))*;
 
-// P: gconst<V4<T>> (swizzled weights in global memory) or lconst<V4<T>> (an LDS copy).
-template <typename T, int MT, int KT, typename P>
-__device__ __forceinline__ void gemm_tiles_p(P Wsw, const T (&cur)[KT][4], T (&nxt)[MT][4], int lane) {
+// The B operand of a chain product (the row multipliers of the current layer in the
+// lane layout described above) lives either in registers or, for wide layers, in a
+// wave-private LDS area (lane l only touches its own slots, so no synchronisation is
+// needed); the LDS form halves the registers a chain needs.
+template <typename T, int NT>
+struct RegStage {
+  T v[NT][4];
+  __device__ __forceinline__ T get(int t, int i) const { return v[t][i]; }
+  __device__ __forceinline__ void set(int t, int i, T x) { v[t][i] = x; }
+};
+template <typename T, int NT>
+struct LdsStage {
+  lmut<T> p;   // NT * 4 * 64 elements, index (t * 4 + i) * 64 + lane
+  int lane;
+  __device__ __forceinline__ T get(int t, int i) const { return p[(t * 4 + i) * 64 + lane]; }
+  __device__ __forceinline__ void set(int t, int i, T x) { p[(t * 4 + i) * 64 + lane] = x; }
+};
+// Wide chains keep the B operand in LDS (FP32 from 128 neurons, FP64 at 128 neurons;
+// FP64 at 256 would need 32 KiB per wavefront).
+__host__ __device__ constexpr bool stage_in_lds_rt(int tsz, int NT) { return tsz == 8 ? NT == 8 : NT >= 8; }
+__host__ __device__ constexpr size_t stage_bytes_rt(int tsz, int NT) {
+  return stage_in_lds_rt(tsz, NT) ? (size_t)NT * 4 * 64 * tsz : 0;
+}
+template <typename T, int NT> __host__ __device__ constexpr bool stage_in_lds() {
+  return stage_in_lds_rt((int)sizeof(T), NT);
+}
+template <typename T, int NT> __host__ __device__ constexpr size_t stage_bytes() {
+  return stage_bytes_rt((int)sizeof(T), NT);
+}
+// The stage of one wavefront; `lds` is its private area (unused for register stages).
+template <typename T, int NT> __device__ __forceinline__ auto make_stage(char* lds, int lane) {
+  if constexpr (stage_in_lds<T, NT>()) return LdsStage<T, NT>{(lmut<T>)lds, lane};
+  else return RegStage<T, NT>{};
+}
+
+// nxt[mt] = sum_kt A(mt, kt) B[kt] for MT x KT tiles, summation-tile outer: the MT
+// accumulations of one K-tile are independent (no back-to-back dependent MFMAs) and
+// the K-tile's B values are read once.  P: gconst<V4<T>> (swizzled weights in global
+// memory) or lconst<V4<T>> (an LDS copy); B: RegStage or LdsStage (or a plain array
+// through RegArr).
+template <typename T, int MT, int KT, typename P, typename B>
+__device__ __forceinline__ void gemm_k(P Wsw, const B& cur, T (&nxt)[MT][4], int lane) {
+  V4<T> acc[MT];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    V4<T> acc = {0, 0, 0, 0};
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = V4<T>{0, 0, 0, 0};
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt) {
+  for (int kt = 0; kt < KT; ++kt) {
+    const T b0 = cur.get(kt, 0), b1 = cur.get(kt, 1), b2 = cur.get(kt, 2), b3 = cur.get(kt, 3);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
       V4<T> a = Wsw[(mt * KT + kt) * 64 + lane];
-      acc = mfma16(a[0], cur[kt][0], acc);
-      acc = mfma16(a[1], cur[kt][1], acc);
-      acc = mfma16(a[2], cur[kt][2], acc);
-      acc = mfma16(a[3], cur[kt][3], acc);
+      acc[mt] = mfma16(a[0], b0, acc[mt]);
+      acc[mt] = mfma16(a[1], b1, acc[mt]);
+      acc[mt] = mfma16(a[2], b2, acc[mt]);
+      acc[mt] = mfma16(a[3], b3, acc[mt]);
     }
-    nxt[mt][0] = acc[0]; nxt[mt][1] = acc[1]; nxt[mt][2] = acc[2]; nxt[mt][3] = acc[3];
-    // keep each output tile's loads within its own tile: bounds register pressure
+    // keep the next K-tile's loads after this one's products: bounds register pressure
     __builtin_amdgcn_sched_barrier(0);
   }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    nxt[mt][0] = acc[mt][0]; nxt[mt][1] = acc[mt][1]; nxt[mt][2] = acc[mt][2]; nxt[mt][3] = acc[mt][3];
+  }
+}
+
+// A register array viewed as a stage.
+template <typename T, int NT>
+struct RegArr {
+  const T (&v)[NT][4];
+  __device__ __forceinline__ T get(int t, int i) const { return v[t][i]; }
+};
+
+template <typename T, int MT, int KT, typename P>
+__device__ __forceinline__ void gemm_tiles_p(P Wsw, const T (&cur)[KT][4], T (&nxt)[MT][4], int lane) {
+  gemm_k<T, MT, KT>(Wsw, RegArr<T, KT>{cur}, nxt, lane);
 }
 
 template <typename T, int MT, int KT>
@@ -194,6 +265,7 @@ __device__ __forceinline__ void gemm_tiles(const V4<T>* __restrict__ Wsw_, const
                                            T (&nxt)[MT][4], int lane) {
   gemm_tiles_p<T, MT, KT>(as_global(uniform_ptr(Wsw_)), cur, nxt, lane);
 }
+
 
 // Forward-swizzled weights of hidden-side layers 1..L-1 staged in LDS (small networks):
 // V4 offset of layer k (1-based) inside the staged block.

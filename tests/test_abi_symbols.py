@@ -34,7 +34,7 @@ def test_struct_layouts():
     # dr_network: int, ptr, int, ptr, ptr, ptr, ptr, int, ptr, int (LP64 natural alignment)
     assert ctypes.sizeof(binding.dr_network) == 80
     assert ctypes.sizeof(binding.dr_batch) == 48
-    assert ctypes.sizeof(binding.dr_options) == 24
+    assert ctypes.sizeof(binding.dr_options) == 28
 
 
 def test_last_error_without_context():

@@ -409,3 +409,22 @@ def test_graph_capture_replay():
         step()   # eager work between replays
         torch.cuda.synchronize()
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_fused_spec_rows_equal_separate_kernel(precision):
+    """dr_bound_init's fused spec rows (relaxation on chip) and the separate spec-chain
+    kernel compute the same affine bounds bit for bit."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(2, n_sub=300)
+    out = []
+    for fuse in (True, False):
+        ctx = BoundContext(wl.nets, precision=precision, max_sub=300, max_splits=8, fuse_spec=fuse)
+        lb, ub, st, aff = ctx.crown(DeviceBatch(wl.batch))
+        m = ctx.dr_get_margins()
+        torch.cuda.synchronize()
+        out.append([t.cpu().numpy() for t in (*aff, lb, ub, st, m)])
+        ctx.close()
+    for a, b in zip(*out):
+        np.testing.assert_array_equal(a, b)
