@@ -60,9 +60,8 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
 // over h_k become the row multipliers a' over z_k.  Offsets and margin accumulate
 // per lane.
 template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage>
-__device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, const T* __restrict__ bias_, int gq,
-                                            double& acc, double& acc2, T& marg) {
-  gconst<T> bias = as_global(bias_);
+__device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bias, int gq, double& acc,
+                                            double& acc2, T& marg) {
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
 #pragma unroll
@@ -99,15 +98,17 @@ __device__ __forceinline__ void gemm_inplace(P Wsw, Stage& st, int lane) {
 
 // Backward chain of one N-tile from hidden layer K-1 down to the input.  st holds
 // the seed multipliers over h_{K-1} (in registers or in the wavefront's LDS stage,
-// see stage_in_lds); on return w holds the input coefficients.  With lds_w != null
-// the products read the LDS copy of the forward-swizzled weights.
+// see stage_in_lds); on return w holds the input coefficients.  lds_b: the hidden
+// biases staged in LDS (layer k at (k - 1) 16 NT).  With lds_w != null the products
+// read the LDS copy of the forward-swizzled weights.
 template <typename T, int NT, bool SHARED, typename Stage>
 __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& st, const V4<T>* rel_all,
                                                double& acc, double& acc2, T& marg, T (&w)[1][4], int lane,
-                                               const V4<T>* lds_w = nullptr) {
+                                               const T* lds_b, const V4<T>* lds_w = nullptr) {
   const int gq = lane >> 4;
   for (int k = K - 1; k >= 1; --k) {
-    relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
+    relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc,
+                               acc2, marg);
     if (lds_w) {
       lconst<V4<T>> Wl = (lconst<V4<T>>)(lds_w + lds_w_offset(k, NT));
       if (k > 1)
@@ -122,6 +123,27 @@ __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& 
         gemm_k<T, 1, NT>(Wg, st, w, lane);
     }
   }
+}
+
+// Stage the hidden biases (padded, layer k at (k - 1) 16 NT) into LDS, once per workgroup.
+template <typename T>
+__device__ void stage_biases(const NetDev& net, T* dst) {
+  const int n16 = 16 * net.NT;
+  for (int e = threadIdx.x; e < net.Hp; e += kWG) {
+    const int k = e / n16;
+    dst[e] = as_global((const T*)net.bn[k])[e - k * n16];
+  }
+}
+
+// Element W_k[r][m] read from the LDS copy of the forward-swizzled weights of hidden
+// layer k >= 2 (both widths 16 NT): the inverse of the forward swizzle.
+template <typename T>
+__device__ __forceinline__ T lds_weight(const V4<T>* lds_w, int k, int NT, int r, int m) {
+  const int rr = r & 15;
+  const int g = sizeof(T) == 4 ? rr >> 2 : rr & 3;    // lane group and component holding row rr
+  const int c = sizeof(T) == 4 ? rr & 3 : rr >> 2;
+  lconst<T> W = (lconst<T>)(lds_w + lds_w_offset(k, NT));
+  return W[(((m >> 4) * NT + (r >> 4)) * 64 + g * 16 + (m & 15)) * 4 + c];
 }
 
 // Stage the forward-swizzled weights of layers 1..L-1 into LDS (once per workgroup).
@@ -276,17 +298,21 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
   const int n_team_waves = TPS / 64;
   const int wave_in_team = (TPS == 64) ? 0 : wid;
   const size_t sub_bytes = SubLds<T>::bytes(Hp, NT);
-  // dynamic LDS: per-wave chain stages, then the subdomain state(s), then staged weights
+  // dynamic LDS: per-wave chain stages, the subdomain state(s), staged weights, biases
   char* stage = lds_raw + (size_t)wid * stage_bytes<T, NT>();
   char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
   SubLds<T> S;
   S.carve(lds_base + (TPS == 64 ? (size_t)wid * sub_bytes : 0), Hp, NT);
+  char* lds_tail = lds_base + (TPS == 64 ? kWavesPerWG : 1) * sub_bytes;
   V4<T>* lds_w = nullptr;
   if (WLDS) {
-    lds_w = (V4<T>*)(lds_base + (TPS == 64 ? kWavesPerWG : 1) * sub_bytes);
+    lds_w = (V4<T>*)lds_tail;
+    lds_tail += (size_t)lds_w_count(L, NT) * sizeof(V4<T>);
     stage_weights<T>(net, lds_w);
-    __syncthreads();
   }
+  T* lds_b = (T*)lds_tail;
+  stage_biases<T>(net, lds_b);
+  __syncthreads();
   const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0];
   const int n16 = 16 * NT;
@@ -406,19 +432,25 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         const int neuron = valid ? S.U[row >> 1] : 0;
         const T sgn = (row & 1) ? (T)-1 : (T)1;
         auto g = make_stage<T, NT>(stage, lane);
-        const T* Wrow = (const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1];
         const int gq = lane >> 4;
         const T sg = valid ? sgn : (T)0;
-        gconst<T> Wr = as_global(Wrow);
+        if (WLDS) {
 #pragma unroll
-        for (int tt = 0; tt < NT; ++tt)
+          for (int tt = 0; tt < NT; ++tt)
 #pragma unroll
-          for (int i = 0; i < 4; ++i) g.set(tt, i, sg * Wr[tt * 16 + nrn<T>(gq, i)]);
+            for (int i = 0; i < 4; ++i) g.set(tt, i, sg * lds_weight<T>(lds_w, k, NT, neuron, tt * 16 + nrn<T>(gq, i)));
+        } else {
+          gconst<T> Wr = as_global((const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1]);
+#pragma unroll
+          for (int tt = 0; tt < NT; ++tt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g.set(tt, i, sg * Wr[tt * 16 + nrn<T>(gq, i)]);
+        }
         // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
-        double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = 0.0;
+        double acc = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron], acc2 = 0.0;
         T marg = 0;
         T w[1][4];
-        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_w);
+        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
         double conc = 0.0, wabs = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -444,7 +476,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         bool split = S.slot[p] >= 0;
         double bj = 0.0;
         if (j < nk) {
-          bj = (double)((const T*)net.bn[k - 1])[j];
+          bj = (double)lds_b[base + j];
           if (split) {
             if (S.slot[p] & 1) lo = fmax(lo, 0.0); else hi = fmin(hi, 0.0);
           }
@@ -483,7 +515,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         }
       double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
       T w[1][4];
-      chain_to_input<T, NT, false>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_w);
+      chain_to_input<T, NT, false>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
       double wt[4], conc = 0.0, wabs = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -559,8 +591,12 @@ struct FinalArgs {
 template <typename T, int NT, bool DUALS>
 __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
   extern __shared__ __align__(16) char lds_raw[];
+  // dynamic LDS: per-wave chain stages, then the hidden biases
   char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT>();
   const NetDev& net = nets[net_index];
+  T* lds_b = (T*)(lds_raw + kWavesPerWG * stage_bytes<T, NT>());
+  stage_biases<T>(net, lds_b);
+  __syncthreads();
   const Scratch& sc = fa.sc;
   const int tid = threadIdx.x, lane = tid & 63, gq = lane >> 4, n = lane & 15;
   const int L = net.L, R = net.R, q = net.q, n0 = net.n[0];
@@ -631,9 +667,9 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         for (int k = L - 1; k >= 1; --k) {
           gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
           if (!DUALS) {
-            relax_layer<T, NT, false>(st, rk, (const T*)net.bn[k - 1], gq, acc, acc2, marg);
+            relax_layer<T, NT, false>(st, rk, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
           } else {
-            gconst<T> bias = as_global((const T*)net.bn[k - 1]);
+            lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
             const int hoff = net.hoff[k - 1];
 #pragma unroll
             for (int t = 0; t < NT; ++t)
@@ -732,7 +768,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       }
       for (int k = 1; k <= L - 1; ++k) {
         gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
-        gconst<T> bias = as_global((const T*)net.bn[k - 1]);
+        lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
         const int hoff = net.hoff[k - 1];
 #pragma unroll
         for (int t = 0; t < NT; ++t)
@@ -862,6 +898,8 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
   SubLds<T> S;
   S.carve(lds_base, Hp, NT);
+  T* lds_b = (T*)(lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds);
+  stage_biases<T>(net, lds_b);
   // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
   double* tm = (double*)(lds_base + SubLds<T>::bytes(Hp, NT) + 64);
   tm = (double*)(((uintptr_t)tm + 15) & ~(uintptr_t)15);
@@ -971,10 +1009,10 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
           for (int t = 0; t < NT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) g.set(t, i, sg * Wr[t * 16 + nrn<T>(gq, i)]);
-          double acc = (gq == 0 ? (double)sg : 0.0) * (double)((const T*)net.bn[k - 1])[neuron], acc2 = acc;
+          double acc = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[base + neuron], acc2 = acc;
           T marg = 0;
           T w[1][4];
-          chain_to_input<T, NT, true>(net, k, g, S.rel, acc, acc2, marg, w, lane);
+          chain_to_input<T, NT, true>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b);
           // TM evaluation of w.x + [acc, acc2] over x = c + P z + r
           double base_v = 0.0, il = 0.0, ih = 0.0, wabs = 0.0;
           double wp[16];
@@ -1010,7 +1048,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
           const int p = base + (j & ~15) + pos_of<T>(j & 15);
           double lo = S.l[base + j], hi = S.u[base + j], bj = 0.0;
           if (j < nk) {
-            bj = (double)((const T*)net.bn[k - 1])[j];
+            bj = (double)lds_b[base + j];
             if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
           }
           S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, false, nk, true, sc.margin_on);
@@ -1040,7 +1078,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
           }
         double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
         T w[1][4];
-        chain_to_input<T, NT, true>(net, L, g, S.rel, acc, acc2, marg, w, lane);
+        chain_to_input<T, NT, true>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b);
         // W_r = A_r + w (FP64); new TM row: c' = W c, P' = W P, I' = W (x) I + [acc, acc2] -+ margin
         double Wr[4];
         double cpart = 0.0, il = 0.0, ih = 0.0, wabs = 0.0;

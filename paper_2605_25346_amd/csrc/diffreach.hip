@@ -116,20 +116,20 @@ bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
   return n.NT <= 4 && lds_weight_bytes(c, n) <= kLdsWeightBudget;
 }
 
-size_t reach_extra_lds() { return 64 + 16 + 640 * sizeof(double); }
 
-// Dynamic LDS of a launch: one chain stage per wavefront (wide layers keep the B
-// operand of the chain products in LDS), then the kernel's own state.
+// Dynamic LDS of a launch: one chain stage per wavefront (wide layers keep the chain
+// state in LDS), the kernel's own state, then the hidden biases.
 size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
   const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
   const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT);
+  const size_t biases = (size_t)n.Hp * tsz;
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
   if (kind == Q_BOUND) {
     const size_t teams = n.NT <= 4 ? dr::kWavesPerWG : 1;   // per-wavefront subdomains for narrow networks
-    return stages + teams * b + (use_lds_weights(c, n) ? lds_weight_bytes(c, n) : 0);
+    return stages + teams * b + (use_lds_weights(c, n) ? lds_weight_bytes(c, n) : 0) + biases;
   }
-  if (kind == Q_REACH) return stages + b + reach_extra_lds();
-  return stages;
+  if (kind == Q_REACH) return stages + b + dr::kReachExtraLds + biases;
+  return stages + biases;
 }
 
 // Launch shape of a persistent kernel: workgroups per CU from the occupancy

@@ -112,6 +112,10 @@ struct Scratch {
   double* fin;               // S x 16 x 17: per final row, input coefficients (16) and offset
 };
 
+// Extra LDS of k_reach_dt after its subdomain state: alignment slack and the Taylor
+// model state (current and next: 2 x (16 + 256 + 16 + 16) doubles, plus |x| bounds).
+constexpr size_t kReachExtraLds = 64 + 16 + 640 * sizeof(double);
+
 // Work items of network `net_index` in the current batch and the subdomain of an item.
 __device__ __forceinline__ int batch_count(const Scratch& sc, int net_index) {
   return sc.direct ? sc.n_sub : sc.net_cnt[net_index];
