@@ -80,7 +80,7 @@ __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bia
       marg += (a < (T)0 ? -a : a) * r[3];
       st.set(t, i, a);
     }
-    __builtin_amdgcn_sched_barrier(0);
+    tile_fence<T, NT>();
   }
 }
 
@@ -511,7 +511,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
           g.set(tt, i, gt);
           const double hu = fmax(S.u[lbase + m], 0.0);
           if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
-          if (i == 3) __builtin_amdgcn_sched_barrier(0);
+          if (i == 3) tile_fence<T, NT>();
         }
       double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
       T w[1][4];
@@ -592,9 +592,9 @@ template <typename T, int NT, bool DUALS>
 __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
   extern __shared__ __align__(16) char lds_raw[];
   // dynamic LDS: per-wave chain stages, then the hidden biases
-  char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT>();
+  char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT, true>();
   const NetDev& net = nets[net_index];
-  T* lds_b = (T*)(lds_raw + kWavesPerWG * stage_bytes<T, NT>());
+  T* lds_b = (T*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
   stage_biases<T>(net, lds_b);
   __syncthreads();
   const Scratch& sc = fa.sc;
@@ -646,7 +646,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     for (int it = 0; it < n_eval; ++it) {
       // read the caller's duals unless they are initialised here (first iteration)
       const bool use_in = live && !(fa.init_duals && it == 0);
-      auto st = make_stage<T, NT>(stage, lane);   // the chain state of this wavefront
+      auto st = make_stage<T, NT, true>(stage, lane);   // the chain state of this wavefront
       double acc = net.seedB[r] * ((gq == 0) ? liveD : 0.0), acc2 = 0.0;
       T marg = 0;
 #pragma unroll
@@ -659,7 +659,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
           st.set(t, i, gt);
           double hu = fmax(bu[m], 0.0) * liveD;
           if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
-          if (i == 3) __builtin_amdgcn_sched_barrier(0);
+          if (i == 3) tile_fence<T, NT>();
         }
       // forward (backward bound propagation) with optional alpha/beta and tape
       T w[1][4];
@@ -691,7 +691,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
                 marg += (a < (T)0 ? -a : a) * rr[3];
                 st.set(t, i, a);
-                if (i == 3) __builtin_amdgcn_sched_barrier(0);
+                if (i == 3) tile_fence<T, NT>();
               }
           }
           gconst<V4<T>> Wg = as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1]));
@@ -806,7 +806,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
               }
             }
             st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
-            if (i == 3) __builtin_amdgcn_sched_barrier(0);
+            if (i == 3) tile_fence<T, NT>();
           }
         if (k < L - 1) gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
       }
@@ -1074,7 +1074,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
             g.set(t, i, gt);
             double hu = fmax(S.u[lbase + m], 0.0);
             if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
-            if (i == 3) __builtin_amdgcn_sched_barrier(0);
+            if (i == 3) tile_fence<T, NT>();
           }
         double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
         T w[1][4];

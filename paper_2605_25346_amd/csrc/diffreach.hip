@@ -106,6 +106,9 @@ const void* kernel_for(const dr_ctx* c, int kind, int NT, bool wlds = false) {
   return c->prec == DR_PREC_F64 ? kernel_of<double>(kind, NT, wlds) : kernel_of<float>(kind, NT, wlds);
 }
 
+// LDS of one compute unit (gfx950).
+constexpr size_t kMaxLds = 160 * 1024;
+
 // Small networks keep their forward-swizzled weights in LDS inside k_bound_init.
 constexpr size_t kLdsWeightBudget = 48 * 1024;
 size_t lds_weight_bytes(const dr_ctx* c, const dr::NetDev& n) {
@@ -121,7 +124,8 @@ bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
 // state in LDS), the kernel's own state, then the hidden biases.
 size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
   const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
-  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT);
+  const bool roomy = kind == Q_FINAL || kind == Q_DUAL;
+  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, roomy);
   const size_t biases = (size_t)n.Hp * tsz;
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
   if (kind == Q_BOUND) {
@@ -338,6 +342,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       const void* fn = kernel_for(c, kind, nd.NT, kind == Q_BOUND && use_lds_weights(c, nd));
       if (!fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
       const size_t lds = lds_bytes(c, kind, nd);
+      if (lds > kMaxLds) return bail(fail(c, DR_ESHAPE, "network too deep for the on-chip state of its kernels"));
       if (lds > 0) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
@@ -460,10 +465,6 @@ dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, floa
   if (c->batch.n_sub == 0) return DR_OK;
   if (!alpha || !beta || !lb || !ub) return fail(c, DR_EINVAL, "alpha/beta/lb/ub is NULL");
   if (c->R > 16) return fail(c, DR_ESHAPE, "spec rows 2q must be <= 16 for the dual ascent");
-  for (int i = 0; i < c->n_nets; ++i)
-    if (c->prec == DR_PREC_F64 && c->hnet[i].NT > 8)
-      return fail(c, DR_ESHAPE,
-                  "FP64 dual ascent supports hidden widths <= 128 (wider chains do not fit the register file)");
   dr::FinalArgs fa{};
   fa.iters = iters; fa.lr = lr; fa.init_duals = init_duals ? 1 : 0;
   fa.alpha = alpha; fa.beta = beta; fa.lb = lb; fa.ub = ub; fa.galpha = grad_alpha; fa.gbeta = grad_beta;

@@ -204,22 +204,34 @@ struct LdsStage {
   __device__ __forceinline__ T get(int t, int i) const { return p[(t * 4 + i) * 64 + lane]; }
   __device__ __forceinline__ void set(int t, int i, T x) { p[(t * 4 + i) * 64 + lane] = x; }
 };
-// Wide chains keep the B operand in LDS (FP32 from 128 neurons, FP64 at 128 neurons;
-// FP64 at 256 would need 32 KiB per wavefront).
-__host__ __device__ constexpr bool stage_in_lds_rt(int tsz, int NT) { return tsz == 8 ? NT == 8 : NT >= 8; }
-__host__ __device__ constexpr size_t stage_bytes_rt(int tsz, int NT) {
-  return stage_in_lds_rt(tsz, NT) ? (size_t)NT * 4 * 64 * tsz : 0;
+// Wide chains keep their state in LDS: FP32 from 128 neurons, FP64 at 128 neurons,
+// and FP64 at 256 neurons (32 KiB per wavefront) only in kernels without per-subdomain
+// LDS state (`roomy`: the final-row and dual-ascent kernel).
+__host__ __device__ constexpr bool stage_in_lds_rt(int tsz, int NT, bool roomy) {
+  return tsz == 8 ? (NT == 8 || (roomy && NT == 16)) : NT >= 8;
 }
-template <typename T, int NT> __host__ __device__ constexpr bool stage_in_lds() {
-  return stage_in_lds_rt((int)sizeof(T), NT);
+__host__ __device__ constexpr size_t stage_bytes_rt(int tsz, int NT, bool roomy) {
+  return stage_in_lds_rt(tsz, NT, roomy) ? (size_t)NT * 4 * 64 * tsz : 0;
 }
-template <typename T, int NT> __host__ __device__ constexpr size_t stage_bytes() {
-  return stage_bytes_rt((int)sizeof(T), NT);
+template <typename T, int NT, bool ROOMY = false> __host__ __device__ constexpr bool stage_in_lds() {
+  return stage_in_lds_rt((int)sizeof(T), NT, ROOMY);
+}
+template <typename T, int NT, bool ROOMY = false> __host__ __device__ constexpr size_t stage_bytes() {
+  return stage_bytes_rt((int)sizeof(T), NT, ROOMY);
 }
 // The stage of one wavefront; `lds` is its private area (unused for register stages).
-template <typename T, int NT> __device__ __forceinline__ auto make_stage(char* lds, int lane) {
-  if constexpr (stage_in_lds<T, NT>()) return LdsStage<T, NT>{(lmut<T>)lds, lane};
+template <typename T, int NT, bool ROOMY = false> __device__ __forceinline__ auto make_stage(char* lds, int lane) {
+  if constexpr (stage_in_lds<T, NT, ROOMY>()) return LdsStage<T, NT>{(lmut<T>)lds, lane};
   else return RegStage<T, NT>{};
+}
+
+// Scheduling fence between the unrolled tiles of a chain step: the loads of the next
+// tile stay behind the current tile's arithmetic, which bounds register pressure for
+// wide layers; narrow layers (NT tiles of at most kFenceFreeBytes bytes per lane)
+// let the compiler overlap the tiles.
+constexpr int kFenceFreeBytes = 0;
+template <typename T, int NT> __device__ __forceinline__ void tile_fence() {
+  if constexpr (NT * (int)sizeof(T) > kFenceFreeBytes) __builtin_amdgcn_sched_barrier(0);
 }
 
 // nxt[mt] = sum_kt A(mt, kt) B[kt] for MT x KT tiles, summation-tile outer: the MT
@@ -243,8 +255,7 @@ __device__ __forceinline__ void gemm_k(P Wsw, const B& cur, T (&nxt)[MT][4], int
       acc[mt] = mfma16(a[2], b2, acc[mt]);
       acc[mt] = mfma16(a[3], b3, acc[mt]);
     }
-    // keep the next K-tile's loads after this one's products: bounds register pressure
-    __builtin_amdgcn_sched_barrier(0);
+    tile_fence<T, MT>();
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
