@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain
 # copy of known size (see profiles/); valid only for the kernel sources they were taken with.
-TRAFFIC = {"src_sha": "be24bd1bfc4fda98", "k_bound_init_bytes": 2.39e6 + 28.72e6}
+TRAFFIC = {"src_sha": "e45c064593b9a235", "k_bound_init_bytes": 2.30e6 + 31.67e6}
 
 
 def kernel_src_sha():
@@ -136,9 +136,10 @@ def headline(torch, args, precision="f32"):
     f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
     aff = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
     out = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+    st0 = torch.zeros(S, dtype=torch.int32, device="cuda")
 
     def step():
-        ctx.dr_bound_init(db)
+        ctx.dr_bound_init(db, status=st0)
         ctx.dr_propagate_backward(aff)
         ctx.dr_concretize(*aff, out=out)
 

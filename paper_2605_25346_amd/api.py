@@ -127,9 +127,11 @@ class BoundContext:
         B.check(st, self.ctx)
 
     # ---- entry points ---------------------------------------------------------------
-    def dr_bound_init(self, batch: DeviceBatch) -> torch.Tensor:
+    def dr_bound_init(self, batch: DeviceBatch, status=None) -> torch.Tensor:
+        """a1-a4 for the batch; returns the per-subdomain status (every entry is written)."""
         self.batch = batch
-        status = torch.zeros(max(batch.n_sub, 1), dtype=torch.int32, device=self.device)
+        if status is None:
+            status = torch.empty(max(batch.n_sub, 1), dtype=torch.int32, device=self.device)
         b = batch.struct()
         self._batch_struct = b
         self._check(self.lib.dr_bound_init(self.ctx, ctypes.byref(b), _ptr(status), _stream()))
