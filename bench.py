@@ -161,6 +161,38 @@ def headline(torch, args, precision="f32"):
     return res, wl
 
 
+def s_sweep(torch, args, mults=(1, 4, 16)):
+    """Steady-state throughput of the headline step at 1x, 4x and 16x the batch: the
+    4096 subdomains of the headline batch tiled m times (identical work per
+    subdomain), so larger launches fill the chip for more rounds."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(2)
+    S0 = wl.batch.n_sub
+    out = []
+    for m in mults:
+        batch = wl.batch.subset(np.tile(np.arange(S0), m))
+        S = batch.n_sub
+        ctx = BoundContext(wl.nets, precision="f32", max_sub=S, max_splits=8)
+        db = DeviceBatch(batch)
+        q, n0 = ctx.q, ctx.n0
+        f = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+        aff = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
+        res = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
+        st0 = torch.zeros(S, dtype=torch.int32, device="cuda")
+
+        def step():
+            ctx.dr_bound_init(db, status=st0)
+            ctx.dr_propagate_backward(aff)
+            ctx.dr_concretize(*aff, out=res)
+
+        ms, _ = time_graph(torch, step, max(5, args.steps // m), 2)
+        out.append(dict(S=S, ms_per_step=ms, subdomains_per_s=S / (ms * 1e-3)))
+        ctx.close()
+        del db, aff, res, st0
+    return out
+
+
 def dual_ascent(torch, args, precision="f32"):
     from paper_2605_25346_amd.api import BoundContext, DeviceBatch
     from paper_2605_25346_amd.workloads import config_workload
@@ -389,6 +421,10 @@ def main():
             subdomains_per_s=h64["S"] / (h64["ms"] * 1e-3), ms_per_step=h64["ms"],
             roofline=dict(bound="mfma", achieved=h64["achieved"], peak=PEAK_TFLOPS["f64"], unit="TFLOP/s",
                           frac=h64["achieved"] / PEAK_TFLOPS["f64"]))
+        print("bench: S sweep", file=sys.stderr, flush=True)
+        sw = s_sweep(torch, args)
+        print(f"bench: S sweep {sw}", file=sys.stderr, flush=True)
+        extra["crown_6-64x3-3_S_sweep_tiled_x1_x4_x16"] = sw
         print("bench: dual ascent", file=sys.stderr, flush=True)
         da = dual_ascent(torch, args, "f32")
         print(f"bench: dual ascent {da}", file=sys.stderr, flush=True)

@@ -99,9 +99,9 @@ __device__ __forceinline__ void gemm_inplace(P Wsw, Stage& st, int lane) {
 // Backward chain of one N-tile from hidden layer K-1 down to the input.  st holds
 // the seed multipliers over h_{K-1} (in registers or in the wavefront's LDS stage,
 // see stage_in_lds); on return w holds the input coefficients.  lds_b: the hidden
-// biases staged in LDS (layer k at (k - 1) 16 NT).  With lds_w != null the products
-// read the LDS copy of the forward-swizzled weights.
-template <typename T, int NT, bool SHARED, typename Stage>
+// biases staged in LDS (layer k at (k - 1) 16 NT).  With WL the products read the LDS
+// copy lds_w of the forward-swizzled weights.
+template <typename T, int NT, bool SHARED, bool WL = false, typename Stage>
 __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& st, const V4<T>* rel_all,
                                                double& acc, double& acc2, T& marg, T (&w)[1][4], int lane,
                                                const T* lds_b, const V4<T>* lds_w = nullptr) {
@@ -109,7 +109,7 @@ __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& 
   for (int k = K - 1; k >= 1; --k) {
     relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc,
                                acc2, marg);
-    if (lds_w) {
+    if constexpr (WL) {
       lconst<V4<T>> Wl = (lconst<V4<T>>)(lds_w + lds_w_offset(k, NT));
       if (k > 1)
         gemm_inplace<T, NT>(Wl, st, lane);
@@ -450,7 +450,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         double acc = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron], acc2 = 0.0;
         T marg = 0;
         T w[1][4];
-        chain_to_input<T, NT, false>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
+        chain_to_input<T, NT, false, WLDS>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
         double conc = 0.0, wabs = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
         }
       double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
       T w[1][4];
-      chain_to_input<T, NT, false>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
+      chain_to_input<T, NT, false, WLDS>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
       double wt[4], conc = 0.0, wabs = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {

@@ -239,23 +239,57 @@ template <typename T, int NT> __device__ __forceinline__ void tile_fence() {
 // the K-tile's B values are read once.  P: gconst<V4<T>> (swizzled weights in global
 // memory) or lconst<V4<T>> (an LDS copy); B: RegStage or LdsStage (or a plain array
 // through RegArr).
+// Weights read from global memory (not from an LDS copy) are software-pipelined: the
+// A tiles of K-tile kt + 1 are loaded before the products of K-tile kt, when they take
+// at most kPrefetchBytes per lane (FP32 up to 256 neurons, FP64 up to 64).
+template <typename P> struct lds_pointer { static constexpr bool value = false; };
+template <typename U> struct lds_pointer<const U __attribute__((address_space(3)))*> {
+  static constexpr bool value = true;
+};
+constexpr int kPrefetchBytes = 256;
+template <typename T> __host__ __device__ constexpr int prefetch_bytes() { return sizeof(T) == 4 ? kPrefetchBytes : 128; }
 template <typename T, int MT, int KT, typename P, typename B>
 __device__ __forceinline__ void gemm_k(P Wsw, const B& cur, T (&nxt)[MT][4], int lane) {
   V4<T> acc[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = V4<T>{0, 0, 0, 0};
+  constexpr bool PF = !lds_pointer<P>::value && KT > 1 && MT * 4 * (int)sizeof(T) <= prefetch_bytes<T>();
+  if constexpr (PF) {
+    V4<T> a_cur[MT], a_nxt[MT];
 #pragma unroll
-  for (int kt = 0; kt < KT; ++kt) {
-    const T b0 = cur.get(kt, 0), b1 = cur.get(kt, 1), b2 = cur.get(kt, 2), b3 = cur.get(kt, 3);
+    for (int mt = 0; mt < MT; ++mt) a_cur[mt] = Wsw[(mt * KT) * 64 + lane];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      V4<T> a = Wsw[(mt * KT + kt) * 64 + lane];
-      acc[mt] = mfma16(a[0], b0, acc[mt]);
-      acc[mt] = mfma16(a[1], b1, acc[mt]);
-      acc[mt] = mfma16(a[2], b2, acc[mt]);
-      acc[mt] = mfma16(a[3], b3, acc[mt]);
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt + 1 < KT) {
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) a_nxt[mt] = Wsw[(mt * KT + kt + 1) * 64 + lane];
+      }
+      const T b0 = cur.get(kt, 0), b1 = cur.get(kt, 1), b2 = cur.get(kt, 2), b3 = cur.get(kt, 3);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        acc[mt] = mfma16(a_cur[mt][0], b0, acc[mt]);
+        acc[mt] = mfma16(a_cur[mt][1], b1, acc[mt]);
+        acc[mt] = mfma16(a_cur[mt][2], b2, acc[mt]);
+        acc[mt] = mfma16(a_cur[mt][3], b3, acc[mt]);
+      }
+      tile_fence<T, MT>();
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) a_cur[mt] = a_nxt[mt];
     }
-    tile_fence<T, MT>();
+  } else {
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt) {
+      const T b0 = cur.get(kt, 0), b1 = cur.get(kt, 1), b2 = cur.get(kt, 2), b3 = cur.get(kt, 3);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        V4<T> a = Wsw[(mt * KT + kt) * 64 + lane];
+        acc[mt] = mfma16(a[0], b0, acc[mt]);
+        acc[mt] = mfma16(a[1], b1, acc[mt]);
+        acc[mt] = mfma16(a[2], b2, acc[mt]);
+        acc[mt] = mfma16(a[3], b3, acc[mt]);
+      }
+      tile_fence<T, MT>();
+    }
   }
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
