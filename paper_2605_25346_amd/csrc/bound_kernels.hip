@@ -572,6 +572,29 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
 // ---------------------------------------------------------------------------
 // a5 / a7: final spec rows.  One wave = one N-tile holding P = 16 / R subdomains.
 // ---------------------------------------------------------------------------
+// Per-lane inputs of one 16-neuron tile of a dual-ascent relaxation step: the
+// relaxation, the split slot and the current alpha / beta of the lane's row (alpha and
+// beta are read at clamped addresses and selected by the caller).
+template <typename T>
+struct GroupIn {
+  V4<T> rr[4];
+  int sp[4];
+  float a[4], b[4];
+};
+template <typename T>
+__device__ __forceinline__ void load_group(GroupIn<T>& g, gconst<V4<T>> rk, gconst<int> sk, gmut<float> arow,
+                                           gmut<float> brow, int t, int gq, int hoff, int nk) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = t * 16 + nrn<T>(gq, i);
+    g.rr[i] = rk[t * 16 + gq * 4 + i];
+    g.sp[i] = sk[t * 16 + gq * 4 + i];
+    const bool uns = g.rr[i][2] > (T)0 && c < nk;
+    g.a[i] = arow[uns ? hoff + c : 0];
+    g.b[i] = brow[g.sp[i] >= 0 ? (g.sp[i] >> 1) : 0];
+  }
+}
+
 struct FinalArgs {
   BatchDev batch;
   Scratch sc;
@@ -670,29 +693,35 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
             relax_layer<T, NT, false>(st, rk, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
           } else {
             lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
-            const int hoff = net.hoff[k - 1];
+            const int hoff = net.hoff[k - 1], nk = net.n[k];
+            gconst<int> sk = slot + (k - 1) * 16 * NT;
+            // the relaxation, split slots and duals of tile t + 1 are loaded while tile t
+            // is processed (distance-one software pipelining across the scheduling fences)
+            GroupIn<T> cur_in, nxt_in;
+            load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
+            for (int t = 0; t < NT; ++t) {
+              if (t + 1 < NT) load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
 #pragma unroll
               for (int i = 0; i < 4; ++i) {
                 const int c = t * 16 + nrn<T>(gq, i);
-                V4<T> rr = rk[t * 16 + gq * 4 + i];
+                const V4<T> rr = cur_in.rr[i];
                 T gv = st.get(t, i);
                 tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
-                const bool uns = rr[2] > (T)0 && c < net.n[k];
-                const float aload = arow[uns ? hoff + c : 0];
-                const T lo = uns ? (use_in ? (T)aload : rr[0]) : rr[0];
+                const bool uns = rr[2] > (T)0 && c < nk;
+                const T lo = uns ? (use_in ? (T)cur_in.a[i] : rr[0]) : rr[0];
                 T a = (gv >= (T)0 ? lo : rr[1]) * gv;
-                const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
-                const float bload = brow[sp >= 0 ? (sp >> 1) : 0];
-                const T bv = (sp >= 0 && use_in) ? (T)bload : (T)0;
+                const int sp = cur_in.sp[i];
+                const T bv = (sp >= 0 && use_in) ? (T)cur_in.b[i] : (T)0;
                 a -= (sp & 1) ? bv : -bv;
                 double bj = (double)bias[c];
                 acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
                 marg += (a < (T)0 ? -a : a) * rr[3];
                 st.set(t, i, a);
-                if (i == 3) tile_fence<T, NT>();
               }
+              tile_fence<T, NT>();
+              if (t + 1 < NT) cur_in = nxt_in;
+            }
           }
           gconst<V4<T>> Wg = as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1]));
           if (k > 1)
@@ -769,18 +798,28 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       for (int k = 1; k <= L - 1; ++k) {
         gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
         lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
-        const int hoff = net.hoff[k - 1];
+        const int hoff = net.hoff[k - 1], nk = net.n[k];
+        gconst<int> sk = slot + (k - 1) * 16 * NT;
+        GroupIn<T> cur_in, nxt_in;
+        T g_cur[4], g_nxt[4];
+        load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
+        for (int i = 0; i < 4; ++i) g_cur[i] = tape[(((size_t)(k - 1) * NT) * 4 + i) * 64 + lane];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          if (t + 1 < NT) {
+            load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g_nxt[i] = tape[(((size_t)(k - 1) * NT + t + 1) * 4 + i) * 64 + lane];
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = t * 16 + nrn<T>(gq, i);
             T delta = st.get(t, i) + bias[c];       // d lb / d a'^(k)
-            V4<T> rr = rk[t * 16 + gq * 4 + i];
-            T gv = tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane];
-            const bool uns = rr[2] > (T)0 && c < net.n[k];
-            const float aload = arow[uns ? hoff + c : 0];
-            const float av = use_in ? aload : (float)rr[0];
+            const V4<T> rr = cur_in.rr[i];
+            const T gv = g_cur[i];
+            const bool uns = rr[2] > (T)0 && c < nk;
+            const float av = use_in ? cur_in.a[i] : (float)rr[0];
             const T lo = uns ? (T)av : rr[0];
             T d = gv >= (T)0 ? lo : rr[1];
             if (uns && live) {
@@ -794,10 +833,10 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 if (fa.galpha) fa.galpha[((size_t)s * R + r) * fa.H_max + hoff + c] = (float)da;
               }
             }
-            const int sp = slot[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
+            const int sp = cur_in.sp[i];
             if (sp >= 0 && live) {
               T db = (sp & 1) ? -delta : delta;    // -sigma * delta
-              float bv = use_in ? brow[sp >> 1] : 0.0f;
+              float bv = use_in ? cur_in.b[i] : 0.0f;
               if (!last) {
                 brow[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
               } else {
@@ -806,8 +845,14 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
               }
             }
             st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
-            if (i == 3) tile_fence<T, NT>();
           }
+          tile_fence<T, NT>();
+          if (t + 1 < NT) {
+            cur_in = nxt_in;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) g_cur[i] = g_nxt[i];
+          }
+        }
         if (k < L - 1) gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
       }
       if (last) break;
