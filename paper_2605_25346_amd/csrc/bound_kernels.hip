@@ -62,11 +62,19 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
 template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage>
 __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bias, int gq, double& acc,
                                             double& acc2, T& marg) {
+  // the relaxation of tile t + 1 is loaded while tile t is processed
+  V4<T> r_cur[4], r_nxt[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r_cur[i] = rel[gq * 4 + i];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r_nxt[i] = rel[(t + 1) * 16 + gq * 4 + i];
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      V4<T> r = rel[t * 16 + gq * 4 + i];
+      const V4<T> r = r_cur[i];
       T gv = st.get(t, i);
       T a = (gv >= (T)0 ? r[0] : r[1]) * gv;
       double bj = (double)bias[t * 16 + nrn<T>(gq, i)];
@@ -81,6 +89,10 @@ __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bia
       st.set(t, i, a);
     }
     tile_fence<T, NT>();
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r_cur[i] = r_nxt[i];
+    }
   }
 }
 
@@ -664,6 +676,21 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     gmut<float> arow = as_global_mut(DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : (float*)nullptr);
     gmut<float> brow = as_global_mut(DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : (float*)nullptr);
     gconst<double> bu = as_global(sc.bu + so + lbase);
+    // the seed's rounding margin is the same in every evaluation
+    T marg0 = 0;
+    if (sc.margin_on) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int m = t * 16 + nrn<T>(gq, i);
+          const double gd = seed[m] * liveD;
+          const T gt = (T)gd;
+          const double hu = fmax(bu[m], 0.0) * liveD;
+          marg0 += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          if (i == 3) tile_fence<T, NT>();
+        }
+    }
     double best = -INFINITY, lbv = 0.0, mgv = 0.0;
     const int n_eval = DUALS ? fa.iters + 1 : 1;
     for (int it = 0; it < n_eval; ++it) {
@@ -671,19 +698,27 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       const bool use_in = live && !(fa.init_duals && it == 0);
       auto st = make_stage<T, NT, true>(stage, lane);   // the chain state of this wavefront
       double acc = net.seedB[r] * ((gq == 0) ? liveD : 0.0), acc2 = 0.0;
-      T marg = 0;
+      T marg = marg0;
+      {
+        // seeds of tile t + 1 are loaded while tile t is stored
+        double sd_cur[4], sd_nxt[4];
 #pragma unroll
-      for (int t = 0; t < NT; ++t)
+        for (int i = 0; i < 4; ++i) sd_cur[i] = seed[nrn<T>(gq, i)];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int m = t * 16 + nrn<T>(gq, i);
-          double gd = seed[m] * liveD;
-          T gt = (T)gd;
-          st.set(t, i, gt);
-          double hu = fmax(bu[m], 0.0) * liveD;
-          if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
-          if (i == 3) tile_fence<T, NT>();
+        for (int t = 0; t < NT; ++t) {
+          if (t + 1 < NT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sd_nxt[i] = seed[(t + 1) * 16 + nrn<T>(gq, i)];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) st.set(t, i, (T)(sd_cur[i] * liveD));
+          tile_fence<T, NT>();
+          if (t + 1 < NT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sd_cur[i] = sd_nxt[i];
+          }
         }
+      }
       // forward (backward bound propagation) with optional alpha/beta and tape
       T w[1][4];
       {
