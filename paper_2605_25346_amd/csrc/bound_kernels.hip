@@ -981,8 +981,8 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   T* lds_b = (T*)(lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds);
   stage_biases<T>(net, lds_b);
   // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
-  double* tm = (double*)(lds_base + SubLds<T>::bytes(Hp, NT) + 64);
-  tm = (double*)(((uintptr_t)tm + 15) & ~(uintptr_t)15);
+  // (offsets stay on the LDS base pointer so that every access is an LDS access)
+  double* tm = (double*)(lds_base + ((SubLds<T>::bytes(Hp, NT) + 64 + 15) & ~(size_t)15));
   double* c = tm;            // 16
   double* Pm = tm + 16;      // 256 (row-major n x n)
   double* Ilo = tm + 272;    // 16
