@@ -89,14 +89,31 @@ def tm_step(net, c, P, Ilo, Ihi):
     return (c2, P2, Ilo2, Ihi2), box, rows
 
 
-def reach_dt(net, xc, xr, horizon):
-    """Boxes X_0 .. X_H (H+1 x n x 2) of the stepwise TM reachability from one box."""
-    c = np.array(xc, np.float64); P = np.diag(np.asarray(xr, np.float64))
-    Ilo = np.zeros_like(c); Ihi = np.zeros_like(c)
+def reach_dt(net, xc, xr, horizon, u=None):
+    """Boxes X_0 .. X_H (H+1 x n x 2) of the stepwise TM reachability from one box.
+
+    With exogenous inputs (the batched reach of candidate action sequences in the
+    paper's MPC section): the network input is v = [x; u_t] and the loop is
+    x' = A v + B f(v), A of shape n x (n + m), with u (H x m) a given sequence.  The
+    TM of v is the state's TM extended by the point u_t (zero linear part, zero
+    interval), so every step is the same CROWN step on the extended TM."""
+    n = net.A.shape[0]
+    xc = np.asarray(xc, np.float64)[:n]; xr = np.asarray(xr, np.float64)[:n]
+    m = net.widths[0] - n
+    if m and (u is None or np.shape(u) != (horizon, m)):
+        raise ValueError("the network has %d exogenous inputs: u must be horizon x %d" % (m, m))
+    c = xc.copy(); P = np.diag(xr)
+    Ilo = np.zeros(n); Ihi = np.zeros(n)
     boxes = [np.stack([c - xr, c + xr], axis=1)]
     rows = []
-    for _ in range(horizon):
-        (c, P, Ilo, Ihi), box, r = tm_step(net, c, P, Ilo, Ihi)
+    for t in range(horizon):
+        if m:
+            uv = np.asarray(u[t], np.float64)
+            cv, Pv = np.concatenate([c, uv]), np.vstack([P, np.zeros((m, n))])
+            Iv_lo, Iv_hi = np.concatenate([Ilo, np.zeros(m)]), np.concatenate([Ihi, np.zeros(m)])
+        else:
+            cv, Pv, Iv_lo, Iv_hi = c, P, Ilo, Ihi
+        (c, P, Ilo, Ihi), box, r = tm_step(net, cv, Pv, Iv_lo, Iv_hi)
         boxes.append(box)
         rows.append(r)
     return np.array(boxes), dict(c=c, P=P, Ilo=Ilo, Ihi=Ihi, rows=rows)

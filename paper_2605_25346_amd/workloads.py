@@ -193,10 +193,15 @@ def unpack_splits(words):
 def make_workload(name, seed, net_widths, n_sub, *, closed_loop=None, radius=(0.01, 0.1),
                   center=(-1.0, 1.0), max_splits=0, dtype="f32", iters=0, lr=0.1,
                   horizon=0, shared_slope=False, n_state=None, rho=0.95, a_var=0.3, b_var=0.3,
-                  A_mode="gauss", n_split_samples=16) -> Workload:
+                  A_mode="gauss", B_mode="gauss", b_gain=0.1, n_split_samples=16) -> Workload:
     """Draw a workload.  Draw order: weights then biases layer by layer (network by
     network), then A, B, then centres, radii, then split candidates, counts,
-    neurons and signs."""
+    neurons and signs, then (networks with exogenous inputs) the input sequences.
+
+    A closed loop with n_state < n_0 takes the remaining n_0 - n_state network
+    inputs as exogenous actions u_t (meta["u"], S x horizon x m, U[-1, 1]):
+    x' = A [x; u] + B f([x; u]).  A_mode "residual": A = [I, 0]; B_mode
+    "scaled_identity": B = b_gain I (the network predicts a scaled state increment)."""
     rng = np.random.default_rng(seed)
     npdt = np.float32 if dtype == "f32" else np.float64
     nets = [make_network(rng, w, npdt) for w in net_widths]
@@ -206,9 +211,14 @@ def make_workload(name, seed, net_widths, n_sub, *, closed_loop=None, radius=(0.
         n_state = n0 if n_state is None else n_state
         if A_mode == "signed_perm":
             A = _signed_permutation(rng, n_state, rho)
+        elif A_mode == "residual":
+            A = np.eye(n_state, n0)
         else:
             A = rng.normal(0.0, np.sqrt(a_var), size=(n_state, n0))
-        B = rng.normal(0.0, np.sqrt(b_var), size=(n_state, nL))
+        if B_mode == "scaled_identity":
+            B = b_gain * np.eye(n_state, nL)
+        else:
+            B = rng.normal(0.0, np.sqrt(b_var), size=(n_state, nL))
         for net in nets:
             net.A, net.B = A, B
     net_id = (rng.integers(0, len(nets), size=n_sub).astype(np.int32) if len(nets) > 1
@@ -221,8 +231,10 @@ def make_workload(name, seed, net_widths, n_sub, *, closed_loop=None, radius=(0.
     xr = np.repeat(r[:, None], n0, axis=1)
     ptr, lay, neu, sg = _draw_splits(rng, nets, net_id, xc, xr, max_splits, n_split_samples)
     batch = Batch(xc, xr, ptr, lay, neu, sg, net_id)
-    return Workload(name, nets, batch, dtype, iters, lr, horizon, shared_slope,
-                    meta=dict(seed=seed, max_splits=max_splits))
+    meta = dict(seed=seed, max_splits=max_splits)
+    if closed_loop and n_state < n0 and horizon > 0:
+        meta["u"] = rng.uniform(-1.0, 1.0, size=(n_sub, horizon, n0 - n_state))
+    return Workload(name, nets, batch, dtype, iters, lr, horizon, shared_slope, meta=meta)
 
 
 # The five synthetic configurations.  Index 1 is the small FP64 closed-loop case the
@@ -240,6 +252,11 @@ CONFIGS = {
     5: dict(name="mixed_12-{64x5,128x3,256x2}-4_S16384",
             net_widths=[[12] + [64] * 5 + [4], [12] + [128] * 3 + [4], [12] + [256] * 2 + [4]],
             n_sub=16384, max_splits=32, iters=10, lr=0.1),
+    # Batched reach of candidate action sequences through a learned dynamics model (the
+    # paper's MPC use; dynamics MLP of three 96-wide layers): state 8, action 4.
+    6: dict(name="mpc_8+4-96x3-8_S4096_H10", net_widths=[[12, 96, 96, 96, 8]], n_sub=4096,
+            closed_loop=True, n_state=8, radius=0.02, horizon=10, shared_slope=True, A_mode="residual",
+            B_mode="scaled_identity", b_gain=0.1),
 }
 
 

@@ -337,6 +337,64 @@ def test_tm_all_active_linear_closed_loop():
         ot = Cm @ ot + o; Ct = Cm @ Ct
 
 
+def test_tm_exogenous_zero_B_closed_form():
+    """Exogenous inputs with B = 0: x' = A_x x + A_u u_t exactly, so the TM stays
+    c_t = A_x c_{t-1} + A_u u_{t-1}, P_t = A_x^t diag(r), I = 0."""
+    rng = np.random.default_rng(5)
+    n, m = 4, 3
+    net = make_network(rng, [n + m, 16, 16, 2], np.float64)
+    net.A = rng.normal(0, 0.5, (n, n + m)); net.B = np.zeros((n, 2))
+    xc = rng.uniform(-1, 1, n); xr = np.full(n, 0.05)
+    u = rng.uniform(-1, 1, (5, m))
+    boxes, _ = tm.reach_dt(net, xc, xr, 5, u)
+    Ax, Au = net.A[:, :n], net.A[:, n:]
+    c, P = xc.copy(), np.diag(xr)
+    for t in range(6):
+        np.testing.assert_allclose(boxes[t, :, 0], c - np.abs(P).sum(axis=1), atol=1e-12)
+        np.testing.assert_allclose(boxes[t, :, 1], c + np.abs(P).sum(axis=1), atol=1e-12)
+        if t < 5:
+            c, P = Ax @ c + Au @ u[t], Ax @ P
+
+
+def test_tm_exogenous_zero_radius_is_the_trajectory():
+    """A point initial set (and a network with no neuron at a kink) gives degenerate
+    boxes on the exact simulated trajectory x_{t+1} = A [x; u] + B f([x; u])."""
+    wl = config_workload(6, n_sub=3)
+    net = wl.nets[0]
+    n = net.A.shape[0]
+    for s in range(3):
+        xc = wl.batch.x_center[s][:n]
+        u = wl.meta["u"][s]
+        boxes, _ = tm.reach_dt(net, xc, np.zeros(n), wl.horizon, u)
+        x = xc.copy()
+        for t in range(wl.horizon + 1):
+            np.testing.assert_allclose(boxes[t, :, 0], x, rtol=1e-11, atol=1e-11)
+            np.testing.assert_allclose(boxes[t, :, 1], x, rtol=1e-11, atol=1e-11)
+            if t < wl.horizon:
+                v = np.concatenate([x, u[t]])
+                y, _ = exact.forward(net, v[None, :])
+                x = net.A @ v + net.B @ y[0]
+
+
+def test_tm_exogenous_soundness_rollouts():
+    """Sampled initial states rolled out under the given action sequence stay inside
+    every box."""
+    wl = config_workload(6, n_sub=2)
+    net = wl.nets[0]
+    n = net.A.shape[0]
+    for s in range(2):
+        xc, xr, u = wl.batch.x_center[s][:n], wl.batch.x_radius[s][:n], wl.meta["u"][s]
+        boxes, _ = tm.reach_dt(net, xc, xr, wl.horizon, u)
+        rng = np.random.default_rng(s)
+        X = exact.sample_points(rng, xc, xr, 500, corners=True)
+        for t in range(wl.horizon + 1):
+            assert np.all(X >= boxes[t, :, 0] - 1e-12) and np.all(X <= boxes[t, :, 1] + 1e-12)
+            if t < wl.horizon:
+                V = np.hstack([X, np.repeat(u[t][None, :], X.shape[0], axis=0)])
+                y, _ = exact.forward(net, V)
+                X = V @ net.A.T + y @ net.B.T
+
+
 # ---------------------------------------------------------------------------- P10
 @pytest.mark.parametrize("cfg", [1, 2, 3, 5])
 def test_soundness_sampling(cfg):
