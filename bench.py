@@ -224,17 +224,20 @@ def dual_ascent(torch, args, precision="f32"):
     return res
 
 
-def tm_reach(torch, args, precision="f32"):
+def tm_reach(torch, args, precision="f32", cfg=4):
+    """Stepwise TM reach (cfg 4: closed-loop controller; cfg 6: candidate action
+    sequences through a dynamics network with exogenous inputs)."""
     from paper_2605_25346_amd.api import BoundContext, DeviceBatch
     from paper_2605_25346_amd.workloads import config_workload
-    wl = config_workload(4)
+    wl = config_workload(cfg)
     S = wl.batch.n_sub
     ctx = BoundContext(wl.nets, precision=precision, max_sub=S)
     db = DeviceBatch(wl.batch)
-    boxes = torch.zeros(S, wl.horizon + 1, ctx.n0, 2, dtype=torch.float64, device="cuda")
+    boxes = torch.zeros(S, wl.horizon + 1, ctx.n_state, 2, dtype=torch.float64, device="cuda")
+    u = torch.as_tensor(wl.meta["u"], dtype=torch.float64, device="cuda") if "u" in wl.meta else None
 
     def step():
-        ctx.dr_reach_dt(db, wl.horizon, boxes=boxes)
+        ctx.dr_reach_dt(db, wl.horizon, boxes=boxes, u=u)
 
     ms, _ = time_graph(torch, step, max(2, args.steps // 4), 1)
     rows = ctx.dr_get_rows().cpu().numpy()
@@ -439,6 +442,13 @@ def main():
             box_steps_per_s=tr["box_steps_per_s"], ms_per_call=tr["ms"],
             roofline=dict(bound="mfma", achieved=tr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=tr["tflops"] / PEAK_TFLOPS["f32"]))
+        print("bench: candidate reach", file=sys.stderr, flush=True)
+        cr = tm_reach(torch, args, "f32", cfg=6)
+        print(f"bench: candidate reach {cr}", file=sys.stderr, flush=True)
+        extra["mpc_candidates_8+4-96x3-8_S4096_H10"] = dict(
+            box_steps_per_s=cr["box_steps_per_s"], ms_per_call=cr["ms"],
+            roofline=dict(bound="mfma", achieved=cr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                          frac=cr["tflops"] / PEAK_TFLOPS["f32"]))
         print("bench: equal tightness", file=sys.stderr, flush=True)
         extra["equal_tightness_abcrown_vs_crown_input_splitting"] = equal_tightness(torch, args, "f32")
         print(f"bench: equal tightness {extra['equal_tightness_abcrown_vs_crown_input_splitting']}", file=sys.stderr,

@@ -84,7 +84,10 @@ typedef struct {
   const void* const* b;       /* HOST array of L device pointers, b_k of n_k */
   const double* A;            /* device n_state x n_0 (closed loop) or NULL */
   const double* B;            /* device n_state x n_L (closed loop) or NULL */
-  int n_state;                /* rows of A and B; 0 without closed loop (requires n_0 == n_state) */
+  int n_state;                /* rows of A and B, 1 <= n_state <= n_0; 0 without closed loop.  The
+                                 network input is v = [x; u]: the first n_state entries are the
+                                 state, the remaining n_0 - n_state exogenous inputs (actions),
+                                 and x' = A v + B f(v) */
   const double* spec;         /* device q x n_target directions, or NULL for unit vectors */
   int n_spec;                 /* q <= 16 (ignored when spec == NULL); the spec chains and the dual
                                  ascent need 2q <= 16, dr_reach_dt needs n_state <= 16 */
@@ -170,10 +173,24 @@ dr_status dr_optimize_duals(dr_ctx* ctx, int iters, float lr, int init_duals, fl
  * Dynamics") with linear Taylor models: each box is normalised to the TM
  * x = c + P z, z in [-1,1]^n; every step certifies the controller with
  * shared-slope CROWN on the TM input, composes x' = A x + B y in TM arithmetic
- * and evaluates the box.  Needs a closed-loop network with n_state == n_0 and no
- * splits.  boxes: S x (horizon+1) x n_0 x 2 FP64 (step 0 is the input box). */
+ * and evaluates the box.  Needs a closed-loop network with n_state == n_0, no
+ * spec and no splits.  boxes: S x (horizon+1) x n_state x 2 FP64 (step 0 is the
+ * input box).  A network with exogenous inputs (n_state < n_0) returns DR_EINVAL
+ * here; use dr_reach_dt_exo. */
 dr_status dr_reach_dt(dr_ctx* ctx, const dr_batch* batch, int horizon, double* boxes, uint32_t* status,
                       hipStream_t stream);
+
+/* The same stepwise reachability for a network whose input is v = [x; u_t] with a
+ * given exogenous sequence u_t per box (the batched reach of candidate action
+ * sequences through a learned dynamics model, Sec. "Model Predictive Control" of the
+ * paper): at step t the TM of v is the state's TM extended by the point u_t (zero
+ * linear part, zero interval), so x' = A v + B f(v) is composed exactly as above.
+ * u: device FP64 S x horizon x (n_0 - n_state), row-major; must be non-NULL when
+ * horizon > 0 and S > 0 (DR_EINVAL otherwise, and when the network has no
+ * exogenous inputs).  The batch's x_center / x_radius keep their S x n_0 layout;
+ * entries n_state..n_0-1 are ignored.  boxes: S x (horizon+1) x n_state x 2. */
+dr_status dr_reach_dt_exo(dr_ctx* ctx, const dr_batch* batch, int horizon, const double* u, double* boxes,
+                          uint32_t* status, hipStream_t stream);
 
 /* Diagnostics of the last dr_bound_init / dr_propagate_backward /
  * dr_optimize_duals / dr_reach_dt on this context (device outputs):

@@ -105,6 +105,7 @@ class BoundContext:
         B.check(st, None)
         self.ctx = ctx
         self.n0 = nets[0].widths[0]
+        self.n_state = nets[0].A.shape[0] if nets[0].closed_loop else 0
         self.R = self.lib.dr_spec_rows(ctx)
         self.q = self.R // 2
         self.H_max = self.lib.dr_hidden_max(ctx)
@@ -178,16 +179,24 @@ class BoundContext:
                                                _stream()))
         return lb, ub, status[:S], ga, gb
 
-    def dr_reach_dt(self, batch: DeviceBatch, horizon: int, boxes=None):
+    def dr_reach_dt(self, batch: DeviceBatch, horizon: int, boxes=None, u=None):
+        """Stepwise reach; ``u`` (S x horizon x (n_0 - n_state), FP64 device) selects
+        dr_reach_dt_exo for networks with exogenous inputs."""
         self.batch = batch
         S = batch.n_sub
         if boxes is None:
-            boxes = torch.empty(S, horizon + 1, self.n0, 2, dtype=torch.float64, device=self.device)
+            boxes = torch.empty(S, horizon + 1, max(self.n_state, 1), 2, dtype=torch.float64, device=self.device)
         status = torch.zeros(max(S, 1), dtype=torch.int32, device=self.device)
         b = batch.struct()
         self._batch_struct = b
-        self._check(self.lib.dr_reach_dt(self.ctx, ctypes.byref(b), int(horizon), _ptr(boxes), _ptr(status),
-                                         _stream()))
+        if u is None:
+            self._check(self.lib.dr_reach_dt(self.ctx, ctypes.byref(b), int(horizon), _ptr(boxes), _ptr(status),
+                                             _stream()))
+        else:
+            u = torch.as_tensor(u, dtype=torch.float64, device=self.device).contiguous()
+            self._u = u
+            self._check(self.lib.dr_reach_dt_exo(self.ctx, ctypes.byref(b), int(horizon), _ptr(u), _ptr(boxes),
+                                                 _ptr(status), _stream()))
         return boxes, status[:S]
 
     def dr_get_bounds(self):

@@ -962,8 +962,9 @@ struct ReachArgs {
   Scratch sc;
   unsigned* queue;
   int horizon;
-  double* boxes;
+  double* boxes;            // S x (horizon + 1) x n_state x 2
   uint32_t* status;
+  const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
 };
 
 template <typename T, int NT>
@@ -1003,17 +1004,18 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
     __syncthreads();
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
-    double* bx = ra.boxes + (size_t)s * (H + 1) * n0 * 2;
-    // TM normalisation of the input box: c = centre, P = diag(radius), I = [0, 0]
+    double* bx = ra.boxes + (size_t)s * (H + 1) * ns * 2;
+    // TM normalisation of the state box: c = centre, P = diag(radius), I = [0, 0]; the
+    // exogenous inputs (network inputs ns..n0-1) enter each step as points
     if (tid < 16) {
-      double cc = tid < n0 ? ra.batch.xc[(size_t)s * n0 + tid] : 0.0;
-      double rr = tid < n0 ? ra.batch.xr[(size_t)s * n0 + tid] : 0.0;
+      double cc = tid < ns ? ra.batch.xc[(size_t)s * n0 + tid] : 0.0;
+      double rr = tid < ns ? ra.batch.xr[(size_t)s * n0 + tid] : 0.0;
       c[tid] = cc; Ilo[tid] = 0.0; Ihi[tid] = 0.0;
-      if (tid < n0) { bx[tid * 2 + 0] = cc - rr; bx[tid * 2 + 1] = cc + rr; }
+      if (tid < ns) { bx[tid * 2 + 0] = cc - rr; bx[tid * 2 + 1] = cc + rr; }
     }
     for (int e = tid; e < 256; e += kWG) {
       int a = e >> 4, b = e & 15;
-      Pm[e] = (a == b && a < n0) ? ra.batch.xr[(size_t)s * n0 + a] : 0.0;
+      Pm[e] = (a == b && a < ns) ? ra.batch.xr[(size_t)s * n0 + a] : 0.0;
     }
     for (int p = tid; p < Hp; p += kWG) S.slot[p] = -1;
     if (tid == 0) S.misc[1] = 0;
@@ -1022,6 +1024,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
     for (int step = 0; step < H; ++step) {
       // |x_m| bound over the TM, and the input-centre/radius for the layer-1 bounds
       if (tid < 16) {
+        if (tid >= ns && tid < n0) c[tid] = ra.u[((size_t)s * H + step) * (n0 - ns) + (tid - ns)];
         double a = fabs(c[tid]) + fmax(fabs(Ilo[tid]), fabs(Ihi[tid]));
         for (int z = 0; z < n0; ++z) a += fabs(Pm[tid * 16 + z]);
         Xab[tid] = tid < n0 ? a : 0.0;
@@ -1193,7 +1196,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
 #pragma unroll
           for (int z = 0; z < 16; ++z) nP[r * 16 + z] = (z < n0) ? pp[z] : 0.0;
           double blo = cpart - rad + nIlo[r], bhi = cpart + rad + nIhi[r];
-          double* bo = bx + (size_t)(step + 1) * n0 * 2;
+          double* bo = bx + (size_t)(step + 1) * ns * 2;
           bo[r * 2 + 0] = blo;
           bo[r * 2 + 1] = bhi;
           if (!(fabs(blo) < INFINITY) || !(fabs(bhi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);

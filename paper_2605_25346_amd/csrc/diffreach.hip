@@ -287,8 +287,8 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     nd.Hp = (L - 1) * 16 * NT;
     const bool closed = nw.A != nullptr || nw.B != nullptr;
     if (closed && (!nw.A || !nw.B)) return bail(fail(c, DR_EINVAL, "closed loop needs both A and B"));
-    if (closed && (nw.n_state < 1 || nw.n_state > 16 || nw.n_state != nd.n[0]))
-      return bail(fail(c, DR_ESHAPE, "closed loop needs n_state == n_0 <= 16"));
+    if (closed && (nw.n_state < 1 || nw.n_state > 16 || nw.n_state > nd.n[0]))
+      return bail(fail(c, DR_ESHAPE, "closed loop needs 1 <= n_state <= n_0 (<= 16)"));
     nd.A = nw.A;
     nd.n_state = closed ? nw.n_state : 0;
     const int n_target = closed ? nw.n_state : nd.n[L];
@@ -477,10 +477,15 @@ dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, floa
   return DR_OK;
 }
 
-dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, uint32_t* status, hipStream_t stream) {
+static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, uint32_t* status,
+                       hipStream_t stream) {
   if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
   if (!c->closed) return fail(c, DR_EINVAL, "reach_dt needs a closed-loop network");
   if (c->has_spec) return fail(c, DR_EINVAL, "reach_dt bounds every state: create the context without a spec");
+  const bool exo = c->q < c->n0;   // without a spec q = n_state
+  if (exo && !u && horizon > 0 && b && b->n_sub > 0)
+    return fail(c, DR_EINVAL, "the network has exogenous inputs: use dr_reach_dt_exo with the input sequences");
+  if (!exo && u) return fail(c, DR_EINVAL, "u given but the network has no exogenous inputs");
   if (horizon < 0 || horizon > 10000) return fail(c, DR_EINVAL, "horizon must be in 0..10000");
   dr_status st = check_batch(c, b);
   if (st != DR_OK) return st;
@@ -507,12 +512,21 @@ dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, 
     const void* fn = kernel_for(c, Q_REACH, nd.NT);
     dr::ReachArgs ra{};
     ra.batch = c->batch; ra.sc = c->sc; ra.sc.st_out = nullptr; ra.queue = queue_of(c, Q_REACH, i);
-    ra.horizon = horizon; ra.boxes = boxes; ra.status = status;
+    ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};
     if ((st = launch(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, stream)) != DR_OK) return st;
   }
   return DR_OK;
+}
+
+dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, uint32_t* status, hipStream_t stream) {
+  return reach(c, b, horizon, nullptr, boxes, status, stream);
+}
+
+dr_status dr_reach_dt_exo(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, uint32_t* status,
+                          hipStream_t stream) {
+  return reach(c, b, horizon, u, boxes, status, stream);
 }
 
 dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {

@@ -283,6 +283,84 @@ def test_cfg4_tm_reach():
         ctx.close()
 
 
+def _step_tol(tol0, H, growth=3.0):
+    """Per-step tolerance of a reach comparison: a rounding difference of the first
+    step is carried by the Taylor-model composition of the later steps, whose
+    interval part grows by up to ~3x per step on the candidate-action workload (the
+    oracle's own widths grow up to 60x over 10 steps); tol(t) = tol0 growth^(t-1)."""
+    t = np.arange(H + 1)
+    return tol0 * growth ** np.maximum(t - 1, 0)
+
+
+def test_exogenous_reach_candidates():
+    """Stepwise reach of candidate action sequences through a dynamics network with
+    exogenous inputs (network input [x; u_t]) against the oracle: one step to the
+    plain tolerance, the full horizon to the step-scaled one, and soundness always."""
+    from paper_2605_25346_amd import binding as B
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(6, n_sub=8)
+    net = wl.nets[0]
+    u = wl.meta["u"]
+    H = wl.horizon
+    oracle = [tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], H, u[s])[0] for s in range(8)]
+    for precision, margins in (("f64", True), ("f64", False), ("f32", True), ("f32", False)):
+        ctx = _ctx(wl, precision, 8, margins=margins)
+        db = DeviceBatch(wl.batch)
+        with pytest.raises(B.DrError) as ei:
+            ctx.dr_reach_dt(db, H)           # the inputs are required
+        assert ei.value.status == B.DR_EINVAL
+        tol0 = 1e-9 if precision == "f64" else 1e-5
+        for horizon in (1, H):
+            boxes, st = ctx.dr_reach_dt(db, horizon, u=u[:, :horizon])
+            torch.cuda.synchronize()
+            boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+            assert np.all(st == 0)
+            gaps = []
+            for s in range(8):
+                ob = oracle[s][: horizon + 1]
+                g = rel_gap(boxes[s], ob)
+                gaps.append(g)
+                if margins:
+                    assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
+                    assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
+                if precision == "f64" or not margins:
+                    tol = _step_tol(tol0, horizon)
+                    if precision == "f64" and margins:
+                        tol = tol * 10          # the FP64 rounding margins ride on top
+                    assert np.all(g <= tol[:, None, None]), (precision, margins, horizon, s, g.max(axis=(1, 2)))
+            print_stats(f"cfg6 exogenous reach {precision} margins={margins} horizon={horizon}", gaps)
+        ctx.close()
+
+
+def test_exogenous_reach_full_size_sampled():
+    """The benchmarked launch (4096 candidates, FP32 chains, rigorous margins): sampled
+    boxes are sound against the oracle; the gap (the rigorous FP32 margins, carried
+    and amplified by the later steps) is reported."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(6)
+    net = wl.nets[0]
+    S = wl.batch.n_sub
+    ctx = _ctx(wl, "f32", S)
+    boxes, st = ctx.dr_reach_dt(DeviceBatch(wl.batch), wl.horizon, u=wl.meta["u"])
+    torch.cuda.synchronize()
+    boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    gaps = []
+    for s in np.random.default_rng(0).choice(S, 12, replace=False):
+        ob, _ = tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.horizon, wl.meta["u"][s])
+        assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
+        assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
+        g = rel_gap(boxes[s], ob)
+        assert np.all(g[1] <= 1e-3), (s, g[1].max())      # one step: the margin itself
+        gaps.append(g)
+    gaps = np.array(gaps)
+    for t in (1, 5, wl.horizon):
+        print_stats(f"cfg6 full size f32 rigorous (sampled) step {t}", gaps[:, t])
+    ctx.close()
+
+
 def test_cfg5_mixed_networks_crown():
     wl = config_workload(5, n_sub=96)
     res = _run_crown(wl, "f64")
