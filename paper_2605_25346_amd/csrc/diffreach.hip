@@ -96,7 +96,7 @@ const void* kernel_of(int kind, int NT, bool wlds) {
       default: return Inst<T, N>::reach();          \
     }
   switch (NT) {
-    DR_CASE(2) DR_CASE(4) DR_CASE(8) DR_CASE(16)
+    DR_CASE(2) DR_CASE(4) DR_CASE(6) DR_CASE(8) DR_CASE(16)
     default: return nullptr;
   }
 #undef DR_CASE
@@ -276,8 +276,10 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     if (nd.n[0] > 16) return bail(fail(c, DR_ESHAPE, "n_0 must be <= 16"));
     if (nd.n[L] > 64) return bail(fail(c, DR_ESHAPE, "n_L must be <= 64"));
     if (wmax > 256) return bail(fail(c, DR_ESHAPE, "hidden widths must be <= 256"));
+    // 16-tiles per hidden layer: 2, 4, 6 (the 96-wide layers of the paper's dynamics
+    // models), 8 or 16
     int NT = 2;
-    while (NT * 16 < wmax) NT *= 2;
+    while (NT * 16 < wmax) NT = NT == 4 ? 6 : (NT == 6 ? 8 : 2 * NT);
     nd.NT = NT;
     nd.np[0] = 16;
     for (int k = 1; k <= L - 1; ++k) nd.np[k] = 16 * NT;

@@ -361,6 +361,42 @@ def test_exogenous_reach_full_size_sampled():
     ctx.close()
 
 
+def test_96_wide_crown_and_duals():
+    """Hidden width 96 (six 16-tiles: the paper's dynamics-model width) through the
+    bound, spec-row and dual-ascent kernels."""
+    from paper_2605_25346_amd.workloads import make_workload
+    wl = make_workload("w96", 61, [[8, 96, 96, 96, 4]], 64, max_splits=8)
+    res = _run_crown(wl, "f64")
+    _compare(wl, res, range(64), 1e-9, "96-wide f64", tie_tol=1e-9)
+    res32 = _run_crown(wl, "f32", margins=False)
+    _compare(wl, res32, range(64), 1e-5, "96-wide f32 no-margin", sound_side=False)
+    # one ascent step from the default point in FP64 against the oracle's ascent
+    ctx, db = res["ctx"], res["db"]
+    alpha, beta = ctx.new_duals()
+    lb, ub, st, _, _ = ctx.dr_optimize_duals(2, 0.1, alpha, beta, init_duals=True)
+    torch.cuda.synchronize()
+    lb, ub = lb.cpu().numpy(), ub.cpu().numpy()
+    gaps = []
+    for s in range(16):
+        net = wl.nets[0]
+        xc, xr, sp = wl.batch.x_center[s], wl.batch.x_radius[s], wl.batch.splits_of(s)
+        bounds, _, status = crown.intermediate_bounds(net, xc, xr, sp)
+        if status or near_tie(bounds, 1e-9):
+            continue
+        r, kink = _traj_kink(net, bounds, xc, xr, sp, 2, 0.1)
+        q = lb.shape[1]
+        for row in range(2 * q):
+            if kink[row]:
+                continue
+            got = lb[s, row] if row < q else -ub[s, row - q]
+            g = rel_gap(got, r["best"][row])
+            assert g <= 1e-7, (s, row, got, r["best"][row])
+            gaps.append(g)
+    print_stats("96-wide f64 PGA (2 steps)", gaps)
+    assert len(gaps) >= 16
+    res["ctx"].close(); res32["ctx"].close()
+
+
 def test_cfg5_mixed_networks_crown():
     wl = config_workload(5, n_sub=96)
     res = _run_crown(wl, "f64")
