@@ -257,12 +257,14 @@ __device__ __forceinline__ int compact_flags(int n16, F flag_of, int* U, int* wc
 // Interval (IBP) bound of neuron j of hidden layer k from the centre/radius of
 // relu(h_{k-1}) (hc, hr, zero-padded to np_{k-1}), with v = |W_k| relu(u_{k-1}) for the
 // margin coefficients; FP64 with outward rounding.  Four partial sums, vector loads.
-template <typename T>
+template <typename T, int NT>
 __device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, const double* hc, const double* hr,
                                            double& lo, double& hi, double& v) {
-  const int npk = net.np[k - 1];
+  constexpr int npk = 16 * NT;     // hidden layers k >= 2 take a padded hidden layer as input
   gconst<V4<T>> W = as_global((const V4<T>*)((const T*)net.Wn[k - 1] + (size_t)j * npk));
   double zc[4] = {0, 0, 0, 0}, zr[4] = {0, 0, 0, 0}, za[4] = {0, 0, 0, 0};
+  // the whole weight row is in flight at once for narrow layers
+#pragma unroll (NT <= 4 ? 4 * NT : 8)
   for (int m4 = 0; m4 < npk / 4; ++m4) {
     V4<T> w4 = W[m4];
 #pragma unroll
@@ -426,7 +428,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
       sub_sync<TPS>();
       for (int j = t; j < n16; j += TPS) {
         double lo = 0.0, hi = 0.0, v = 0.0;
-        if (j < nk) ibp_neuron<T>(net, k, j, S.hc, S.hr, lo, hi, v);
+        if (j < nk) ibp_neuron<T, NT>(net, k, j, S.hc, S.hr, lo, hi, v);
         S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
         S.l[base + j] = lo; S.u[base + j] = hi;
       }
@@ -1072,7 +1074,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
         if (tid < 16 * NT) {
           const int j = tid;
           double lo = 0.0, hi = 0.0, v = 0.0;
-          if (j < nk) ibp_neuron<T>(net, k, j, S.hc, S.hr, lo, hi, v);
+          if (j < nk) ibp_neuron<T, NT>(net, k, j, S.hc, S.hr, lo, hi, v);
           S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
           S.l[base + j] = lo; S.u[base + j] = hi;
         }
