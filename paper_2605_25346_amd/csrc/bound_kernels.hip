@@ -331,15 +331,21 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
   const int n0 = net.n[0];
   const int n16 = 16 * NT;
 
+  bool first = true;
   for (;;) {
     int item;
     if (TPS == 64) {
-      item = wave_fetch(queue);
+      item = next_item(queue, first, blockIdx.x * kWavesPerWG + wid, gridDim.x * kWavesPerWG);
     } else {
-      if (tid == 0) S.misc[0] = (int)atomicAdd(queue, 1u);
-      __syncthreads();
-      item = S.misc[0];
-      __syncthreads();
+      if (first) {
+        first = false;
+        item = blockIdx.x;
+      } else {
+        if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        item = S.misc[0];
+        __syncthreads();
+      }
     }
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
@@ -645,8 +651,9 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
   const int wave_global = blockIdx.x * kWavesPerWG + (tid >> 6);
   gmut<T> tape = as_global_mut(DUALS ? (T*)fa.tape + (size_t)wave_global * (L - 1) * NT * 256 : (T*)nullptr);
 
+  bool first = true;
   for (;;) {
-    const int item = wave_fetch(fa.queue);
+    const int item = next_item(fa.queue, first, wave_global, (int)n_workers);
     if (item >= n_items) break;
     const int sl = n / R, r = n % R;
     const int idx = item * P + sl;
@@ -999,11 +1006,18 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0], ns = net.n_state, H = ra.horizon;
 
+  bool first = true;
   for (;;) {
-    if (tid == 0) S.misc[0] = (int)atomicAdd(ra.queue, 1u);
-    __syncthreads();
-    const int item = S.misc[0];
-    __syncthreads();
+    int item;
+    if (first) {
+      first = false;
+      item = blockIdx.x;
+    } else {
+      if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(ra.queue, 1u);
+      __syncthreads();
+      item = S.misc[0];
+      __syncthreads();
+    }
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
     double* bx = ra.boxes + (size_t)s * (H + 1) * ns * 2;

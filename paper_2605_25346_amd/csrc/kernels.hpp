@@ -144,6 +144,16 @@ __device__ __forceinline__ int wave_fetch(unsigned* q) {
   if (lane == 0) v = (int)atomicAdd(q, 1u);
   return __shfl(v, 0);
 }
+// Work item of a persistent worker: its first item is its own index (no atomic at
+// launch, when every worker would contend for the counter); later ones come from the
+// queue, offset by the number of workers.  Called by a whole wavefront.
+__device__ __forceinline__ int next_item(unsigned* q, bool& first, int worker, int n_workers) {
+  if (first) {
+    first = false;
+    return worker;
+  }
+  return n_workers + wave_fetch(q);
+}
 __device__ __forceinline__ void wave_done(unsigned* q, unsigned n_workers) {
   int lane = threadIdx.x & 63;
   if (lane == 0) {
