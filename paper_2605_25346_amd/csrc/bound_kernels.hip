@@ -581,12 +581,6 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
     }
     sub_sync<TPS>();
   }
-  if (TPS == 64) {
-    wave_done(queue, gridDim.x * kWavesPerWG);
-  } else if (wid == 0) {
-    // one worker per workgroup for the queue's completion counter
-    wave_done(queue, gridDim.x);
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -911,7 +905,6 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       if (live && !(fabs(best) < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
     }
   }
-  wave_done(fa.queue, n_workers);
 }
 
 // ---------------------------------------------------------------------------
@@ -1235,7 +1228,12 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
     }
     __syncthreads();
   }
-  if (wid == 0) wave_done(ra.queue, gridDim.x);
+}
+
+// Work queue of a persistent launch, cleared by a kernel of its own just before the
+// launch on the same stream (a kernel node, so graph replays need no memset node).
+__global__ void k_reset_queue(unsigned* q) {
+  if (threadIdx.x < 2) q[threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------------------

@@ -156,6 +156,15 @@ dr_status launch(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, h
 
 unsigned* queue_of(dr_ctx* c, int kind, int net) { return c->queues + ((size_t)kind * kMaxNets + net) * 2; }
 
+// A persistent launch: clear its queue, then launch (same stream, so in order).
+dr_status launch_persistent(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, unsigned* q,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(dr::k_reset_queue, dim3(1), dim3(64), 0, stream, q);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "queue reset");
+  return launch(c, fn, grid, lds, args, stream);
+}
+
 dr_status check_batch(dr_ctx* c, const dr_batch* b) {
   if (!b) return fail(c, DR_EINVAL, "batch is NULL");
   if (b->n_sub < 0) return fail(c, DR_ESHAPE, "n_sub < 0");
@@ -392,7 +401,7 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
     sc.st_out = status;
     unsigned* q = queue_of(c, Q_BOUND, i);
     void* args[] = {&c->dnet, &net_index, &bd, &sc, &q, &inter, &ms};
-    if ((st = launch(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, stream)) != DR_OK) return st;
+    if ((st = launch_persistent(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, q, stream)) != DR_OK) return st;
   }
   if (status && !c->sc.direct) {
     // subdomains with an invalid network id are not processed by any launch
@@ -418,7 +427,7 @@ static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t 
     fa.queue = queue_of(c, kind, i);
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &fa};
-    dr_status st = launch(c, fn, c->grid[kind][i], c->lds[kind][i], args, stream);
+    dr_status st = launch_persistent(c, fn, c->grid[kind][i], c->lds[kind][i], args, fa.queue, stream);
     if (st != DR_OK) return st;
   }
   return DR_OK;
@@ -517,7 +526,8 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
     ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};
-    if ((st = launch(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, stream)) != DR_OK) return st;
+    if ((st = launch_persistent(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, ra.queue, stream)) != DR_OK)
+      return st;
   }
   return DR_OK;
 }

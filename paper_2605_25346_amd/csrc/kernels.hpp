@@ -134,9 +134,8 @@ struct BatchDev {
 };
 
 // ---------------------------------------------------------------------------
-// Work queue of a persistent launch: a counter of handed-out items and a counter
-// of finished workers; the last worker to finish resets both, so the next launch
-// (also a graph replay) starts from zero without any host-side reset.
+// Work queue of a persistent launch: a counter of handed-out items, cleared by a
+// one-block kernel on the same stream before every launch (k_reset_queue).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int wave_fetch(unsigned* q) {
   int lane = threadIdx.x & 63;
@@ -153,17 +152,6 @@ __device__ __forceinline__ int next_item(unsigned* q, bool& first, int worker, i
     return worker;
   }
   return n_workers + wave_fetch(q);
-}
-__device__ __forceinline__ void wave_done(unsigned* q, unsigned n_workers) {
-  int lane = threadIdx.x & 63;
-  if (lane == 0) {
-    __threadfence();
-    unsigned d = atomicAdd(q + 1, 1u);
-    if (d == n_workers - 1) {
-      atomicExch(q, 0u);
-      atomicExch(q + 1, 0u);
-    }
-  }
 }
 
 // Sum over the four lane groups holding the same row (lanes n, n+16, n+32, n+48).
