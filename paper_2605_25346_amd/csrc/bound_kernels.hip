@@ -910,20 +910,23 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
 // ---------------------------------------------------------------------------
 // a6: concretization of affine bounds over the boxes (FP64, outward rounding).
 // ---------------------------------------------------------------------------
-__global__ void k_concretize(int S, int q, int n0, const double* __restrict__ xc, const double* __restrict__ xr,
+__global__ void k_concretize(int S, int q, int n0, int Q2, const double* __restrict__ xc, const double* __restrict__ xr,
                              const double* lam_lo, const double* acc_lo, const double* lam_hi,
                              const double* acc_hi, double* lb, double* ub, const uint32_t* ctx_st,
                              uint32_t* status) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= S) return;
-  const uint32_t cst = ctx_st ? ctx_st[s] : 0u;
+  // Q2 (a power of two >= q, <= 16) consecutive lanes per subdomain, one spec row each
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = e / Q2, r = e % Q2;
+  const bool valid = s < S && r < q;
+  const int sc_ = s < S ? s : 0, rc = r < q ? r : 0;
+  const uint32_t cst = ctx_st ? ctx_st[sc_] : 0u;
   const bool dead = cst & (DR_RES_INFEASIBLE | DR_RES_BADSPLIT);
-  uint32_t bits = cst;
-  for (int r = 0; r < q; ++r) {
-    const size_t i = (size_t)s * q + r;
+  uint32_t bits = 0;
+  if (valid) {
+    const size_t i = (size_t)sc_ * q + rc;
     double cl = acc_lo[i], ch = acc_hi[i], al = 0.0, ah = 0.0;
     for (int m = 0; m < n0; ++m) {
-      double c = xc[(size_t)s * n0 + m], rr = xr[(size_t)s * n0 + m];
+      double c = xc[(size_t)sc_ * n0 + m], rr = xr[(size_t)sc_ * n0 + m];
       double wl = lam_lo[i * n0 + m], wh = lam_hi[i * n0 + m];
       cl += wl * c - fabs(wl) * rr;
       ch += wh * c + fabs(wh) * rr;
@@ -934,9 +937,11 @@ __global__ void k_concretize(int S, int q, int n0, const double* __restrict__ xc
     const double vh = ch + 0x1p-48 * (fabs(acc_hi[i]) + ah);
     lb[i] = dead ? INFINITY : vl;
     ub[i] = dead ? -INFINITY : vh;
-    if (!dead && (!(fabs(vl) < INFINITY) || !(fabs(vh) < INFINITY))) bits |= DR_RES_NONFINITE;
+    if (!dead && (!(fabs(vl) < INFINITY) || !(fabs(vh) < INFINITY))) bits = DR_RES_NONFINITE;
   }
-  if (status) status[s] = bits;
+  // OR of the row bits over the subdomain's lane group
+  for (int o = 1; o < Q2; o <<= 1) bits |= (uint32_t)__shfl_xor((int)bits, o);
+  if (status && s < S && r == 0) status[s] = cst | bits;
 }
 
 // a5 when fused into k_bound_init: lay the stored final rows out as the affine bounds.

@@ -460,8 +460,11 @@ dr_status dr_concretize(dr_ctx* c, const double* lam_lo, const double* acc_lo, c
   if (c->batch.n_sub == 0) return DR_OK;
   if (!lam_lo || !acc_lo || !lam_hi || !acc_hi || !lb || !ub) return fail(c, DR_EINVAL, "array pointer is NULL");
   const int S = c->batch.n_sub;
-  hipLaunchKernelGGL(dr::k_concretize, dim3((S + 255) / 256), dim3(256), 0, stream, S, c->q, c->n0, c->batch.xc,
-                     c->batch.xr, lam_lo, acc_lo, lam_hi, acc_hi, lb, ub, c->sc.st, status);
+  int Q2 = 1;
+  while (Q2 < c->q) Q2 *= 2;     // q <= 16
+  const long long threads = (long long)S * Q2;
+  hipLaunchKernelGGL(dr::k_concretize, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream, S, c->q, c->n0,
+                     Q2, c->batch.xc, c->batch.xr, lam_lo, acc_lo, lam_hi, acc_hi, lb, ub, c->sc.st, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "concretize kernel");
   return DR_OK;
