@@ -59,8 +59,8 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
 // Relaxation of one layer applied in place to the chain state st: the multipliers g
 // over h_k become the row multipliers a' over z_k.  Offsets and margin accumulate
 // per lane.
-template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage>
-__device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bias, int gq, double& acc,
+template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage, typename BT>
+__device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<BT> bias, int gq, double& acc,
                                             double& acc2, T& marg) {
   // the relaxation of tile t + 1 is loaded while tile t is processed
   V4<T> r_cur[4], r_nxt[4];
@@ -85,7 +85,7 @@ __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<T> bia
       } else {
         acc += fmin(gt, 0.0) + (double)a * bj;
       }
-      marg += (a < (T)0 ? -a : a) * r[3];
+      marg += fabs(a) * r[3];
       st.set(t, i, a);
     }
     tile_fence<T, NT>();
@@ -113,13 +113,13 @@ __device__ __forceinline__ void gemm_inplace(P Wsw, Stage& st, int lane) {
 // see stage_in_lds); on return w holds the input coefficients.  lds_b: the hidden
 // biases staged in LDS (layer k at (k - 1) 16 NT).  With WL the products read the LDS
 // copy lds_w of the forward-swizzled weights.
-template <typename T, int NT, bool SHARED, bool WL = false, typename Stage>
+template <typename T, int NT, bool SHARED, bool WL = false, typename Stage, typename BT>
 __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& st, const V4<T>* rel_all,
                                                double& acc, double& acc2, T& marg, T (&w)[1][4], int lane,
-                                               const T* lds_b, const V4<T>* lds_w = nullptr) {
+                                               const BT* lds_b, const V4<T>* lds_w = nullptr) {
   const int gq = lane >> 4;
   for (int k = K - 1; k >= 1; --k) {
-    relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc,
+    relax_layer<T, NT, SHARED>(st, rel_all + (k - 1) * 16 * NT, (lconst<BT>)(lds_b + (k - 1) * 16 * NT), gq, acc,
                                acc2, marg);
     if constexpr (WL) {
       lconst<V4<T>> Wl = (lconst<V4<T>>)(lds_w + lds_w_offset(k, NT));
@@ -137,13 +137,15 @@ __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& 
   }
 }
 
-// Stage the hidden biases (padded, layer k at (k - 1) 16 NT) into LDS, once per workgroup.
-template <typename T>
-__device__ void stage_biases(const NetDev& net, T* dst) {
+// Stage the hidden biases (padded, layer k at (k - 1) 16 NT) into LDS, once per
+// workgroup: in FP64 (BT = double, saves a conversion per relaxed multiplier, the
+// offsets being summed in FP64) or in the chain type (less LDS and registers).
+template <typename T, typename BT>
+__device__ void stage_biases(const NetDev& net, BT* dst) {
   const int n16 = 16 * net.NT;
   for (int e = threadIdx.x; e < net.Hp; e += kWG) {
     const int k = e / n16;
-    dst[e] = as_global((const T*)net.bn[k])[e - k * n16];
+    dst[e] = (BT)as_global((const T*)net.bn[k])[e - k * n16];
   }
 }
 
@@ -324,8 +326,8 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
     lds_tail += (size_t)lds_w_count(L, NT) * sizeof(V4<T>);
     stage_weights<T>(net, lds_w);
   }
-  T* lds_b = (T*)lds_tail;
-  stage_biases<T>(net, lds_b);
+  double* lds_b = (double*)lds_tail;
+  stage_biases<T, double>(net, lds_b);
   __syncthreads();
   const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0];
@@ -631,8 +633,8 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
   // dynamic LDS: per-wave chain stages, then the hidden biases
   char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT, true>();
   const NetDev& net = nets[net_index];
-  T* lds_b = (T*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
-  stage_biases<T>(net, lds_b);
+  double* lds_b = (double*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
+  stage_biases<T, double>(net, lds_b);
   __syncthreads();
   const Scratch& sc = fa.sc;
   const int tid = threadIdx.x, lane = tid & 63, gq = lane >> 4, n = lane & 15;
@@ -728,9 +730,9 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         for (int k = L - 1; k >= 1; --k) {
           gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
           if (!DUALS) {
-            relax_layer<T, NT, false>(st, rk, (lconst<T>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
+            relax_layer<T, NT, false>(st, rk, (lconst<double>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
           } else {
-            lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
+            lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
             const int hoff = net.hoff[k - 1], nk = net.n[k];
             gconst<int> sk = slot + (k - 1) * 16 * NT;
             // the relaxation, split slots and duals of tile t + 1 are loaded while tile t
@@ -754,7 +756,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
                 a -= (sp & 1) ? bv : -bv;
                 double bj = (double)bias[c];
                 acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
-                marg += (a < (T)0 ? -a : a) * rr[3];
+                marg += fabs(a) * rr[3];
                 st.set(t, i, a);
               }
               tile_fence<T, NT>();
@@ -835,7 +837,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       }
       for (int k = 1; k <= L - 1; ++k) {
         gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
-        lconst<T> bias = (lconst<T>)(lds_b + (k - 1) * 16 * NT);
+        lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
         const int hoff = net.hoff[k - 1], nk = net.n[k];
         gconst<int> sk = slot + (k - 1) * 16 * NT;
         GroupIn<T> cur_in, nxt_in;
@@ -853,7 +855,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int c = t * 16 + nrn<T>(gq, i);
-            T delta = st.get(t, i) + bias[c];       // d lb / d a'^(k)
+            T delta = st.get(t, i) + (T)bias[c];    // d lb / d a'^(k)
             const V4<T> rr = cur_in.rr[i];
             const T gv = g_cur[i];
             const bool uns = rr[2] > (T)0 && c < nk;
@@ -987,7 +989,7 @@ __global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ net
   SubLds<T> S;
   S.carve(lds_base, Hp, NT);
   T* lds_b = (T*)(lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds);
-  stage_biases<T>(net, lds_b);
+  stage_biases<T, T>(net, lds_b);
   // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
   // (offsets stay on the LDS base pointer so that every access is an LDS access)
   double* tm = (double*)(lds_base + ((SubLds<T>::bytes(Hp, NT) + 64 + 15) & ~(size_t)15));

@@ -126,7 +126,7 @@ size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
   const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
   const bool roomy = kind == Q_FINAL || kind == Q_DUAL;
   const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, roomy);
-  const size_t biases = (size_t)n.Hp * tsz;
+  const size_t biases = (size_t)n.Hp * (kind == Q_REACH ? tsz : sizeof(double));   // see stage_biases
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
   if (kind == Q_BOUND) {
     const size_t teams = n.NT <= 4 ? dr::kWavesPerWG : 1;   // per-wavefront subdomains for narrow networks
