@@ -597,9 +597,9 @@ struct GroupIn {
   int sp[4];
   float a[4], b[4];
 };
-template <typename T>
-__device__ __forceinline__ void load_group(GroupIn<T>& g, gconst<V4<T>> rk, gconst<int> sk, gmut<float> arow,
-                                           gmut<float> brow, int t, int gq, int hoff, int nk) {
+template <typename T, typename RP, typename SP>
+__device__ __forceinline__ void load_group(GroupIn<T>& g, RP rk, SP sk, gmut<float> arow, gmut<float> brow, int t,
+                                           int gq, int hoff, int nk) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int c = t * 16 + nrn<T>(gq, i);
@@ -627,15 +627,24 @@ struct FinalArgs {
   int q;
 };
 
-template <typename T, int NT, bool DUALS>
+// LDS copy of a dual-ascent work item's relaxation and split slots (P subdomains):
+// they do not change over the iterations.
+template <typename T> __host__ __device__ constexpr size_t item_cache_bytes(int P, int Hp) {
+  return ((size_t)P * Hp * (sizeof(V4<T>) + sizeof(int)) + 15) & ~(size_t)15;
+}
+
+template <typename T, int NT, bool DUALS, bool CACHE = false>
 __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
   extern __shared__ __align__(16) char lds_raw[];
-  // dynamic LDS: per-wave chain stages, then the hidden biases
+  // dynamic LDS: per-wave chain stages, the hidden biases, then (CACHE) per-wave item copies
   char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT, true>();
   const NetDev& net = nets[net_index];
   double* lds_b = (double*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
   stage_biases<T, double>(net, lds_b);
   __syncthreads();
+  const int Hp = net.Hp;
+  char* cache = (char*)lds_b + (((size_t)Hp * sizeof(double) + 15) & ~(size_t)15) +
+                (size_t)(threadIdx.x >> 6) * item_cache_bytes<T>(16 / net.R, Hp);
   const Scratch& sc = fa.sc;
   const int tid = threadIdx.x, lane = tid & 63, gq = lane >> 4, n = lane & 15;
   const int L = net.L, R = net.R, q = net.q, n0 = net.n[0];
@@ -660,6 +669,29 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     const size_t so = (size_t)s * HpS;
     gconst<V4<T>> rel = as_global((const V4<T>*)sc.rel + so);
     gconst<int> slot = as_global(sc.slot + so);
+    // relaxation / slots of this lane's subdomain: global, or the wave's LDS copy
+    using RelP = std::conditional_t<CACHE, lconst<V4<T>>, gconst<V4<T>>>;
+    using SlotP = std::conditional_t<CACHE, lconst<int>, gconst<int>>;
+    RelP relb;
+    SlotP slotb;
+    if constexpr (CACHE) {
+      lmut<V4<T>> crel = (lmut<V4<T>>)cache;
+      lmut<int> cslot = (lmut<int>)(cache + (size_t)P * Hp * sizeof(V4<T>));
+      for (int e = lane; e < P * Hp; e += 64) {
+        const int sle = e / Hp, p = e - sle * Hp;
+        const int idxe = item * P + sle;
+        const int se = idxe < cnt ? subdomain_of(sc, net_index, idxe) : 0;
+        crel[e] = as_global((const V4<T>*)sc.rel)[(size_t)se * HpS + p];
+        cslot[e] = as_global(sc.slot)[(size_t)se * HpS + p];
+      }
+      sub_sync<64>();
+      const int slc = sl < P ? sl : 0;
+      relb = (RelP)(crel + slc * Hp);
+      slotb = (SlotP)(cslot + slc * Hp);
+    } else {
+      relb = rel;
+      slotb = slot;
+    }
     // loads below are unconditional (addresses are clamped into range) and masked
     // by selects, so the wave runs straight-line code
     double xcv[4], xrv[4];
@@ -728,13 +760,13 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       T w[1][4];
       {
         for (int k = L - 1; k >= 1; --k) {
-          gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
+          const RelP rk = relb + (k - 1) * 16 * NT;
           if (!DUALS) {
             relax_layer<T, NT, false>(st, rk, (lconst<double>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
           } else {
             lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
             const int hoff = net.hoff[k - 1], nk = net.n[k];
-            gconst<int> sk = slot + (k - 1) * 16 * NT;
+            const SlotP sk = slotb + (k - 1) * 16 * NT;
             // the relaxation, split slots and duals of tile t + 1 are loaded while tile t
             // is processed (distance-one software pipelining across the scheduling fences)
             GroupIn<T> cur_in, nxt_in;
@@ -836,10 +868,10 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
           for (int i = 0; i < 4; ++i) st.set(t, i, dlt[t][i]);
       }
       for (int k = 1; k <= L - 1; ++k) {
-        gconst<V4<T>> rk = rel + (k - 1) * 16 * NT;
+        const RelP rk = relb + (k - 1) * 16 * NT;
         lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
         const int hoff = net.hoff[k - 1], nk = net.n[k];
-        gconst<int> sk = slot + (k - 1) * 16 * NT;
+        const SlotP sk = slotb + (k - 1) * 16 * NT;
         GroupIn<T> cur_in, nxt_in;
         T g_cur[4], g_nxt[4];
         load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);

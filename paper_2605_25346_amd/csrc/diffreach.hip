@@ -82,9 +82,11 @@ struct Inst {
   }
   static const void* final_() { return (const void*)&dr::k_final<T, NT, false>; }
   static const void* dual() { return (const void*)&dr::k_final<T, NT, true>; }
+  static const void* dual_cached() { return (const void*)&dr::k_final<T, NT, true, true>; }
   static const void* reach() { return (const void*)&dr::k_reach_dt<T, NT>; }
 };
 
+// wlds: the bound kernel with LDS weights; for the dual ascent: the item-cached instance
 template <typename T>
 const void* kernel_of(int kind, int NT, bool wlds) {
 #define DR_CASE(N)                                  \
@@ -92,7 +94,7 @@ const void* kernel_of(int kind, int NT, bool wlds) {
     switch (kind) {                                 \
       case Q_BOUND: return wlds ? Inst<T, N>::bound_lds() : Inst<T, N>::bound(); \
       case Q_FINAL: return Inst<T, N>::final_();    \
-      case Q_DUAL: return Inst<T, N>::dual();       \
+      case Q_DUAL: return wlds ? Inst<T, N>::dual_cached() : Inst<T, N>::dual(); \
       default: return Inst<T, N>::reach();          \
     }
   switch (NT) {
@@ -122,18 +124,33 @@ bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
 
 // Dynamic LDS of a launch: one chain stage per wavefront (wide layers keep the chain
 // state in LDS), the kernel's own state, then the hidden biases.
+// The dual ascent copies each work item's relaxation and split slots to LDS when the
+// copies of the four wavefronts fit beside the chain stages.
+size_t item_cache_total(const dr_ctx* c, const dr::NetDev& n) {
+  const int P = 16 / std::max(c->R, 1);
+  const size_t one = c->prec == DR_PREC_F64 ? dr::item_cache_bytes<double>(P, n.Hp) : dr::item_cache_bytes<float>(P, n.Hp);
+  return dr::kWavesPerWG * one;
+}
+size_t final_lds_base(const dr_ctx* c, const dr::NetDev& n) {
+  const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
+  return dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, true) + (((size_t)n.Hp * sizeof(double) + 15) & ~(size_t)15);
+}
+bool use_item_cache(const dr_ctx* c, const dr::NetDev& n) {
+  return c->R <= 16 && final_lds_base(c, n) + item_cache_total(c, n) <= kMaxLds;
+}
+
 size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
   const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
-  const bool roomy = kind == Q_FINAL || kind == Q_DUAL;
-  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, roomy);
+  if (kind == Q_FINAL) return final_lds_base(c, n);
+  if (kind == Q_DUAL) return final_lds_base(c, n) + (use_item_cache(c, n) ? item_cache_total(c, n) : 0);
+  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, false);
   const size_t biases = (size_t)n.Hp * (kind == Q_REACH ? tsz : sizeof(double));   // see stage_biases
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
   if (kind == Q_BOUND) {
     const size_t teams = n.NT <= 4 ? dr::kWavesPerWG : 1;   // per-wavefront subdomains for narrow networks
     return stages + teams * b + (use_lds_weights(c, n) ? lds_weight_bytes(c, n) : 0) + biases;
   }
-  if (kind == Q_REACH) return stages + b + dr::kReachExtraLds + biases;
-  return stages + biases;
+  return stages + b + dr::kReachExtraLds + biases;   // Q_REACH
 }
 
 // Launch shape of a persistent kernel: workgroups per CU from the occupancy
@@ -350,7 +367,8 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   for (int i = 0; i < n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     for (int kind = 0; kind < Q_KINDS; ++kind) {
-      const void* fn = kernel_for(c, kind, nd.NT, kind == Q_BOUND && use_lds_weights(c, nd));
+      const void* fn = kernel_for(c, kind, nd.NT, (kind == Q_BOUND && use_lds_weights(c, nd)) ||
+                                                      (kind == Q_DUAL && use_item_cache(c, nd)));
       if (!fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
       const size_t lds = lds_bytes(c, kind, nd);
       if (lds > kMaxLds) return bail(fail(c, DR_ESHAPE, "network too deep for the on-chip state of its kernels"));
@@ -423,7 +441,7 @@ static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t 
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const int kind = duals ? Q_DUAL : Q_FINAL;
-    const void* fn = kernel_for(c, kind, nd.NT);
+    const void* fn = kernel_for(c, kind, nd.NT, duals && use_item_cache(c, nd));
     fa.queue = queue_of(c, kind, i);
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &fa};
