@@ -611,6 +611,22 @@ __device__ __forceinline__ void load_group(GroupIn<T>& g, RP rk, SP sk, gmut<flo
   }
 }
 
+// alpha / beta of one 16-neuron tile (addresses from the relaxation and split slots).
+template <typename T, typename RP, typename SP>
+__device__ __forceinline__ void load_ab(float (&ao)[4], float (&bo)[4], RP rk, SP sk, gmut<float> arow,
+                                        gmut<float> brow, int t, int gq, int hoff, int nk) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int c = t * 16 + nrn<T>(gq, i);
+    const bool uns = rk[t * 16 + gq * 4 + i][2] > (T)0 && c < nk;
+    const int sp = sk[t * 16 + gq * 4 + i];
+    ao[i] = arow[uns ? hoff + c : 0];
+    bo[i] = brow[sp >= 0 ? (sp >> 1) : 0];
+  }
+}
+// Pipeline depth (tiles) of the dual loads: deeper when the relaxation is in LDS.
+template <bool CACHE> constexpr int dual_depth() { return CACHE ? 3 : 1; }
+
 struct FinalArgs {
   BatchDev batch;
   Scratch sc;
@@ -769,30 +785,50 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
             const SlotP sk = slotb + (k - 1) * 16 * NT;
             // the relaxation, split slots and duals of tile t + 1 are loaded while tile t
             // is processed (distance-one software pipelining across the scheduling fences)
-            GroupIn<T> cur_in, nxt_in;
-            load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
+            // relaxed multiplier of neuron (t, i) with the tile's inputs
+            auto relax_one = [&](int t, int i, V4<T> rr, int sp, float aval, float bval) {
+              const int c = t * 16 + nrn<T>(gq, i);
+              T gv = st.get(t, i);
+              tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
+              const bool uns = rr[2] > (T)0 && c < nk;
+              const T lo = uns ? (use_in ? (T)aval : rr[0]) : rr[0];
+              T a = (gv >= (T)0 ? lo : rr[1]) * gv;
+              const T bv = (sp >= 0 && use_in) ? (T)bval : (T)0;
+              a -= (sp & 1) ? bv : -bv;
+              double bj = (double)bias[c];
+              acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
+              marg += fabs(a) * rr[3];
+              st.set(t, i, a);
+            };
+            if constexpr (CACHE) {
+              // relaxation and slots from LDS at use; alpha / beta DEP tiles ahead
+              constexpr int DEP = dual_depth<CACHE>();
+              float a_r[DEP + 1][4], b_r[DEP + 1][4];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              if (t + 1 < NT) load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
+              for (int tt = 0; tt < DEP; ++tt)
+                if (tt < NT) load_ab<T>(a_r[tt], b_r[tt], rk, sk, arow, brow, tt, gq, hoff, nk);
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const int c = t * 16 + nrn<T>(gq, i);
-                const V4<T> rr = cur_in.rr[i];
-                T gv = st.get(t, i);
-                tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane] = gv;
-                const bool uns = rr[2] > (T)0 && c < nk;
-                const T lo = uns ? (use_in ? (T)cur_in.a[i] : rr[0]) : rr[0];
-                T a = (gv >= (T)0 ? lo : rr[1]) * gv;
-                const int sp = cur_in.sp[i];
-                const T bv = (sp >= 0 && use_in) ? (T)cur_in.b[i] : (T)0;
-                a -= (sp & 1) ? bv : -bv;
-                double bj = (double)bias[c];
-                acc += fmin((double)gv * (double)rr[2], 0.0) + (double)a * bj;
-                marg += fabs(a) * rr[3];
-                st.set(t, i, a);
+              for (int t = 0; t < NT; ++t) {
+                if (t + DEP < NT)
+                  load_ab<T>(a_r[(t + DEP) % (DEP + 1)], b_r[(t + DEP) % (DEP + 1)], rk, sk, arow, brow, t + DEP, gq,
+                             hoff, nk);
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                  relax_one(t, i, rk[t * 16 + gq * 4 + i], sk[t * 16 + gq * 4 + i], a_r[t % (DEP + 1)][i],
+                            b_r[t % (DEP + 1)][i]);
+                tile_fence<T, NT>();
               }
-              tile_fence<T, NT>();
-              if (t + 1 < NT) cur_in = nxt_in;
+            } else {
+              GroupIn<T> cur_in, nxt_in;
+              load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
+#pragma unroll
+              for (int t = 0; t < NT; ++t) {
+                if (t + 1 < NT) load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) relax_one(t, i, cur_in.rr[i], cur_in.sp[i], cur_in.a[i], cur_in.b[i]);
+                tile_fence<T, NT>();
+                if (t + 1 < NT) cur_in = nxt_in;
+              }
             }
           }
           gconst<V4<T>> Wg = as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1]));
@@ -872,57 +908,85 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
         const int hoff = net.hoff[k - 1], nk = net.n[k];
         const SlotP sk = slotb + (k - 1) * 16 * NT;
-        GroupIn<T> cur_in, nxt_in;
-        T g_cur[4], g_nxt[4];
-        load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) g_cur[i] = tape[(((size_t)(k - 1) * NT) * 4 + i) * 64 + lane];
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          if (t + 1 < NT) {
-            load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) g_nxt[i] = tape[(((size_t)(k - 1) * NT + t + 1) * 4 + i) * 64 + lane];
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int c = t * 16 + nrn<T>(gq, i);
-            T delta = st.get(t, i) + (T)bias[c];    // d lb / d a'^(k)
-            const V4<T> rr = cur_in.rr[i];
-            const T gv = g_cur[i];
-            const bool uns = rr[2] > (T)0 && c < nk;
-            const float av = use_in ? cur_in.a[i] : (float)rr[0];
-            const T lo = uns ? (T)av : rr[0];
-            T d = gv >= (T)0 ? lo : rr[1];
-            if (uns && live) {
-              T da = gv >= (T)0 ? delta * gv : (T)0;
-              if (!last) {
-                float nv = av + fa.lr * (float)da;
-                nv = fminf(fmaxf(nv, 0.0f), 1.0f);
-                arow[hoff + c] = nv;
-              } else {
-                if (init_now) arow[hoff + c] = av;
-                if (fa.galpha) fa.galpha[((size_t)s * R + r) * fa.H_max + hoff + c] = (float)da;
-              }
+        // adjoint of neuron (t, i) with the tile's inputs; PGA update of alpha / beta
+        auto adjoint_one = [&](int t, int i, V4<T> rr, int sp, float aval, float bval, T gv) {
+          const int c = t * 16 + nrn<T>(gq, i);
+          T delta = st.get(t, i) + (T)bias[c];    // d lb / d a'^(k)
+          const bool uns = rr[2] > (T)0 && c < nk;
+          const float av = use_in ? aval : (float)rr[0];
+          const T lo = uns ? (T)av : rr[0];
+          T d = gv >= (T)0 ? lo : rr[1];
+          if (uns && live) {
+            T da = gv >= (T)0 ? delta * gv : (T)0;
+            if (!last) {
+              float nv = av + fa.lr * (float)da;
+              nv = fminf(fmaxf(nv, 0.0f), 1.0f);
+              arow[hoff + c] = nv;
+            } else {
+              if (init_now) arow[hoff + c] = av;
+              if (fa.galpha) fa.galpha[((size_t)s * R + r) * fa.H_max + hoff + c] = (float)da;
             }
-            const int sp = cur_in.sp[i];
-            if (sp >= 0 && live) {
-              T db = (sp & 1) ? -delta : delta;    // -sigma * delta
-              float bv = use_in ? cur_in.b[i] : 0.0f;
-              if (!last) {
-                brow[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
-              } else {
-                if (init_now) brow[sp >> 1] = bv;
-                if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
-              }
-            }
-            st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
           }
-          tile_fence<T, NT>();
-          if (t + 1 < NT) {
-            cur_in = nxt_in;
+          if (sp >= 0 && live) {
+            T db = (sp & 1) ? -delta : delta;    // -sigma * delta
+            float bv = use_in ? bval : 0.0f;
+            if (!last) {
+              brow[sp >> 1] = fmaxf(0.0f, bv + fa.lr * (float)db);
+            } else {
+              if (init_now) brow[sp >> 1] = bv;
+              if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
+            }
+          }
+          st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
+        };
+        auto tape_at = [&](int t, int i) { return tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane]; };
+        if constexpr (CACHE) {
+          constexpr int DEP = dual_depth<CACHE>();
+          float a_r[DEP + 1][4], b_r[DEP + 1][4];
+          T g_r[DEP + 1][4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g_cur[i] = g_nxt[i];
+          for (int tt = 0; tt < DEP; ++tt)
+            if (tt < NT) {
+              load_ab<T>(a_r[tt], b_r[tt], rk, sk, arow, brow, tt, gq, hoff, nk);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) g_r[tt][i] = tape_at(tt, i);
+            }
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            if (t + DEP < NT) {
+              constexpr int W = DEP + 1;
+              load_ab<T>(a_r[(t + DEP) % W], b_r[(t + DEP) % W], rk, sk, arow, brow, t + DEP, gq, hoff, nk);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) g_r[(t + DEP) % W][i] = tape_at(t + DEP, i);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              adjoint_one(t, i, rk[t * 16 + gq * 4 + i], sk[t * 16 + gq * 4 + i], a_r[t % (DEP + 1)][i],
+                          b_r[t % (DEP + 1)][i], g_r[t % (DEP + 1)][i]);
+            tile_fence<T, NT>();
+          }
+        } else {
+          GroupIn<T> cur_in, nxt_in;
+          T g_cur[4], g_nxt[4];
+          load_group<T>(cur_in, rk, sk, arow, brow, 0, gq, hoff, nk);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g_cur[i] = tape_at(0, i);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) {
+            if (t + 1 < NT) {
+              load_group<T>(nxt_in, rk, sk, arow, brow, t + 1, gq, hoff, nk);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) g_nxt[i] = tape_at(t + 1, i);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+              adjoint_one(t, i, cur_in.rr[i], cur_in.sp[i], cur_in.a[i], cur_in.b[i], g_cur[i]);
+            tile_fence<T, NT>();
+            if (t + 1 < NT) {
+              cur_in = nxt_in;
+#pragma unroll
+              for (int i = 0; i < 4; ++i) g_cur[i] = g_nxt[i];
+            }
           }
         }
         if (k < L - 1) gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
