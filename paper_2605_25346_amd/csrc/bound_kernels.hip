@@ -266,7 +266,8 @@ __device__ __forceinline__ void ibp_neuron(const NetDev& net, int k, int j, cons
   gconst<V4<T>> W = as_global((const V4<T>*)((const T*)net.Wn[k - 1] + (size_t)j * npk));
   double zc[4] = {0, 0, 0, 0}, zr[4] = {0, 0, 0, 0}, za[4] = {0, 0, 0, 0};
   // the whole weight row is in flight at once for narrow layers
-#pragma unroll (NT <= 4 ? 4 * NT : 8)
+  constexpr int kUnroll = NT <= 4 ? 4 * NT : 8;
+#pragma unroll kUnroll
   for (int m4 = 0; m4 < npk / 4; ++m4) {
     V4<T> w4 = W[m4];
 #pragma unroll
@@ -1370,7 +1371,7 @@ __global__ void k_swizzle(const T* __restrict__ Wn, int npk, int npkm1, int adjo
 
 // Seeds of the final rows [c; -c]: a_L = c (or c B), g = a_L W_L, acc = a_L . b_L, skip = c A.
 template <typename T>
-__global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npL, int npLm1,
+__global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npLm1,
                         const double* __restrict__ C, int q, int n_target, const double* __restrict__ A,
                         const double* __restrict__ B, int n0, double* seedW, double* seedB, double* skip) {
   const int R = 2 * q;

@@ -20,7 +20,6 @@ using dr::kWG;
 namespace {
 thread_local std::string g_create_error;
 enum { Q_BOUND = 0, Q_FINAL = 1, Q_DUAL = 2, Q_REACH = 3, Q_KINDS = 4 };
-constexpr int kSupportedNT[] = {2, 4, 8, 16};
 int pad16(int n) { return (n + 15) / 16 * 16; }
 }  // namespace
 
@@ -238,7 +237,7 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStre
   }
   const int tot = nd.R * npLm1;
   hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
-                     (const T*)nd.bn[L - 1], nd.n[L], nd.np[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0],
+                     (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0],
                      seedW, seedB, skip);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
   nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip;
