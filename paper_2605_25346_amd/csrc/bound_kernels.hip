@@ -1073,8 +1073,14 @@ struct ReachArgs {
   const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
 };
 
+// Two workgroups per CU for the FP32 reach of 64- and 96-wide networks: the register
+// budget of 256 costs a few spills there and doubles the boxes in flight (measured);
+// wider or FP64 instances keep one.
+template <typename T, int NT> constexpr int reach_waves_per_eu() { return sizeof(T) == 4 && (NT == 4 || NT == 6) ? 2 : 1; }
+
 template <typename T, int NT>
-__global__ void __launch_bounds__(kWG) k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(reach_waves_per_eu<T, NT>())))
+k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
   extern __shared__ __align__(16) char lds_raw[];
   const NetDev& net = nets[net_index];
   const Scratch& sc = ra.sc;

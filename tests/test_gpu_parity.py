@@ -283,6 +283,39 @@ def test_cfg4_tm_reach():
         ctx.close()
 
 
+@pytest.mark.parametrize("width", [64, 128])
+def test_tm_reach_narrow_networks(width):
+    """The stepwise reach kernel on 64- and 128-wide controllers (instances other than
+    the 256-wide one of configuration 4)."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    from paper_2605_25346_amd.workloads import make_workload
+    require_gpu()
+    wl = make_workload(f"reach{width}", 70 + width, [[8, width, width, 4]], 8, closed_loop=True, radius=0.02,
+                       horizon=6, shared_slope=True, A_mode="signed_perm", rho=0.95, b_var=3e-5)
+    net = wl.nets[0]
+    oracle = [tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.horizon)[0] for s in range(8)]
+    for precision, margins in (("f64", True), ("f32", True), ("f32", False)):
+        ctx = _ctx(wl, precision, 8, margins=margins)
+        boxes, st = ctx.dr_reach_dt(DeviceBatch(wl.batch), wl.horizon)
+        torch.cuda.synchronize()
+        boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        gaps = []
+        for s in range(8):
+            ob = oracle[s]
+            g = rel_gap(boxes[s], ob)
+            gaps.append(g)
+            if margins:
+                assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
+                assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
+            if precision == "f64":
+                assert np.all(g <= 1e-9), (s, g.max())
+            elif not margins:
+                assert np.all(g <= 1e-5), (s, g.max())
+        print_stats(f"reach {width}-wide {precision} margins={margins}", gaps)
+        ctx.close()
+
+
 def _step_tol(tol0, H, growth=3.0):
     """Per-step tolerance of a reach comparison: a rounding difference of the first
     step is carried by the Taylor-model composition of the later steps, whose
