@@ -37,6 +37,12 @@ struct dr_ctx {
   dr::Scratch sc{};
   unsigned* queues = nullptr;
   void* tape = nullptr;
+  size_t tape_off[kMaxNets] = {};   // per-network tape regions (the launches may overlap)
+  // several networks: one stream per network, forked from and joined back into the
+  // caller's stream around the per-network launches so that they overlap
+  hipStream_t aux[kMaxNets] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[kMaxNets] = {};
   int cus = 0;
   int grid[Q_KINDS][kMaxNets] = {};
   size_t lds[Q_KINDS][kMaxNets] = {};
@@ -171,6 +177,25 @@ dr_status launch(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, h
 }
 
 unsigned* queue_of(dr_ctx* c, int kind, int net) { return c->queues + ((size_t)kind * kMaxNets + net) * 2; }
+
+// Per-network launches of a multi-network context run on their own streams between a
+// fork and a join on the caller's stream (also inside a graph capture).
+dr_status fork_nets(dr_ctx* c, hipStream_t s) {
+  if (c->n_nets < 2) return DR_OK;
+  hipError_t e = hipEventRecord(c->fork_ev, s);
+  for (int i = 0; e == hipSuccess && i < c->n_nets; ++i) e = hipStreamWaitEvent(c->aux[i], c->fork_ev, 0);
+  return e == hipSuccess ? DR_OK : hip_fail(c, e, "stream fork");
+}
+hipStream_t net_stream(dr_ctx* c, hipStream_t s, int i) { return c->n_nets < 2 ? s : c->aux[i]; }
+dr_status join_nets(dr_ctx* c, hipStream_t s) {
+  if (c->n_nets < 2) return DR_OK;
+  hipError_t e = hipSuccess;
+  for (int i = 0; e == hipSuccess && i < c->n_nets; ++i) {
+    e = hipEventRecord(c->join_ev[i], c->aux[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, c->join_ev[i], 0);
+  }
+  return e == hipSuccess ? DR_OK : hip_fail(c, e, "stream join");
+}
 
 // A persistent launch: clear its queue, then launch (same stream, so in order).
 dr_status launch_persistent(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, unsigned* q,
@@ -361,7 +386,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       (e = hipMemsetAsync(sc.rows, 0, sizeof(int) * S * 8, stream)) != hipSuccess ||
       (e = hipMemsetAsync(sc.margin, 0, sizeof(double) * S * 32, stream)) != hipSuccess)
     return bail(hip_fail(c, e, "hipMemsetAsync"));
-  // launch shapes and the per-wave tape of the dual ascent
+  // launch shapes and the per-wave tape of the dual ascent (one region per network)
   size_t tape_bytes = 0;
   for (int i = 0; i < n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
@@ -379,9 +404,18 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       c->grid[kind][i] = persistent_grid(c, fn, lds, kind);
     }
     const size_t waves = (size_t)c->grid[Q_DUAL][i] * dr::kWavesPerWG;
-    tape_bytes = std::max(tape_bytes, waves * (size_t)(nd.L - 1) * nd.NT * 256 * tsz);
+    c->tape_off[i] = tape_bytes;
+    tape_bytes += (waves * (size_t)(nd.L - 1) * nd.NT * 256 * tsz + 255) & ~(size_t)255;
   }
   if ((e = ctx_alloc(c, &c->tape, tape_bytes)) != hipSuccess) return bail(hip_fail(c, e, "hipMalloc tape"));
+  if (n_nets > 1) {
+    if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
+      return bail(hip_fail(c, e, "hipEventCreate"));
+    for (int i = 0; i < n_nets; ++i)
+      if ((e = hipStreamCreateWithFlags(&c->aux[i], hipStreamNonBlocking)) != hipSuccess ||
+          (e = hipEventCreateWithFlags(&c->join_ev[i], hipEventDisableTiming)) != hipSuccess)
+        return bail(hip_fail(c, e, "stream/event creation"));
+  }
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(c, e, "set-up"));
   *out = c;
   return DR_OK;
@@ -409,6 +443,7 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "order kernel");
   }
+  if ((st = fork_nets(c, stream)) != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const void* fn = kernel_for(c, Q_BOUND, nd.NT, use_lds_weights(c, nd));
@@ -418,8 +453,11 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
     sc.st_out = status;
     unsigned* q = queue_of(c, Q_BOUND, i);
     void* args[] = {&c->dnet, &net_index, &bd, &sc, &q, &inter, &ms};
-    if ((st = launch_persistent(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, q, stream)) != DR_OK) return st;
+    if ((st = launch_persistent(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, q, net_stream(c, stream, i))) !=
+        DR_OK)
+      return st;
   }
+  if ((st = join_nets(c, stream)) != DR_OK) return st;
   if (status && !c->sc.direct) {
     // subdomains with an invalid network id are not processed by any launch
     e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * b->n_sub, hipMemcpyDeviceToDevice, stream);
@@ -433,21 +471,23 @@ static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t 
   fa.batch = c->batch;
   fa.sc = c->sc;
   fa.sc.st_out = nullptr;
-  fa.tape = c->tape;
   fa.H_max = c->H_max;
   fa.max_splits = std::max(c->max_splits, 1);
   fa.q = c->q;
+  dr_status st = fork_nets(c, stream);
+  if (st != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const int kind = duals ? Q_DUAL : Q_FINAL;
     const void* fn = kernel_for(c, kind, nd.NT, duals && use_item_cache(c, nd));
     fa.queue = queue_of(c, kind, i);
+    fa.tape = (char*)c->tape + c->tape_off[i];
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &fa};
-    dr_status st = launch_persistent(c, fn, c->grid[kind][i], c->lds[kind][i], args, fa.queue, stream);
+    st = launch_persistent(c, fn, c->grid[kind][i], c->lds[kind][i], args, fa.queue, net_stream(c, stream, i));
     if (st != DR_OK) return st;
   }
-  return DR_OK;
+  return join_nets(c, stream);
 }
 
 dr_status dr_propagate_backward(dr_ctx* c, double* lam_lo, double* acc_lo, double* lam_hi, double* acc_hi,
@@ -538,6 +578,7 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(c, e, "order kernel");
   }
+  if ((st = fork_nets(c, stream)) != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     const void* fn = kernel_for(c, Q_REACH, nd.NT);
@@ -546,9 +587,11 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
     ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};
-    if ((st = launch_persistent(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, ra.queue, stream)) != DR_OK)
+    if ((st = launch_persistent(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, ra.queue,
+                                 net_stream(c, stream, i))) != DR_OK)
       return st;
   }
+  if ((st = join_nets(c, stream)) != DR_OK) return st;
   return DR_OK;
 }
 
@@ -606,6 +649,11 @@ void dr_destroy(dr_ctx* c) {
   if (!c) return;
   (void)hipDeviceSynchronize();
   for (void* p : c->allocs) (void)hipFree(p);
+  for (int i = 0; i < kMaxNets; ++i) {
+    if (c->aux[i]) (void)hipStreamDestroy(c->aux[i]);
+    if (c->join_ev[i]) (void)hipEventDestroy(c->join_ev[i]);
+  }
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   delete c;
 }
 
