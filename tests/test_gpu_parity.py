@@ -503,19 +503,21 @@ def test_autograd_function_matches_oracle_gradient():
     ctx.close()
 
 
-def test_graph_capture_replay():
+@pytest.mark.parametrize("cfg", [3, 5])
+def test_graph_capture_replay(cfg):
     """bound_init -> propagate -> concretize -> 3 dual steps captured in one graph;
-    replays (with eager work between them) reproduce the eager results exactly."""
+    replays (with eager work between them) reproduce the eager results exactly.
+    cfg 5 has three networks, whose launches run on forked streams."""
     from paper_2605_25346_amd.api import DeviceBatch
     require_gpu()
-    wl = config_workload(3, n_sub=32)
+    wl = config_workload(cfg, n_sub=32)
     ctx = _ctx(wl, "f32", 32)
     db = DeviceBatch(wl.batch)
     ctx.dr_bound_init(db)
     alpha, beta = ctx.new_duals()
-    S, q = 32, ctx.q
+    S, q, n0 = 32, ctx.q, ctx.n0
     f = lambda *s: torch.zeros(*s, dtype=torch.float64, device="cuda")
-    aff = (f(S, q, 8), f(S, q), f(S, q, 8), f(S, q))
+    aff = (f(S, q, n0), f(S, q), f(S, q, n0), f(S, q))
     cout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
     dout = (f(S, q), f(S, q), torch.zeros(S, dtype=torch.int32, device="cuda"))
 
