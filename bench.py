@@ -14,7 +14,7 @@ Also measured (reported under "extra", each with its own roofline figure):
   * the FP64-chain variant of the headline workload.
 The FP64 reference is timed on the host on a bounded sample ("cpu_baseline").
 
-Prints ONE JSON line.  Multi-GPU runs are not supported by this build.
+Prints ONE JSON line.  Runs on one GPU: the path has no multi-GPU execution.
 """
 from __future__ import annotations
 
@@ -395,7 +395,7 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU scaling is not part of it",
+        print(json.dumps({"error": "one GPU only: the bound propagation has no multi-GPU execution",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

@@ -120,7 +120,7 @@ def test_cfg2_f32_rigorous_sound():
 
 @pytest.mark.parametrize("precision", ["f64", "f32"])
 def test_cfg2_full_size_sampled(precision):
-    """BASELINE size (4096 subdomains) in the benchmark's launch shape; 40 sampled
+    """Full headline size (4096 subdomains) in the benchmark's launch shape; 40 sampled
     subdomains against the oracle."""
     wl = config_workload(2)
     res = _run_crown(wl, precision, margins=(precision == "f64"))
