@@ -10,6 +10,9 @@ fallback for it.  Parity status per function:
   dense sampling).
 * crown.gradient / evaluate_duals: pinned (central finite differences, and an
   independent torch-FP64 autograd of the same bound).
+* crown.param_gradient: pinned (central finite differences of final_bounds at a
+  fixed relaxation; on all-active networks, finite differences of the full crown
+  with its intermediate bounds recomputed, and the closed form of the affine map).
 * crown.optimize_duals: pinned (one-neuron and split hand cases, strong duality
   against the LP optimum, soundness against brute force).
 * tm.reach_dt: pinned (B = 0 closed form A^t x +- |A^t| r, all-stable linear

@@ -315,6 +315,55 @@ def evaluate_duals(net, bounds, xc, xr, alpha_flat, beta_flat, splits=(), spec=N
     return out["rowlb"], dalpha, dbeta, out
 
 
+def param_gradient(net, bounds, xc, xr, alpha_flat, beta_flat, omega, splits=(), spec=None):
+    """Weighted gradient of the row bounds w.r.t. the network parameters and the box,
+    with the relaxation held fixed.
+
+    The bound of row r is lb_r = acc_r + w_r.xc - |w_r|.xr (Theorem "CROWN linear
+    bounds of NN"), where the slopes, intercepts (from the fixed intermediate bounds)
+    and alpha, beta are constants.  W_k enters only through g^(k-1) = a^(k) W_k and
+    b_k only through acc += a^(k).b_k, so with e^(k) = d lb / d g^(k) (the adjoint
+    of the alpha/beta gradient) and e^(0) = xc - sgn(w) xr:
+        d lb_r / d W_k = a^(k)_r (outer) e^(k-1)_r,   d lb_r / d b_k = a^(k)_r,
+        d lb_r / d xc = w_r,   d lb_r / d xr = -|w_r|.
+    ``omega`` (2q,) weights the rows (the incoming gradient of each row bound).
+
+    Returns dict(dW, db (per layer, natural shapes), dxc, dxr (n0,), absW (per layer:
+    sum_r |omega_r| |a^(k)_r| (outer) |e^(k-1)_r|, the scale of the rounding error
+    of any summation order), rowlb)."""
+    alpha = _split_alpha(net, alpha_flat)
+    beta = _dense_beta(net, beta_flat, splits)
+    out = final_bounds(net, bounds, xc, xr, spec, alpha=alpha, beta=beta, splits=splits, tape=True)
+    L = net.n_layers
+    Ws, bs = net.Ws, net.bs
+    relax, res, sig = out["relax"], out["res"], out["sig"]
+    om = np.asarray(omega, np.float64)
+    a_L, _ = spec_rows(net, default_spec(net) if spec is None else np.asarray(spec, np.float64))
+    # multipliers a^(k) on z_k (k = 1..L) and adjoints e^(k) (k = 0..L-1)
+    a = [None] * (L + 1)
+    e = [None] * L
+    a[L] = a_L
+    for k in range(1, L):
+        tp = res["tape"][k - 1]
+        a[k] = tp["d"] * tp["g"] - beta[k - 1] * sig[k - 1]
+    w = res["w"]
+    e[0] = xc[None, :] - np.sign(w) * xr[None, :]
+    delta = e[0] @ Ws[0].T + bs[0]
+    for k in range(1, L):
+        kind, s, t, _ = relax[k - 1]
+        g = res["tape"][k - 1]["g"]
+        d = res["tape"][k - 1]["d"]
+        e[k] = delta * d + np.where((kind == UNSTABLE) & (g < 0), t, 0.0)
+        if k < L - 1:
+            delta = e[k] @ Ws[k].T + bs[k]
+    dW, db, absW = [], [], []
+    for k in range(1, L + 1):
+        dW.append((om[:, None] * a[k]).T @ e[k - 1])
+        db.append(om @ a[k])
+        absW.append((np.abs(om)[:, None] * np.abs(a[k])).T @ np.abs(e[k - 1]))
+    return dict(dW=dW, db=db, dxc=om @ w, dxr=-(om @ np.abs(w)), absW=absW, rowlb=out["rowlb"])
+
+
 def optimize_duals(net, bounds, xc, xr, splits=(), spec=None, iters=20, lr=0.1,
                    alpha_init=None, beta_init=None, opt_alpha=True, opt_beta=True):
     """Projected gradient ascent on (alpha, beta) with fixed intermediate bounds.

@@ -291,6 +291,107 @@ def test_gradient_matches_torch_autograd():
             np.testing.assert_allclose(Bt.grad.numpy(), dbe, rtol=1e-10, atol=1e-12)
 
 
+# ------------------------------------------------------- parameter gradient (fixed relaxation)
+def _perturbed(net, k, i, j, h, bias=False):
+    Ws = [W.copy() for W in net.Ws]; bs = [b.copy() for b in net.bs]
+    if bias:
+        bs[k][i] += h
+    else:
+        Ws[k][i, j] += h
+    return Network(Ws, bs, net.A, net.B)
+
+
+def _same_branches(op, om):
+    same = np.array_equal(np.sign(op["res"]["w"]), np.sign(om["res"]["w"]))
+    return same and all(np.array_equal(a["g"] >= 0, b["g"] >= 0) for a, b in zip(op["res"]["tape"], om["res"]["tape"]))
+
+
+@pytest.mark.parametrize("cfg", [1, 3])
+def test_param_gradient_finite_differences(cfg):
+    """Central differences (h = 1e-6) of the weighted row bounds w.r.t. weights, biases
+    and the box, with the intermediate bounds and alpha, beta held fixed, match the
+    hand adjoint (cfg 1: closed loop, the rows enter through B and the skip A)."""
+    wl = config_workload(cfg, n_sub=2)
+    net = wl.nets[0]
+    rng = np.random.default_rng(17)
+    q = crown.default_spec(net).shape[0]
+    R, H, h = 2 * q, sum(net.hidden), 1e-6
+    checked = 0
+    for s in range(2):
+        xc, xr = wl.batch.x_center[s], wl.batch.x_radius[s]
+        sp = wl.batch.splits_of(s)
+        bounds, _, status = crown.intermediate_bounds(net, xc, xr, sp)
+        assert status == 0
+        al = rng.uniform(0, 1, (R, H)); be = rng.uniform(0, 0.5, (R, len(sp)))
+        om = rng.normal(size=R)
+        pg = crown.param_gradient(net, bounds, xc, xr, al, be, om, sp)
+        alpha = crown._split_alpha(net, al); beta = crown._dense_beta(net, be, sp)
+
+        def val(n, c=xc, r=xr):
+            o = crown.final_bounds(n, bounds, c, r, alpha=alpha, beta=beta, splits=sp, tape=True)
+            return om @ o["rowlb"], o
+
+        for k in range(net.n_layers):
+            W = net.Ws[k]
+            for _ in range(6):
+                i, j = rng.integers(W.shape[0]), rng.integers(W.shape[1])
+                vp, op = val(_perturbed(net, k, i, j, h)); vm, omn = val(_perturbed(net, k, i, j, -h))
+                if not _same_branches(op, omn):
+                    continue
+                fd = (vp - vm) / (2 * h)
+                assert pg["dW"][k][i, j] == pytest.approx(fd, rel=1e-6, abs=1e-8), (k, i, j)
+                checked += 1
+            i = rng.integers(W.shape[0])
+            vp, _ = val(_perturbed(net, k, i, 0, h, bias=True)); vm, _ = val(_perturbed(net, k, i, 0, -h, bias=True))
+            assert pg["db"][k][i] == pytest.approx((vp - vm) / (2 * h), rel=1e-6, abs=1e-8)
+        for m in range(len(xc)):
+            dc = np.zeros_like(xc); dc[m] = h
+            vp, _ = val(net, xc + dc); vm, _ = val(net, xc - dc)
+            assert pg["dxc"][m] == pytest.approx((vp - vm) / (2 * h), rel=1e-6, abs=1e-8)
+            vp, _ = val(net, xc, xr + dc); vm, _ = val(net, xc, xr - dc)
+            assert pg["dxr"][m] == pytest.approx((vp - vm) / (2 * h), rel=1e-6, abs=1e-8)
+        np.testing.assert_array_equal(pg["rowlb"], crown.evaluate_duals(net, bounds, xc, xr, al, be, sp, grad=False)[0])
+    assert checked >= 6 * net.n_layers
+
+
+def test_param_gradient_all_active_is_the_full_gradient():
+    """On a network whose every neuron is active over the box the bound is the exact
+    range of the affine map  M x + m  (M = W_L ... W_1): lb_r = c_r (M xc + m) - |c_r M| xr.
+    There the relaxation carries no slope or intercept, so the fixed-relaxation gradient
+    is the gradient of the full CROWN bound (intermediate bounds recomputed at every
+    perturbation), and d lb_r / d b_1 = c_r W_L ... W_2 in closed form."""
+    rng = np.random.default_rng(3)
+    widths = [3, 5, 4, 2]
+    Ws = [rng.uniform(0.1, 1.0, (widths[k + 1], widths[k])) for k in range(3)]
+    bs = [rng.uniform(0.5, 1.0, widths[k + 1]) for k in range(3)]
+    net = net_from(Ws, bs)
+    xc, xr = np.array([1.0, 2.0, 1.5]), np.array([0.2, 0.1, 0.3])
+    out = crown.crown(net, xc, xr)
+    assert all(np.all(l > 0) for (l, u) in out["bounds"])
+    R, H = 4, sum(net.hidden)
+    om = np.array([0.7, -1.3, 0.4, 2.0])
+    pg = crown.param_gradient(net, out["bounds"], xc, xr, crown.default_alpha(net, out["bounds"], R),
+                              np.zeros((R, 0)), om)
+    C = np.vstack([np.eye(2), -np.eye(2)])
+    np.testing.assert_allclose(pg["db"][0], om @ (C @ Ws[2] @ Ws[1]), rtol=1e-13)
+    M = Ws[2] @ Ws[1] @ Ws[0]
+    np.testing.assert_allclose(pg["dxc"], om @ (C @ M), rtol=1e-13)
+    np.testing.assert_allclose(pg["dxr"], -(om @ np.abs(C @ M)), rtol=1e-13)
+    h = 1e-6
+
+    def full(n):
+        o = crown.crown(n, xc, xr)
+        return om @ np.concatenate([o["lb"], -o["ub"]])
+
+    for k in range(3):
+        for i in range(Ws[k].shape[0]):
+            for j in range(Ws[k].shape[1]):
+                fd = (full(_perturbed(net, k, i, j, h)) - full(_perturbed(net, k, i, j, -h))) / (2 * h)
+                assert pg["dW"][k][i, j] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+            fd = (full(_perturbed(net, k, i, 0, h, True)) - full(_perturbed(net, k, i, 0, -h, True))) / (2 * h)
+            assert pg["db"][k][i] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
 # ---------------------------------------------------------------------------- P9
 def test_closed_loop_zero_B():
     """x' = A x with B = 0: the bound is the exact range A xc -+ |A| r."""
