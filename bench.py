@@ -224,6 +224,41 @@ def dual_ascent(torch, args, precision="f32"):
     return res
 
 
+def param_grad(torch, args, precision="f32"):
+    """Gradient of a weighted sum of the bounds w.r.t. every weight, bias and box of the
+    8-128x4-4 network over its 2048-subdomain batch (plain-CROWN relaxation)."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(3)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, max_splits=16)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    rng = np.random.default_rng(0)
+    g_lb = torch.tensor(rng.normal(size=(S, ctx.q)), device="cuda")
+    g_ub = torch.tensor(rng.normal(size=(S, ctx.q)), device="cuda")
+    out, ws = ctx.param_grad_outputs()
+
+    def step():
+        ctx.dr_param_grad(alpha, beta, g_lb, g_ub, init_duals=True, out=out, workspace=ws)
+
+    ms, _ = time_graph(torch, step, max(4, args.steps // 2), 2)
+    status = out[6].cpu().numpy()
+    live = int(np.sum((status & 9) == 0))
+    w = wl.nets[0].widths
+    L = len(w) - 1
+    # forward chain + adjoint chain of every final row, then the per-layer contraction
+    # over all rows (rows of infeasible subdomains are zero but still summed)
+    adj = sum(2 * w[j] * w[j - 1] for j in range(1, L))
+    contr = sum(2 * w[k] * (w[k - 1] + 1) for k in range(1, L + 1))
+    flops = live * ctx.R * (final_flops_per_row(w) + adj) + S * ctx.R * contr
+    res = dict(ms=ms, S=S, rows=S * ctx.R, tflops=flops / (ms * 1e-3) / 1e12,
+               subdomains_per_s=S / (ms * 1e-3))
+    ctx.close()
+    return res
+
+
 def tm_reach(torch, args, precision="f32", cfg=4):
     """Stepwise TM reach (cfg 4: closed-loop controller; cfg 6: candidate action
     sequences through a dynamics network with exogenous inputs)."""
@@ -435,6 +470,13 @@ def main():
             subdomain_iters_per_s=da["subdomain_iters_per_s"], ms_per_call=da["ms"],
             roofline=dict(bound="mfma", achieved=da["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=da["tflops"] / PEAK_TFLOPS["f32"]))
+        print("bench: parameter gradient", file=sys.stderr, flush=True)
+        pg = param_grad(torch, args, "f32")
+        print(f"bench: parameter gradient {pg}", file=sys.stderr, flush=True)
+        extra["param_grad_8-128x4-4_S2048"] = dict(
+            subdomains_per_s=pg["subdomains_per_s"], ms_per_call=pg["ms"],
+            roofline=dict(bound="mfma", achieved=pg["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                          frac=pg["tflops"] / PEAK_TFLOPS["f32"]))
         print("bench: TM reach", file=sys.stderr, flush=True)
         tr = tm_reach(torch, args, "f32")
         print(f"bench: TM reach {tr}", file=sys.stderr, flush=True)

@@ -169,6 +169,38 @@ dr_status dr_optimize_duals(dr_ctx* ctx, int iters, float lr, int init_duals, fl
                             double* lb, double* ub, float* grad_alpha, float* grad_beta,
                             uint32_t* status, hipStream_t stream);
 
+/* Gradient of the bounds w.r.t. the network's weights and biases and the boxes, the
+ * training signal of the reachability-aware loss (Sec. "Certified training of
+ * neural dynamics and controllers": the loss is a function of bound widths, e.g.
+ * mean log(1 + V) with V a width sum, and is differentiated through the bound).
+ * For the objective
+ *   J = sum_{s,i} g_lb[s,i] * lb[s,i] + g_ub[s,i] * ub[s,i]
+ * (g_lb, g_ub: the caller's d loss / d lb, d loss / d ub) it returns dJ/dW_k,
+ * dJ/db_k, dJ/dx_center and dJ/dx_radius with the relaxation of the last
+ * dr_bound_init held fixed: the intermediate bounds (hence the chord slopes and
+ * intercepts) and the given alpha, beta are constants; their own dependence on
+ * the weights is not differentiated.  Where every neuron is stable this is the
+ * gradient of the bound itself.  The bounds are those of dr_optimize_duals with
+ * iters = 0 at (alpha, beta).
+ * Context: one network (DR_EINVAL otherwise).
+ *   alpha, beta   as dr_optimize_duals (init_duals: start at the adaptive slopes
+ *                 and beta = 0, i.e. plain CROWN, and write them back).
+ *   g_lb, g_ub    S x q FP64 (device).  Rows of infeasible subdomains are ignored.
+ *   lb, ub        S x q FP64 out: the bounds at (alpha, beta).
+ *   dW            host array of L device pointers, dW[k-1]: n_k x n_{k-1} FP64
+ *                 row-major; db: L device pointers, db[k-1]: n_k FP64.  Overwritten.
+ *   dxc, dxr      S x n_0 FP64 (nullable): dJ/dx_center and dJ/dx_radius.
+ *   workspace     device memory of at least dr_param_grad_workspace(ctx, S) bytes
+ *                 (caller-owned; holds the per-row multipliers and adjoints and the
+ *                 per-chunk partial sums), so the call allocates nothing.
+ * Asynchronous on `stream`; outputs are complete when the stream reaches the call's
+ * end.  Sizes are checked before any launch (DR_EINVAL / DR_ESHAPE). */
+size_t dr_param_grad_workspace(const dr_ctx* ctx, int n_sub);
+dr_status dr_param_grad(dr_ctx* ctx, float* alpha, float* beta, int init_duals, const double* g_lb,
+                        const double* g_ub, double* lb, double* ub, double* const* dW, double* const* db,
+                        double* dxc, double* dxr, void* workspace, size_t workspace_bytes, uint32_t* status,
+                        hipStream_t stream);
+
 /* Step a8: stepwise closed-loop reachability (Algorithm "Reachability of DT
  * Dynamics") with linear Taylor models: each box is normalised to the TM
  * x = c + P z, z in [-1,1]^n; every step certifies the controller with

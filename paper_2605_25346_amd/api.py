@@ -105,6 +105,7 @@ class BoundContext:
         B.check(st, None)
         self.ctx = ctx
         self.n0 = nets[0].widths[0]
+        self.widths = list(nets[0].widths)
         self.n_state = nets[0].A.shape[0] if nets[0].closed_loop else 0
         self.R = self.lib.dr_spec_rows(ctx)
         self.q = self.R // 2
@@ -178,6 +179,38 @@ class BoundContext:
                                                _ptr(beta), _ptr(lb), _ptr(ub), _ptr(ga), _ptr(gb), _ptr(status),
                                                _stream()))
         return lb, ub, status[:S], ga, gb
+
+    def param_grad_outputs(self):
+        """Output tensors of dr_param_grad for the current batch and its workspace."""
+        S, q = self.batch.n_sub, self.q
+        f = lambda *s: torch.empty(*s, dtype=torch.float64, device=self.device)
+        dW = [f(n_out, n_in) for n_in, n_out in zip(self.widths[:-1], self.widths[1:])]
+        db = [f(n_out) for n_out in self.widths[1:]]
+        status = torch.zeros(max(S, 1), dtype=torch.int32, device=self.device)
+        out = (f(S, q), f(S, q), dW, db, f(max(S, 1), self.n0), f(max(S, 1), self.n0), status)
+        nbytes = int(self.lib.dr_param_grad_workspace(self.ctx, S))
+        return out, torch.empty(max(nbytes, 1), dtype=torch.uint8, device=self.device)
+
+    def dr_param_grad(self, alpha, beta, g_lb, g_ub, init_duals=False, out=None, workspace=None):
+        """Weighted gradient of the bounds w.r.t. weights, biases and boxes at a fixed
+        relaxation.  Returns (lb, ub, dW list, db list, dxc, dxr, status); dW[k-1] is
+        n_k x n_{k-1} FP64."""
+        S = self.batch.n_sub
+        if out is None or workspace is None:
+            out2, ws2 = self.param_grad_outputs()
+            out = out if out is not None else out2
+            workspace = workspace if workspace is not None else ws2
+        lb, ub, dW, db, dxc, dxr, status = out
+        g_lb = torch.as_tensor(g_lb, dtype=torch.float64, device=self.device).contiguous()
+        g_ub = torch.as_tensor(g_ub, dtype=torch.float64, device=self.device).contiguous()
+        self._pg_keep = (g_lb, g_ub)
+        Wp = (ctypes.c_void_p * len(dW))(*[t.data_ptr() for t in dW])
+        bp = (ctypes.c_void_p * len(db))(*[t.data_ptr() for t in db])
+        self._check(self.lib.dr_param_grad(self.ctx, _ptr(alpha), _ptr(beta), int(bool(init_duals)), _ptr(g_lb),
+                                           _ptr(g_ub), _ptr(lb), _ptr(ub), Wp, bp, _ptr(dxc), _ptr(dxr),
+                                           _ptr(workspace), ctypes.c_size_t(workspace.numel()), _ptr(status),
+                                           _stream()))
+        return lb, ub, dW, db, dxc[:S], dxr[:S], status[:S]
 
     def dr_reach_dt(self, batch: DeviceBatch, horizon: int, boxes=None, u=None):
         """Stepwise reach; ``u`` (S x horizon x (n_0 - n_state), FP64 device) selects

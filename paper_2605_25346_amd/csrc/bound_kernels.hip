@@ -642,6 +642,11 @@ struct FinalArgs {
   int H_max;                // alpha row stride
   int max_splits;           // beta row stride
   int q;
+  // parameter gradient (k_final with PGRAD): row weights, the column-major per-row
+  // tapes of multipliers a^(k) (weighted) and adjoints e^(k), input gradients
+  const double* g_lb; const double* g_ub;
+  void* ptape; size_t rows_pad;
+  double* dxc; double* dxr;
 };
 
 // LDS copy of a dual-ascent work item's relaxation and split slots (P subdomains):
@@ -650,8 +655,17 @@ template <typename T> __host__ __device__ constexpr size_t item_cache_bytes(int 
   return ((size_t)P * Hp * (sizeof(V4<T>) + sizeof(int)) + 15) & ~(size_t)15;
 }
 
-template <typename T, int NT, bool DUALS, bool CACHE = false>
+// Column offsets of the parameter-gradient tapes (rows_pad entries per column): the
+// multipliers a^(k) of layers k = 1..L, then the adjoints e^(k) of layers k = 0..L-1
+// (e^(0) = xc - sgn(w) xr); every hidden layer has 16 NT columns, the input 16.
+__host__ __device__ inline int ptape_col_a(int k, int NT) { return (k - 1) * 16 * NT; }
+__host__ __device__ inline int ptape_col_g(int k, int L, int NT, int npL) {
+  return (L - 1) * 16 * NT + npL + (k == 0 ? 0 : 16 + (k - 1) * 16 * NT);
+}
+
+template <typename T, int NT, bool DUALS, bool CACHE = false, bool PGRAD = false>
 __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, int net_index, FinalArgs fa) {
+  static_assert(!PGRAD || DUALS, "the parameter gradient extends the dual adjoint");
   extern __shared__ __align__(16) char lds_raw[];
   // dynamic LDS: per-wave chain stages, the hidden biases, then (CACHE) per-wave item copies
   char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT, true>();
@@ -724,6 +738,13 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       xrv[i] = ok ? rv : 0.0;
     }
     const double liveD = live ? 1.0 : 0.0;
+    // parameter gradient: this lane's tape row and its weight (zero for dead rows)
+    const size_t prow = (size_t)s * R + r;
+    double omega = 0.0;
+    if constexpr (PGRAD) {
+      if (live) omega = r < q ? fa.g_lb[(size_t)s * q + r] : -fa.g_ub[(size_t)s * q + (r - q)];
+    }
+    auto ptape_at = [&](int col) -> gmut<T> { return as_global_mut((T*)fa.ptape + (size_t)col * fa.rows_pad + prow); };
     // seed margin: rounding of the FP64 seed g = a_L W_L to the chain type, times |h_{L-1}|
     gconst<double> seed = as_global(net.seedW + (size_t)r * net.np[L - 1]);
     const int lbase = (L - 2) * 16 * NT;
@@ -888,7 +909,41 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       best = fmax(best, lbv);
       const bool last = (it == n_eval - 1);
       const bool init_now = fa.init_duals && it == 0;
-      if (last && fa.galpha == nullptr && fa.gbeta == nullptr && !init_now) break;
+      if (last && !PGRAD && fa.galpha == nullptr && fa.gbeta == nullptr && !init_now) break;
+      if constexpr (PGRAD) {
+        // d lb / d xc = w, d lb / d xr = -|w|, summed over the R rows of the subdomain
+        // with their weights (lanes sl R .. sl R + R - 1 of the lane group)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const double vc = omega * wt[i], vr = -omega * fabs(wt[i]);
+          double sc_ = 0.0, sr_ = 0.0;
+          for (int j = 0; j < R; ++j) {
+            const int src = (lane & ~15) + (sl < P ? sl : 0) * R + j;
+            sc_ += __shfl(vc, src);
+            sr_ += __shfl(vr, src);
+          }
+          const int m = nrn<T>(gq, i);
+          if (inrange && r == 0 && m < n0) {
+            if (fa.dxc) fa.dxc[(size_t)s * n0 + m] = live ? sc_ : 0.0;
+            if (fa.dxr) fa.dxr[(size_t)s * n0 + m] = live ? sr_ : 0.0;
+          }
+        }
+        if (inrange) {
+          // a^(L): the seed row (weighted); e^(0) = xc - sgn(w) xr
+          const int npL = net.np[L];
+          for (int t = 0; t < npL / 16; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int o = t * 16 + nrn<T>(gq, i);
+              ptape_at(ptape_col_a(L, NT) + o)[0] = (T)(omega * net.seedA[(size_t)r * npL + o]);
+            }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const double sg = wt[i] > 0.0 ? 1.0 : (wt[i] < 0.0 ? -1.0 : 0.0);
+            ptape_at(ptape_col_g(0, L, NT, npL) + nrn<T>(gq, i))[0] = live ? (T)(xcv[i] - sg * xrv[i]) : (T)0;
+          }
+        }
+      }
       // ---- hand-written adjoint of lb = acc + w.xc - |w|.xr w.r.t. alpha, beta
       // the chain state now holds d lb / d(W_k^T a'^(k)) (without the bias term)
       {
@@ -938,7 +993,16 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
               if (fa.gbeta) fa.gbeta[((size_t)s * R + r) * fa.max_splits + (sp >> 1)] = (float)db;
             }
           }
-          st.set(t, i, delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0));
+          const T e = delta * d + ((uns && gv < (T)0) ? rr[2] : (T)0);
+          if constexpr (PGRAD) {
+            if (inrange) {
+              const T bs = (sp >= 0 && use_in) ? (T)bval : (T)0;
+              const T am = d * gv - ((sp & 1) ? bs : -bs);   // a^(k), as in the forward pass
+              ptape_at(ptape_col_a(k, NT) + c)[0] = live ? (T)(omega * (double)am) : (T)0;
+              ptape_at(ptape_col_g(k, L, NT, net.np[L]) + c)[0] = live ? e : (T)0;
+            }
+          }
+          st.set(t, i, e);
         };
         auto tape_at = [&](int t, int i) { return tape[(((size_t)(k - 1) * NT + t) * 4 + i) * 64 + lane]; };
         if constexpr (CACHE) {
@@ -1004,6 +1068,105 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       if (live && !(fabs(best) < INFINITY)) atomicOr(&sc.st[s], (uint32_t)DR_RES_NONFINITE);
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Parameter gradient: a contraction over the rows of the batch per layer,
+//   dW_k[m][j] = sum_row A_k[row][m] E_{k-1}[row][j],   db_k[m] = sum_row A_k[row][m],
+// with A the weighted multipliers and E the adjoints written by k_final<..., PGRAD>.
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+  const void* tape;         // column-major tapes, rows_pad entries per column
+  size_t rows_pad;
+  int rows;                 // valid rows (S R); later rows are read as zero
+  int chunk_rows;           // rows per workgroup (multiple of 16)
+  int n_chunks;
+  size_t poff[kMaxL];       // partial sums of layer k at poff[k-1]: n_chunks x np_k x (np_{k-1} + 1)
+  void* part;
+  double* dW[kMaxL];        // outputs (natural n_k x n_{k-1}, FP64)
+  double* db[kMaxL];
+};
+
+// One workgroup = (row chunk, 16-row tile m of dW_k, layer k).  Each wave owns the
+// 16-column tiles j = wave, wave + 4, ... and runs the 16x16x4 MFMA over the chunk:
+// a lane fetches four consecutive rows of one column with one vector load, and the
+// four MFMA steps of a 16-row block take rows {v, 4 + v, 8 + v, 12 + v} in lane-group
+// order (any bijection of the summation index is the same sum).
+template <typename T>
+__global__ void __launch_bounds__(256) k_wgrad(const NetDev* __restrict__ nets, int net_index, WgradArgs wa) {
+  const NetDev& net = nets[net_index];
+  const int k = blockIdx.z + 1, mt = blockIdx.y, chunk = blockIdx.x;
+  const int L = net.L, NT = net.NT;
+  const int npk = net.np[k], npj = net.np[k - 1];
+  if (k > L || mt * 16 >= npk) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, n = lane & 15;
+  const int njt = npj / 16;
+  const size_t rp = wa.rows_pad;
+  gconst<T> tp = as_global((const T*)wa.tape);
+  gconst<T> colA = tp + (size_t)(ptape_col_a(k, NT) + mt * 16 + n) * rp;
+  const int cg0 = ptape_col_g(k - 1, L, NT, net.np[L]);
+  const int row0 = chunk * wa.chunk_rows;
+  const int row1 = min(row0 + wa.chunk_rows, (int)rp);
+  V4<T> acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = V4<T>{0, 0, 0, 0};
+  double bsum = 0.0;
+  for (int b = row0; b < row1; b += 16) {
+    const int rb = b + 4 * g;
+    V4<T> a4 = *(gconst<V4<T>>)(colA + rb);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (rb + v >= wa.rows) a4[v] = (T)0;
+    if (wave == 0) bsum += (double)a4[0] + (double)a4[1] + (double)a4[2] + (double)a4[3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int jt = wave + 4 * u;
+      if (jt < njt) {
+        V4<T> e4 = *(gconst<V4<T>>)(tp + (size_t)(cg0 + jt * 16 + n) * rp + rb);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          if (rb + v >= wa.rows) e4[v] = (T)0;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u] = mfma16(a4[v], e4[v], acc[u]);
+      }
+    }
+  }
+  T* part = (T*)wa.part + wa.poff[k - 1] + (size_t)chunk * npk * (npj + 1);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int jt = wave + 4 * u;
+    if (jt < njt) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = mt * 16 + nrn<T>(g, v);
+        part[(size_t)m * (npj + 1) + jt * 16 + n] = acc[u][v];
+      }
+    }
+  }
+  if (wave == 0) {
+    bsum += __shfl_xor(bsum, 16);
+    bsum += __shfl_xor(bsum, 32);
+    if (g == 0) part[(size_t)(mt * 16 + n) * (npj + 1) + npj] = (T)bsum;
+  }
+}
+
+// Sum of the per-chunk partials (FP64) into the natural-layout outputs.
+template <typename T>
+__global__ void k_wgrad_reduce(const NetDev* __restrict__ nets, int net_index, WgradArgs wa) {
+  const NetDev& net = nets[net_index];
+  const int k = blockIdx.y + 1;
+  if (k > net.L) return;
+  const int npk = net.np[k], npj = net.np[k - 1], nk = net.n[k], nj = net.n[k - 1];
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk * (nj + 1)) return;
+  const int m = e / (nj + 1), jj = e % (nj + 1);
+  const int j = jj < nj ? jj : npj;   // the last column holds the bias
+  const T* part = (const T*)wa.part + wa.poff[k - 1];
+  const size_t stride = (size_t)npk * (npj + 1);
+  double sum = 0.0;
+  for (int c = 0; c < wa.n_chunks; ++c) sum += (double)part[c * stride + (size_t)m * (npj + 1) + j];
+  if (jj < nj) wa.dW[k - 1][(size_t)m * nj + jj] = sum;
+  else wa.db[k - 1][m] = sum;
 }
 
 // ---------------------------------------------------------------------------
@@ -1379,7 +1542,8 @@ __global__ void k_swizzle(const T* __restrict__ Wn, int npk, int npkm1, int adjo
 template <typename T>
 __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npLm1,
                         const double* __restrict__ C, int q, int n_target, const double* __restrict__ A,
-                        const double* __restrict__ B, int n0, double* seedW, double* seedB, double* skip) {
+                        const double* __restrict__ B, int n0, int npL, double* seedW, double* seedB, double* skip,
+                        double* seedA) {
   const int R = 2 * q;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= R * npLm1) return;
@@ -1396,11 +1560,15 @@ __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int 
       a = C[(size_t)rr * n_target + o];
     }
     a *= sg;
+    if (m == 0) seedA[(size_t)r * npL + o] = a;
     g += a * (double)WL[(size_t)o * npLm1 + m];
     acc += a * (double)bL[o];
   }
   seedW[(size_t)r * npLm1 + m] = g;
-  if (m == 0) seedB[r] = acc;
+  if (m == 0) {
+    seedB[r] = acc;
+    for (int o = nL; o < npL; ++o) seedA[(size_t)r * npL + o] = 0.0;
+  }
   if (m < 16) {
     double sk = 0.0;
     if (A && m < n0)

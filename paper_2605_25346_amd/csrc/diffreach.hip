@@ -49,6 +49,8 @@ struct dr_ctx {
   dr::BatchDev batch{};
   bool have_batch = false;
   bool fused_ready = false;   // the last dr_bound_init also produced the plain spec rows
+  const void* pg_fn = nullptr;  // parameter-gradient instance of k_final (single network)
+  int pg_grid = 0;
   std::string err;
 };
 
@@ -89,7 +91,23 @@ struct Inst {
   static const void* dual() { return (const void*)&dr::k_final<T, NT, true>; }
   static const void* dual_cached() { return (const void*)&dr::k_final<T, NT, true, true>; }
   static const void* reach() { return (const void*)&dr::k_reach_dt<T, NT>; }
+  static const void* pgrad(bool cache) {
+    return cache ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
+  }
 };
+
+// k_final instance of the parameter gradient (the dual kernel that also writes the tapes)
+template <typename T>
+const void* pgrad_kernel_of(int NT, bool cache) {
+  switch (NT) {
+    case 2: return Inst<T, 2>::pgrad(cache);
+    case 4: return Inst<T, 4>::pgrad(cache);
+    case 6: return Inst<T, 6>::pgrad(cache);
+    case 8: return Inst<T, 8>::pgrad(cache);
+    case 16: return Inst<T, 16>::pgrad(cache);
+    default: return nullptr;
+  }
+}
 
 // wlds: the bound kernel with LDS weights; for the dual ascent: the item-cached instance
 template <typename T>
@@ -245,11 +263,12 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStre
   }
   // seeds of the final rows
   const int npLm1 = nd.np[L - 1];
-  double *seedW, *seedB, *skip, *C;
+  double *seedW, *seedB, *skip, *seedA, *C;
   hipError_t e;
   if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
   if ((e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
   if ((e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+  if ((e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess) return hip_fail(c, e, "hipMalloc");
   const int n_target = nw.A ? nw.n_state : nd.n[L];
   const double* Cdev = nw.spec;
   if (!Cdev) {
@@ -262,10 +281,10 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStre
   }
   const int tot = nd.R * npLm1;
   hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
-                     (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0],
-                     seedW, seedB, skip);
+                     (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0], nd.np[L],
+                     seedW, seedB, skip, seedA);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
-  nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip;
+  nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip; nd.seedA = seedA;
   return DR_OK;
 }
 
@@ -408,6 +427,18 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     tape_bytes += (waves * (size_t)(nd.L - 1) * nd.NT * 256 * tsz + 255) & ~(size_t)255;
   }
   if ((e = ctx_alloc(c, &c->tape, tape_bytes)) != hipSuccess) return bail(hip_fail(c, e, "hipMalloc tape"));
+  if (n_nets == 1) {
+    // the parameter-gradient instance of the dual kernel: same LDS, at most the dual
+    // kernel's grid (the per-wave g tape is sized for it)
+    const dr::NetDev& nd = c->hnet[0];
+    const bool cache = use_item_cache(c, nd);
+    c->pg_fn = c->prec == DR_PREC_F64 ? pgrad_kernel_of<double>(nd.NT, cache) : pgrad_kernel_of<float>(nd.NT, cache);
+    if (!c->pg_fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
+    const size_t lds = c->lds[Q_DUAL][0];
+    if (lds > 0 && (e = hipFuncSetAttribute(c->pg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+      return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+    c->pg_grid = std::min(persistent_grid(c, c->pg_fn, lds, Q_DUAL), c->grid[Q_DUAL][0]);
+  }
   if (n_nets > 1) {
     if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
       return bail(hip_fail(c, e, "hipEventCreate"));
@@ -543,6 +574,108 @@ dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, floa
   if (st != DR_OK) return st;
   if (status) {
     hipError_t e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * c->batch.n_sub, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return hip_fail(c, e, "status copy");
+  }
+  return DR_OK;
+}
+
+// ---- parameter gradient --------------------------------------------------------
+namespace {
+constexpr int kWgradChunk = 256;   // rows per workgroup of the contraction
+
+struct PgradLayout {
+  size_t rows_pad = 0, cols = 0, tape_bytes = 0, part_off = 0, total = 0;
+  int n_chunks = 0;
+  size_t poff[kMaxL] = {};
+};
+
+PgradLayout pgrad_layout(const dr_ctx* c, int S) {
+  PgradLayout pl;
+  const dr::NetDev& nd = c->hnet[0];
+  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
+  const size_t rows = (size_t)S * c->R;
+  pl.rows_pad = (rows + 15) / 16 * 16;
+  pl.cols = (size_t)dr::ptape_col_g(nd.L - 1, nd.L, nd.NT, nd.np[nd.L]) + 16 * nd.NT;
+  pl.tape_bytes = (pl.cols * pl.rows_pad * tsz + 255) & ~(size_t)255;
+  pl.n_chunks = (int)((pl.rows_pad + kWgradChunk - 1) / kWgradChunk);
+  size_t off = 0;
+  for (int k = 1; k <= nd.L; ++k) {
+    pl.poff[k - 1] = off;
+    off += (size_t)pl.n_chunks * nd.np[k] * (nd.np[k - 1] + 1);
+  }
+  pl.part_off = pl.tape_bytes;
+  pl.total = pl.part_off + ((off * tsz + 255) & ~(size_t)255);
+  return pl;
+}
+}  // namespace
+
+size_t dr_param_grad_workspace(const dr_ctx* c, int n_sub) {
+  if (!c || n_sub < 0 || c->n_nets != 1) return 0;
+  return pgrad_layout(c, std::max(n_sub, 1)).total;
+}
+
+dr_status dr_param_grad(dr_ctx* c, float* alpha, float* beta, int init_duals, const double* g_lb, const double* g_ub,
+                        double* lb, double* ub, double* const* dW, double* const* db, double* dxc, double* dxr,
+                        void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
+  if (c->n_nets != 1) return fail(c, DR_EINVAL, "the parameter gradient takes a single-network context");
+  if (c->R > 16) return fail(c, DR_ESHAPE, "spec rows 2q must be <= 16 for the spec chains");
+  const dr::NetDev& nd = c->hnet[0];
+  if (!dW || !db) return fail(c, DR_EINVAL, "dW/db is NULL");
+  for (int k = 0; k < nd.L; ++k)
+    if (!dW[k] || !db[k]) return fail(c, DR_EINVAL, "a dW/db layer pointer is NULL");
+  const int S = c->batch.n_sub;
+  if (S > 0 && (!alpha || !beta || !g_lb || !g_ub || !lb || !ub))
+    return fail(c, DR_EINVAL, "alpha/beta/g_lb/g_ub/lb/ub is NULL");
+  const PgradLayout pl = pgrad_layout(c, std::max(S, 1));
+  if (!workspace || workspace_bytes < pl.total) return fail(c, DR_EINVAL, "workspace is NULL or smaller than dr_param_grad_workspace");
+  if (((uintptr_t)workspace & 255) != 0) return fail(c, DR_EINVAL, "workspace must be 256-byte aligned");
+  dr::WgradArgs wa{};
+  wa.tape = workspace;
+  wa.rows_pad = pl.rows_pad;
+  wa.rows = S * c->R;
+  wa.chunk_rows = kWgradChunk;
+  wa.n_chunks = pl.n_chunks;
+  for (int k = 0; k < nd.L; ++k) { wa.poff[k] = pl.poff[k]; wa.dW[k] = dW[k]; wa.db[k] = db[k]; }
+  wa.part = (char*)workspace + pl.part_off;
+  int net_index = 0;
+  if (S > 0) {
+    dr::FinalArgs fa{};
+    fa.iters = 0; fa.lr = 0.0f; fa.init_duals = init_duals ? 1 : 0;
+    fa.alpha = alpha; fa.beta = beta; fa.lb = lb; fa.ub = ub;
+    fa.g_lb = g_lb; fa.g_ub = g_ub; fa.ptape = workspace; fa.rows_pad = pl.rows_pad; fa.dxc = dxc; fa.dxr = dxr;
+    fa.batch = c->batch;
+    fa.sc = c->sc;
+    fa.sc.st_out = nullptr;
+    fa.H_max = c->H_max;
+    fa.max_splits = std::max(c->max_splits, 1);
+    fa.q = c->q;
+    fa.queue = queue_of(c, Q_DUAL, 0);
+    fa.tape = c->tape;
+    void* args[] = {&c->dnet, &net_index, &fa};
+    dr_status st = launch_persistent(c, c->pg_fn, c->pg_grid, c->lds[Q_DUAL][0], args, fa.queue, stream);
+    if (st != DR_OK) return st;
+  }
+  // the contraction (rows of an empty batch sum to zero)
+  int max_mt = 1;
+  for (int k = 1; k <= nd.L; ++k) max_mt = std::max(max_mt, nd.np[k] / 16);
+  const dim3 gw(pl.n_chunks, max_mt, nd.L);
+  if (c->prec == DR_PREC_F64)
+    hipLaunchKernelGGL(dr::k_wgrad<double>, gw, dim3(256), 0, stream, c->dnet, net_index, wa);
+  else
+    hipLaunchKernelGGL(dr::k_wgrad<float>, gw, dim3(256), 0, stream, c->dnet, net_index, wa);
+  int max_el = 1;
+  for (int k = 1; k <= nd.L; ++k) max_el = std::max(max_el, nd.n[k] * (nd.n[k - 1] + 1));
+  const dim3 gr((max_el + 255) / 256, nd.L);
+  if (c->prec == DR_PREC_F64)
+    hipLaunchKernelGGL(dr::k_wgrad_reduce<double>, gr, dim3(256), 0, stream, c->dnet, net_index, wa);
+  else
+    hipLaunchKernelGGL(dr::k_wgrad_reduce<float>, gr, dim3(256), 0, stream, c->dnet, net_index, wa);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "parameter-gradient kernels");
+  if (status && S > 0) {
+    e = hipMemcpyAsync(status, c->sc.st, sizeof(uint32_t) * S, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return hip_fail(c, e, "status copy");
   }
   return DR_OK;

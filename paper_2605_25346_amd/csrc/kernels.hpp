@@ -85,6 +85,7 @@ struct NetDev {
   int np[kMaxL + 1];         // padded widths (hidden: 16 NT; input/output: multiple of 16)
   const double* seedW;       // R x np_{L-1}: g = a_L W_L of every final row (FP64)
   const double* seedB;       // R: a_L . b_L
+  const double* seedA;       // R x np_L: a_L, the multipliers of every final row on the network output
   const double* skip;        // R x 16: (+-c) A for the closed loop, zeros otherwise
   const double* A;           // n_state x n_0 (closed loop) or null
   int n_state;

@@ -195,6 +195,113 @@ def test_duals_and_gradient_at_random_point(cfg):
         ctx.close()
 
 
+def _param_grad_case(wl, precision, subset, seed):
+    """dr_param_grad at random duals and random row weights against the oracle's
+    param_gradient summed over the same subdomains.  Rows within floating-point reach
+    of a branch (a g or w component near zero, or a subdomain near a stability
+    decision) get weight zero on both sides; only ``subset`` carries weights."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    net = wl.nets[0]
+    q = crown.default_spec(net).shape[0]
+    S, R, H = wl.batch.n_sub, 2 * q, sum(net.hidden)
+    ms = int(np.max(np.diff(wl.batch.split_ptr)))
+    rng = np.random.default_rng(seed)
+    al, be = random_duals(seed, S, R, H, max(ms, 1), beta_scale=0.5)
+    omega = np.zeros((S, R))
+    ref = dict(dW=[np.zeros((o, i)) for i, o in zip(net.widths[:-1], net.widths[1:])],
+               db=[np.zeros(o) for o in net.widths[1:]],
+               absW=[np.zeros((o, i)) for i, o in zip(net.widths[:-1], net.widths[1:])],
+               dxc=np.zeros((S, net.widths[0])), dxr=np.zeros((S, net.widths[0])),
+               sxc=np.zeros((S, net.widths[0])))
+    ktol = 1e-9 if precision == "f64" else 1e-5
+    used = 0
+    for s in subset:
+        xc, xr = wl.batch.x_center[s], wl.batch.x_radius[s]
+        sp = wl.batch.splits_of(s)
+        bounds, _, status = crown.intermediate_bounds(net, xc, xr, sp)
+        if status or near_tie(bounds, 1e-9 if precision == "f64" else 1e-4, slope=False):
+            continue
+        w_s = rng.normal(size=R)
+        _, _, _, out = crown.evaluate_duals(net, bounds, xc, xr, al[s], be[s, :, :len(sp)], sp)
+        kink = np.zeros(R, bool)
+        for t in out["res"]["tape"]:
+            sc = np.maximum(np.abs(t["g"]).max(axis=1, keepdims=True), 1e-300)
+            kink |= np.any((np.abs(t["g"]) <= ktol * sc) & (t["g"] != 0), axis=1)
+        w = out["res"]["w"]
+        kink |= np.any(np.abs(w) <= ktol * np.maximum(np.abs(w).max(axis=1, keepdims=True), 1e-300), axis=1)
+        w_s[kink] = 0.0
+        omega[s] = w_s
+        pg = crown.param_gradient(net, bounds, xc, xr, al[s], be[s, :, :len(sp)], w_s, sp)
+        for k in range(net.n_layers):
+            ref["dW"][k] += pg["dW"][k]
+            ref["db"][k] += pg["db"][k]
+            ref["absW"][k] += pg["absW"][k]
+        ref["dxc"][s], ref["dxr"][s] = pg["dxc"], pg["dxr"]
+        ref["sxc"][s] = np.abs(w_s) @ np.abs(w)
+        used += 1
+    # margins off: the gradient is that of the bound in exact arithmetic, and the
+    # outward margins of the intermediate bounds move the chord slopes of nearly
+    # stable neurons by more than the FP64 rounding of the chains
+    ctx = _ctx(wl, precision, S, margins=False)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha = torch.tensor(al, dtype=torch.float32, device="cuda")
+    beta = torch.tensor(be, dtype=torch.float32, device="cuda")
+    g_lb = torch.tensor(omega[:, :q], device="cuda")
+    g_ub = torch.tensor(-omega[:, q:], device="cuda")     # ub = -lb of the upper row
+    lb, ub, dW, dbias, dxc, dxr, st = ctx.dr_param_grad(alpha, beta, g_lb, g_ub)
+    torch.cuda.synchronize()
+    got = dict(dW=[t.cpu().numpy() for t in dW], db=[t.cpu().numpy() for t in dbias], dxc=dxc.cpu().numpy(),
+               dxr=dxr.cpu().numpy(), lb=lb.cpu().numpy(), ub=ub.cpu().numpy())
+    ctx.close()
+    return ref, got, used
+
+
+def _check_param_grad(ref, got, tol, tag):
+    errs = []
+    for k in range(len(ref["dW"])):
+        scale = ref["absW"][k] + 1e-300
+        e = np.abs(got["dW"][k] - ref["dW"][k]) / np.maximum(scale, 1e-12 * scale.max())
+        assert np.all(e <= tol), (tag, "dW", k, e.max())
+        errs.append(e.max())
+        sb = np.abs(ref["db"][k]).max() + 1e-300
+        assert np.all(np.abs(got["db"][k] - ref["db"][k]) <= tol * max(sb, 1e-12)), (tag, "db", k)
+    sx = np.maximum(ref["sxc"], 1e-300)
+    assert np.all(np.abs(got["dxc"] - ref["dxc"]) <= tol * sx + 1e-300), (tag, "dxc")
+    assert np.all(np.abs(got["dxr"] - ref["dxr"]) <= tol * sx + 1e-300), (tag, "dxr")
+    print_stats(f"{tag} dW (rel. to the absolute sum)", errs)
+
+
+@pytest.mark.parametrize("cfg", [1, 2, 3])
+def test_param_grad_matches_oracle(cfg):
+    """Weighted gradient w.r.t. W, b, x_center, x_radius at a fixed relaxation: cfg1
+    (closed loop: rows through B and the skip A), cfg2 (64-wide), cfg3 (128-wide)."""
+    require_gpu()
+    n_sub = {1: 16, 2: 24, 3: 24}[cfg]
+    wl = config_workload(cfg, n_sub=n_sub)
+    for precision, tol in (("f64", 1e-9), ("f32", 2e-4)):
+        if cfg == 1 and precision == "f32":
+            continue   # the closed-loop configuration is FP64 on both sides
+        ref, got, used = _param_grad_case(wl, precision, range(n_sub), seed=31 + cfg)
+        assert used >= n_sub // 2
+        _check_param_grad(ref, got, tol, f"cfg{cfg} {precision}")
+
+
+def test_param_grad_full_size_sampled():
+    """The 2048-subdomain batch of the 8-128x4-4 network (the size the benchmark
+    times): weights on 12 sampled subdomains, zero elsewhere, so the oracle sums only
+    those; every other subdomain must contribute nothing."""
+    require_gpu()
+    wl = config_workload(3)
+    rng = np.random.default_rng(5)
+    subset = np.sort(rng.choice(wl.batch.n_sub, 12, replace=False))
+    ref, got, used = _param_grad_case(wl, "f32", subset, seed=41)
+    assert used >= 6
+    _check_param_grad(ref, got, 2e-4, "cfg3 full size f32")
+    others = np.setdiff1d(np.arange(wl.batch.n_sub), subset)
+    assert np.all(got["dxc"][others] == 0.0) and np.all(got["dxr"][others] == 0.0)
+
+
 def _traj_kink(net, bounds, xc, xr, sp, iters, lr, ktol=1e-9):
     """Run the oracle ascent and report rows whose trajectory passes within 1e-6 of a
     kink (a g or w component changing sign), where FP rounding may pick a branch."""
@@ -568,3 +675,48 @@ def test_fused_spec_rows_equal_separate_kernel(precision):
         ctx.close()
     for a, b in zip(*out):
         np.testing.assert_array_equal(a, b)
+
+
+def test_param_grad_graph_replay():
+    """bound_init + parameter gradient captured in one graph: replays (with eager work
+    between them) reproduce the eager weight, bias and box gradients bit for bit (the
+    contraction sums fixed chunks in a fixed order, no atomics)."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(3, n_sub=40)
+    ctx = _ctx(wl, "f32", 40)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    rng = np.random.default_rng(2)
+    g_lb = torch.tensor(rng.normal(size=(40, ctx.q)), device="cuda")
+    g_ub = torch.tensor(rng.normal(size=(40, ctx.q)), device="cuda")
+    out, ws = ctx.param_grad_outputs()
+    flat = lambda: [out[0], out[1], *out[2], *out[3], out[4], out[5]]
+
+    def step():
+        ctx.dr_bound_init(db)
+        ctx.dr_param_grad(alpha, beta, g_lb, g_ub, init_duals=True, out=out, workspace=ws)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in flat()]
+    assert all(torch.isfinite(t).all() for t in ref[2:])
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        for t in flat():
+            t.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(flat(), ref):
+            assert torch.equal(a, b), f"replay {rep} differs"
+        step()
+        torch.cuda.synchronize()
+    ctx.close()
