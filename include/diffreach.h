@@ -82,8 +82,9 @@ typedef struct {
   int wdtype;                 /* DR_DTYPE_F32 or DR_DTYPE_F64: element type of W and b */
   const void* const* W;       /* HOST array of L device pointers, W_k row-major n_k x n_{k-1} */
   const void* const* b;       /* HOST array of L device pointers, b_k of n_k */
-  const double* A;            /* device n_state x n_0 (closed loop) or NULL */
-  const double* B;            /* device n_state x n_L (closed loop) or NULL */
+  const double* A;            /* device n_state x n_0 (closed loop) or NULL; read by later calls, so
+                                 it must stay valid while the context lives */
+  const double* B;            /* device n_state x n_L (closed loop) or NULL; same lifetime as A */
   int n_state;                /* rows of A and B, 1 <= n_state <= n_0; 0 without closed loop.  The
                                  network input is v = [x; u]: the first n_state entries are the
                                  state, the remaining n_0 - n_state exogenous inputs (actions),
@@ -200,6 +201,15 @@ dr_status dr_param_grad(dr_ctx* ctx, float* alpha, float* beta, int init_duals, 
                         const double* g_ub, double* lb, double* ub, double* const* dW, double* const* db,
                         double* dxc, double* dxr, void* workspace, size_t workspace_bytes, uint32_t* status,
                         hipStream_t stream);
+
+/* Replace the weights and biases of network `net_index` of the context in place
+ * (same widths; W, b and wdtype read as in dr_create; the closed-loop A, B and the
+ * spec stay those given at creation, and A, B must stay valid).  The copies, swizzles
+ * and final-row seeds are rebuilt by kernels on `stream` into the existing buffers:
+ * nothing is allocated, so a training step (set weights, dr_bound_init,
+ * dr_param_grad) can be captured in one HIP graph.  The state of the last
+ * dr_bound_init is invalidated.  DR_ESHAPE if the widths differ. */
+dr_status dr_set_weights(dr_ctx* ctx, int net_index, const dr_network* net, hipStream_t stream);
 
 /* Step a8: stepwise closed-loop reachability (Algorithm "Reachability of DT
  * Dynamics") with linear Taylor models: each box is normalised to the TM

@@ -89,6 +89,7 @@ class BoundContext:
                 nw.spec, nw.n_spec = C.data_ptr(), C.shape[0]
                 keep.append(C)
             self._keep.append(keep)
+        self._structs = structs
         opt = B.dr_options()
         opt.precision = B.DR_PREC_F32 if precision == "f32" else B.DR_PREC_F64
         opt.intermediate = B.DR_INTER_CROWN_IBP if intermediate == "crown_ibp" else B.DR_INTER_IBP
@@ -249,6 +250,23 @@ class BoundContext:
         self._check(self.lib.dr_get_margins(self.ctx, _ptr(m), _stream()))
         return m
 
+    def dr_set_weights(self, net_index, Ws, bs):
+        """Replace network ``net_index``'s weights and biases (device tensors of the same
+        shapes, or arrays) in place; A, B and the spec stay those of creation."""
+        wdt = torch.float32 if self.precision == "f32" else torch.float64
+        Ws = [torch.as_tensor(W, device=self.device).to(wdt).contiguous() for W in Ws]
+        bs = [torch.as_tensor(b, device=self.device).to(wdt).contiguous() for b in bs]
+        old = self._structs[net_index]
+        nw = B.dr_network()
+        nw.n_layers = old.n_layers
+        nw.widths = old.widths
+        nw.wdtype = B.DR_DTYPE_F32 if self.precision == "f32" else B.DR_DTYPE_F64
+        Wp = (ctypes.c_void_p * len(Ws))(*[W.data_ptr() for W in Ws])
+        bp = (ctypes.c_void_p * len(bs))(*[b.data_ptr() for b in bs])
+        nw.W, nw.b = Wp, bp
+        self._keep_weights = (Ws, bs, Wp, bp)   # read by kernels queued on the stream
+        self._check(self.lib.dr_set_weights(self.ctx, int(net_index), ctypes.byref(nw), _stream()))
+
     # ---- conveniences ----------------------------------------------------------------
     def crown(self, batch: DeviceBatch):
         """a1-a6 for a batch: plain CROWN lower/upper bounds and status."""
@@ -281,3 +299,36 @@ class DualBound(torch.autograd.Function):
         q = ctx_.q
         w = torch.cat([g_lb, -g_ub], dim=1).to(ga.dtype)     # d ub = - d lb_row
         return ga * w[:, :, None], gb * w[:, :, None], None
+
+
+class CrownBounds(torch.autograd.Function):
+    """Plain-CROWN bounds of a batch (lb, ub: S x q) as a differentiable function of a
+    single-network context's weights and biases.
+
+    forward: dr_set_weights, dr_bound_init, and the bound at the adaptive slopes;
+    backward: dr_param_grad with the incoming gradients as row weights, i.e. the
+    gradient at a fixed relaxation (the intermediate bounds and slopes of the forward
+    pass are constants)."""
+
+    @staticmethod
+    def forward(ctx_, bctx: BoundContext, batch: DeviceBatch, *params):
+        L = len(params) // 2
+        Ws, bs = params[:L], params[L:]
+        bctx.dr_set_weights(0, [W.detach() for W in Ws], [b.detach() for b in bs])
+        bctx.dr_bound_init(batch)
+        alpha, beta = bctx.new_duals()
+        lb, ub, _, _, _ = bctx.dr_optimize_duals(0, 0.0, alpha, beta, init_duals=True)
+        ctx_.bctx, ctx_.duals = bctx, (alpha, beta)
+        ctx_.dtypes = [p.dtype for p in params]
+        return lb, ub
+
+    @staticmethod
+    def backward(ctx_, g_lb, g_ub):
+        bctx = ctx_.bctx
+        alpha, beta = ctx_.duals
+        g_lb = torch.zeros_like(g_lb) if g_lb is None else g_lb
+        g_ub = torch.zeros_like(g_ub) if g_ub is None else g_ub
+        _, _, dW, db, _, _, _ = bctx.dr_param_grad(alpha, beta, g_lb.contiguous(), g_ub.contiguous(),
+                                                   init_duals=False)
+        grads = [g.to(dt) for g, dt in zip(list(dW) + list(db), ctx_.dtypes)]
+        return (None, None, *grads)

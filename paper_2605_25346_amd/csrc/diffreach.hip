@@ -49,6 +49,8 @@ struct dr_ctx {
   dr::BatchDev batch{};
   bool have_batch = false;
   bool fused_ready = false;   // the last dr_bound_init also produced the plain spec rows
+  const double* spec_dev[kMaxNets] = {};   // context-owned spec of each network (the default [I] if none given)
+  const double* B_dev[kMaxNets] = {};      // the caller's closed-loop B (valid for the context's lifetime)
   const void* pg_fn = nullptr;  // parameter-gradient instance of k_final (single network)
   int pg_grid = 0;
   std::string err;
@@ -234,16 +236,27 @@ dr_status check_batch(dr_ctx* c, const dr_batch* b) {
   return DR_OK;
 }
 
+// Device copies of one network's parameters and the seeds of its final rows: the
+// natural padded copy, the forward and adjoint swizzles, and the seeds (a_L, a_L W_L,
+// a_L b_L, skip).  `alloc` creates the buffers (context creation); without it the
+// existing buffers are refilled (dr_set_weights: no allocation, capturable).
 template <typename T>
-dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStream_t stream) {
+dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net_i, bool alloc, hipStream_t stream) {
   const int L = nw.n_layers;
+  hipError_t e;
   for (int k = 1; k <= L; ++k) {
     const int npk = nd.np[k], npkm1 = nd.np[k - 1];
-    T *Wn, *bn, *Wf, *Wa;
-    hipError_t e;
-    if ((e = ctx_alloc(c, &Wn, sizeof(T) * npk * npkm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = ctx_alloc(c, &bn, sizeof(T) * npk)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
     const int total = npk * npkm1;
+    T *Wn, *bn, *Wf, *Wa;
+    if (alloc) {
+      if ((e = ctx_alloc(c, &Wn, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if ((e = ctx_alloc(c, &bn, sizeof(T) * npk)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if ((e = ctx_alloc(c, &Wf, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      if ((e = ctx_alloc(c, &Wa, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+      nd.Wn[k - 1] = Wn; nd.bn[k - 1] = bn; nd.Wf[k - 1] = Wf; nd.Wa[k - 1] = Wa;
+    } else {
+      Wn = (T*)nd.Wn[k - 1]; bn = (T*)nd.bn[k - 1]; Wf = (T*)nd.Wf[k - 1]; Wa = (T*)nd.Wa[k - 1];
+    }
     const int blocks = (std::max(total, npk) + 255) / 256;
     if (nw.wdtype == DR_DTYPE_F64)
       hipLaunchKernelGGL((dr::k_copy_weights<T, double>), dim3(blocks), dim3(256), 0, stream,
@@ -254,37 +267,44 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, hipStre
                          (const float*)nw.W[k - 1], (const float*)nw.b[k - 1], nd.n[k], nd.n[k - 1], npk, npkm1,
                          Wn, bn);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "weight copy");
-    if ((e = ctx_alloc(c, &Wf, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = ctx_alloc(c, &Wa, sizeof(T) * total)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
     hipLaunchKernelGGL((dr::k_swizzle<T>), dim3((total + 255) / 256), dim3(256), 0, stream, Wn, npk, npkm1, 0, Wf);
     hipLaunchKernelGGL((dr::k_swizzle<T>), dim3((total + 255) / 256), dim3(256), 0, stream, Wn, npk, npkm1, 1, Wa);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "weight swizzle");
-    nd.Wn[k - 1] = Wn; nd.bn[k - 1] = bn; nd.Wf[k - 1] = Wf; nd.Wa[k - 1] = Wa;
   }
   // seeds of the final rows
   const int npLm1 = nd.np[L - 1];
-  double *seedW, *seedB, *skip, *seedA, *C;
-  hipError_t e;
-  if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-  if ((e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-  if ((e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-  if ((e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-  const int n_target = nw.A ? nw.n_state : nd.n[L];
-  const double* Cdev = nw.spec;
-  if (!Cdev) {
-    std::vector<double> I((size_t)nd.q * n_target, 0.0);
-    for (int i = 0; i < nd.q; ++i) I[(size_t)i * n_target + i] = 1.0;
-    if ((e = ctx_alloc(c, &C, sizeof(double) * I.size())) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = hipMemcpy(C, I.data(), sizeof(double) * I.size(), hipMemcpyHostToDevice)) != hipSuccess)
-      return hip_fail(c, e, "hipMemcpy");
-    Cdev = C;
+  double *seedW, *seedB, *skip, *seedA;
+  if (alloc) {
+    if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip; nd.seedA = seedA;
+  } else {
+    seedW = (double*)nd.seedW; seedB = (double*)nd.seedB; skip = (double*)nd.skip; seedA = (double*)nd.seedA;
   }
+  // the spec: a context-owned copy of the caller's (or the default [I], q = n_target)
+  const int n_target = nd.n_state > 0 ? nd.n_state : nd.n[L];
+  if (alloc) {
+    double* C;
+    if ((e = ctx_alloc(c, &C, sizeof(double) * nd.q * n_target)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if (nw.spec) {
+      e = hipMemcpyAsync(C, nw.spec, sizeof(double) * nd.q * n_target, hipMemcpyDeviceToDevice, stream);
+    } else {
+      std::vector<double> I((size_t)nd.q * n_target, 0.0);
+      for (int i = 0; i < nd.q; ++i) I[(size_t)i * n_target + i] = 1.0;
+      e = hipMemcpy(C, I.data(), sizeof(double) * I.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "spec copy");
+    c->spec_dev[net_i] = C;
+    c->B_dev[net_i] = nw.B;
+  }
+  const double* Cdev = c->spec_dev[net_i];
   const int tot = nd.R * npLm1;
   hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
-                     (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nw.A, nw.B, nd.n[0], nd.np[L],
+                     (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nd.A, c->B_dev[net_i], nd.n[0], nd.np[L],
                      seedW, seedB, skip, seedA);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
-  nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip; nd.seedA = seedA;
   return DR_OK;
 }
 
@@ -374,7 +394,8 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     }
     c->H_max = std::max(c->H_max, nd.H);
     c->Hp_max = std::max(c->Hp_max, nd.Hp);
-    dr_status st = c->prec == DR_PREC_F64 ? setup_weights<double>(c, nw, nd, stream) : setup_weights<float>(c, nw, nd, stream);
+    dr_status st = c->prec == DR_PREC_F64 ? setup_weights<double>(c, nw, nd, i, true, stream)
+                                          : setup_weights<float>(c, nw, nd, i, true, stream);
     if (st != DR_OK) return bail(st);
   }
   if ((e = ctx_alloc(c, &c->dnet, sizeof(dr::NetDev) * n_nets)) != hipSuccess) return bail(hip_fail(c, e, "hipMalloc"));
@@ -449,6 +470,28 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   }
   if ((e = hipStreamSynchronize(stream)) != hipSuccess) return bail(hip_fail(c, e, "set-up"));
   *out = c;
+  return DR_OK;
+}
+
+dr_status dr_set_weights(dr_ctx* c, int net_index, const dr_network* nw, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (net_index < 0 || net_index >= c->n_nets) return fail(c, DR_EINVAL, "net_index out of range");
+  if (!nw || !nw->widths || !nw->W || !nw->b) return fail(c, DR_EINVAL, "network arrays are NULL");
+  dr::NetDev& nd = c->hnet[net_index];
+  if (nw->n_layers != nd.L) return fail(c, DR_ESHAPE, "n_layers differs from the network of the context");
+  for (int k = 0; k <= nd.L; ++k)
+    if (nw->widths[k] != nd.n[k]) return fail(c, DR_ESHAPE, "widths differ from the network of the context");
+  if (nw->wdtype != DR_DTYPE_F32 && nw->wdtype != DR_DTYPE_F64) return fail(c, DR_EINVAL, "bad wdtype");
+  if (nw->wdtype == DR_DTYPE_F64 && c->prec == DR_PREC_F32)
+    return fail(c, DR_EINVAL, "FP64 weights need precision DR_PREC_F64 (the network is its weights)");
+  for (int k = 0; k < nd.L; ++k)
+    if (!nw->W[k] || !nw->b[k]) return fail(c, DR_EINVAL, "W/b pointer NULL");
+  dr_status st = c->prec == DR_PREC_F64 ? setup_weights<double>(c, *nw, nd, net_index, false, stream)
+                                        : setup_weights<float>(c, *nw, nd, net_index, false, stream);
+  if (st != DR_OK) return st;
+  // state computed with the old weights is stale
+  c->have_batch = false;
+  c->fused_ready = false;
   return DR_OK;
 }
 

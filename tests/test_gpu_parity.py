@@ -720,3 +720,83 @@ def test_param_grad_graph_replay():
         step()
         torch.cuda.synchronize()
     ctx.close()
+
+
+def test_set_weights_equals_fresh_context():
+    """dr_set_weights into a context created with other weights gives bit-identical
+    bounds to a context created with the new weights (open loop, and the closed loop
+    whose seeds go through B)."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    for cfg in (3, 1):
+        wl_a = config_workload(cfg, n_sub=32)
+        wl_b = config_workload(cfg, n_sub=32)
+        net_b = wl_b.nets[0]
+        rng = np.random.default_rng(9)
+        Ws = [(W * rng.uniform(0.8, 1.2, W.shape)).astype(np.float32).astype(np.float64) for W in net_b.Ws]
+        bs = [(b + rng.normal(0, 0.05, b.shape)).astype(np.float32).astype(np.float64) for b in net_b.bs]
+        net_b.Ws, net_b.bs = Ws, bs
+        precision = "f64" if cfg == 1 else "f32"
+        ctx_a = _ctx(wl_a, precision, 32)
+        ctx_b = _ctx(wl_b, precision, 32)
+        ctx_a.dr_set_weights(0, Ws, bs)
+        db = DeviceBatch(wl_a.batch)
+        lb_a, ub_a, st_a, _ = ctx_a.crown(db)
+        lb_b, ub_b, st_b, _ = ctx_b.crown(db)
+        torch.cuda.synchronize()
+        assert torch.equal(lb_a, lb_b) and torch.equal(ub_a, ub_b) and torch.equal(st_a, st_b), cfg
+        ctx_a.close(); ctx_b.close()
+
+
+def test_crown_bounds_autograd_and_descent():
+    """CrownBounds (set weights -> bounds; backward = dr_param_grad) on the 8-128x4-4
+    network: its gradient of the width loss mean log(1 + V) equals a direct
+    dr_param_grad call with the loss's row weights, and a few small gradient steps on
+    the weights lower the loss (the reachability-regularisation use of the gradient)."""
+    from paper_2605_25346_amd.api import CrownBounds, DeviceBatch
+    require_gpu()
+    wl = config_workload(3, n_sub=64)
+    ctx = _ctx(wl, "f32", 64)
+    db = DeviceBatch(wl.batch)
+    net = wl.nets[0]
+    params = [torch.tensor(W, dtype=torch.float32, device="cuda", requires_grad=True) for W in net.Ws] + \
+             [torch.tensor(b, dtype=torch.float32, device="cuda", requires_grad=True) for b in net.bs]
+
+    def loss_of(lb, ub, keep):
+        V = (ub - lb).sum(dim=1)
+        return torch.log1p(V[keep]).mean()
+
+    lb, ub = CrownBounds.apply(ctx, db, *params)
+    keep = torch.isfinite(lb).all(dim=1) & torch.isfinite(ub).all(dim=1)
+    assert int(keep.sum()) >= 32
+    loss = loss_of(lb, ub, keep)
+    loss.backward()
+    # the same gradient through the entry point directly
+    lb2, ub2 = lb.detach().clone().requires_grad_(), ub.detach().clone().requires_grad_()
+    loss_of(lb2, ub2, keep).backward()
+    alpha, beta = ctx.new_duals()
+    ctx.dr_optimize_duals(0, 0.0, alpha, beta, init_duals=True)
+    _, _, dW, dbias, _, _, _ = ctx.dr_param_grad(alpha, beta, lb2.grad, ub2.grad)
+    torch.cuda.synchronize()
+    L = len(net.Ws)
+    for k in range(L):
+        np.testing.assert_allclose(params[k].grad.cpu().numpy(), dW[k].cpu().numpy().astype(np.float32), rtol=1e-6,
+                                   atol=1e-12)
+        np.testing.assert_allclose(params[L + k].grad.cpu().numpy(), dbias[k].cpu().numpy().astype(np.float32),
+                                   rtol=1e-6, atol=1e-12)
+    # a few gradient steps on the weights
+    losses = [float(loss.detach())]
+    step = 0.1     # length of each step in the joint parameter norm (weights have norm ~30)
+    for _ in range(5):
+        with torch.no_grad():
+            gn = torch.sqrt(sum((p.grad.double() ** 2).sum() for p in params))
+            for p in params:
+                p -= (step / gn).float() * p.grad
+                p.grad = None
+        lb, ub = CrownBounds.apply(ctx, db, *params)
+        loss = loss_of(lb, ub, keep)
+        loss.backward()
+        losses.append(float(loss.detach()))
+    print(f"[reach-loss descent] {' '.join(f'{v:.4f}' for v in losses)}", flush=True)
+    assert losses[-1] < losses[0]
+    ctx.close()
