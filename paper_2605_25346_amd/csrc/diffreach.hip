@@ -308,6 +308,32 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   return DR_OK;
 }
 
+constexpr int kWgradChunk = 256;   // rows per workgroup of the contraction
+
+struct PgradLayout {
+  size_t rows_pad = 0, cols = 0, tape_bytes = 0, part_off = 0, total = 0;
+  int n_chunks = 0;
+  size_t poff[kMaxL] = {};
+};
+
+PgradLayout pgrad_layout(const dr_ctx* c, int S) {
+  PgradLayout pl;
+  const dr::NetDev& nd = c->hnet[0];
+  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
+  const size_t rows = (size_t)S * c->R;
+  pl.rows_pad = (rows + 15) / 16 * 16;
+  pl.cols = (size_t)dr::ptape_col_g(nd.L - 1, nd.L, nd.NT, nd.np[nd.L]) + 16 * nd.NT;
+  pl.tape_bytes = (pl.cols * pl.rows_pad * tsz + 255) & ~(size_t)255;
+  pl.n_chunks = (int)((pl.rows_pad + kWgradChunk - 1) / kWgradChunk);
+  size_t off = 0;
+  for (int k = 1; k <= nd.L; ++k) {
+    pl.poff[k - 1] = off;
+    off += (size_t)pl.n_chunks * nd.np[k] * (nd.np[k - 1] + 1);
+  }
+  pl.part_off = pl.tape_bytes;
+  pl.total = pl.part_off + ((off * tsz + 255) & ~(size_t)255);
+  return pl;
+}
 }  // namespace
 
 extern "C" {
@@ -622,35 +648,6 @@ dr_status dr_optimize_duals(dr_ctx* c, int iters, float lr, int init_duals, floa
   return DR_OK;
 }
 
-// ---- parameter gradient --------------------------------------------------------
-namespace {
-constexpr int kWgradChunk = 256;   // rows per workgroup of the contraction
-
-struct PgradLayout {
-  size_t rows_pad = 0, cols = 0, tape_bytes = 0, part_off = 0, total = 0;
-  int n_chunks = 0;
-  size_t poff[kMaxL] = {};
-};
-
-PgradLayout pgrad_layout(const dr_ctx* c, int S) {
-  PgradLayout pl;
-  const dr::NetDev& nd = c->hnet[0];
-  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
-  const size_t rows = (size_t)S * c->R;
-  pl.rows_pad = (rows + 15) / 16 * 16;
-  pl.cols = (size_t)dr::ptape_col_g(nd.L - 1, nd.L, nd.NT, nd.np[nd.L]) + 16 * nd.NT;
-  pl.tape_bytes = (pl.cols * pl.rows_pad * tsz + 255) & ~(size_t)255;
-  pl.n_chunks = (int)((pl.rows_pad + kWgradChunk - 1) / kWgradChunk);
-  size_t off = 0;
-  for (int k = 1; k <= nd.L; ++k) {
-    pl.poff[k - 1] = off;
-    off += (size_t)pl.n_chunks * nd.np[k] * (nd.np[k - 1] + 1);
-  }
-  pl.part_off = pl.tape_bytes;
-  pl.total = pl.part_off + ((off * tsz + 255) & ~(size_t)255);
-  return pl;
-}
-}  // namespace
 
 size_t dr_param_grad_workspace(const dr_ctx* c, int n_sub) {
   if (!c || n_sub < 0 || c->n_nets != 1) return 0;
