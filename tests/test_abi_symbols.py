@@ -46,3 +46,20 @@ def test_last_error_without_context():
     st = lib.dr_create(None, None, 0, None, None)
     assert st == binding.DR_EINVAL
     assert b"NULL" in lib.dr_last_error(None)
+
+
+def test_null_context_is_rejected_before_any_device_call():
+    """Every entry point that takes a context returns DR_EINVAL for a NULL one (and
+    the size query 0) without touching a device."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("library not built")
+    lib = binding.load()
+    N = None
+    assert lib.dr_bound_init(N, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_propagate_backward(N, N, N, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_optimize_duals(N, 0, 0.0, 0, N, N, N, N, N, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_param_grad(N, N, N, 0, N, N, N, N, N, N, N, N, N, 0, N, N) == binding.DR_EINVAL
+    assert lib.dr_set_weights(N, 0, N, N) == binding.DR_EINVAL
+    assert lib.dr_param_grad_workspace(N, 16) == 0
+    assert lib.dr_reach_dt(N, N, 1, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_hidden_max(N) == 0 and lib.dr_spec_rows(N) == 0
