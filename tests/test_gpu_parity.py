@@ -800,3 +800,54 @@ def test_crown_bounds_autograd_and_descent():
     print(f"[reach-loss descent] {' '.join(f'{v:.4f}' for v in losses)}", flush=True)
     assert losses[-1] < losses[0]
     ctx.close()
+
+
+def test_param_grad_edge_cases():
+    """Parameter gradient on a two-neuron network (z = [x; x], y = h1 + h2, FP64):
+    an infeasible subdomain with a nonzero weight contributes nothing, an unstable and
+    an all-active subdomain match the oracle, and an empty batch gives zero gradients."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import Batch, Network
+    require_gpu()
+    net = Network([np.array([[1.0], [1.0]]), np.array([[1.0, 1.0]])], [np.zeros(2), np.zeros(1)])
+    xc = np.array([[-1.5], [0.5], [1.5]])
+    xr = np.array([[0.5], [1.5], [0.5]])
+    # subdomain 0: split z_1[0] >= 0 on x in [-2, -1] (infeasible); 1: x in [-1, 2]; 2: x in [1, 2]
+    batch = Batch(xc, xr, np.array([0, 1, 1, 1], np.int32), np.array([1], np.int32), np.array([0], np.int32),
+                  np.array([1], np.int32), np.zeros(3, np.int32))
+    ctx = BoundContext([net], precision="f64", max_sub=3, max_splits=1)
+    db = DeviceBatch(batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    omega = np.array([[5.0, -3.0], [0.7, -1.1], [1.3, 0.4]])      # rows: lower, upper (R = 2)
+    g_lb = torch.tensor(omega[:, :1], device="cuda")
+    g_ub = torch.tensor(-omega[:, 1:], device="cuda")
+    lb, ub, dW, dbias, dxc, dxr, st = ctx.dr_param_grad(alpha, beta, g_lb, g_ub, init_duals=True)
+    torch.cuda.synchronize()
+    assert st.cpu().numpy()[0] & 1 and np.isposinf(lb.cpu().numpy()[0, 0])
+    ref_dW = [np.zeros((2, 1)), np.zeros((1, 2))]
+    ref_db = [np.zeros(2), np.zeros(1)]
+    for s in (1, 2):
+        bounds, _, status = crown.intermediate_bounds(net, xc[s], xr[s])
+        assert status == 0
+        pg = crown.param_gradient(net, bounds, xc[s], xr[s], crown.default_alpha(net, bounds, 2), np.zeros((2, 0)),
+                                  omega[s])
+        for k in range(2):
+            ref_dW[k] += pg["dW"][k]
+            ref_db[k] += pg["db"][k]
+        np.testing.assert_allclose(dxc.cpu().numpy()[s], pg["dxc"], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dxr.cpu().numpy()[s], pg["dxr"], rtol=1e-12, atol=1e-12)
+    assert np.all(dxc.cpu().numpy()[0] == 0) and np.all(dxr.cpu().numpy()[0] == 0)
+    for k in range(2):
+        np.testing.assert_allclose(dW[k].cpu().numpy(), ref_dW[k], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dbias[k].cpu().numpy(), ref_db[k], rtol=1e-12, atol=1e-12)
+    # empty batch: the contraction over no rows
+    empty = Batch(np.zeros((0, 1)), np.zeros((0, 1)), np.zeros(1, np.int32), np.zeros(0, np.int32),
+                  np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+    ctx.dr_bound_init(DeviceBatch(empty))
+    a0, b0 = ctx.new_duals()
+    z = torch.zeros(0, 1, dtype=torch.float64, device="cuda")
+    _, _, dW0, db0, _, _, _ = ctx.dr_param_grad(a0, b0, z, z, init_duals=True)
+    torch.cuda.synchronize()
+    assert all(float(t.abs().max()) == 0.0 for t in dW0 + db0)
+    ctx.close()
