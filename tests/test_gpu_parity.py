@@ -851,3 +851,64 @@ def test_param_grad_edge_cases():
     torch.cuda.synchronize()
     assert all(float(t.abs().max()) == 0.0 for t in dW0 + db0)
     ctx.close()
+
+
+def test_training_step_graph_replay():
+    """A whole training step — dr_set_weights, dr_bound_init, dr_param_grad — captured
+    in one graph: replays match the eager step bit for bit, and after an in-place update
+    of the weight tensors a replay matches the eager step at the new weights (the graph
+    reads the caller's weights; nothing was allocated during capture)."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    wl = config_workload(3, n_sub=32)
+    ctx = _ctx(wl, "f32", 32)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    alpha, beta = ctx.new_duals()
+    net = wl.nets[0]
+    Ws = [torch.tensor(W, dtype=torch.float32, device="cuda") for W in net.Ws]
+    bs = [torch.tensor(b, dtype=torch.float32, device="cuda") for b in net.bs]
+    rng = np.random.default_rng(4)
+    g_lb = torch.tensor(rng.normal(size=(32, ctx.q)), device="cuda")
+    g_ub = torch.tensor(rng.normal(size=(32, ctx.q)), device="cuda")
+    out, ws = ctx.param_grad_outputs()
+    flat = lambda: [out[0], out[1], *out[2], *out[3], out[4], out[5]]
+
+    def step():
+        ctx.dr_set_weights(0, Ws, bs)
+        ctx.dr_bound_init(db)
+        ctx.dr_param_grad(alpha, beta, g_lb, g_ub, init_duals=True, out=out, workspace=ws)
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in flat()]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(2):
+        for t in flat():
+            t.fill_(7.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(flat(), ref):
+            assert torch.equal(a, b), f"replay {rep} differs"
+    with torch.no_grad():
+        for W in Ws:
+            W.mul_(0.98)
+    step()
+    torch.cuda.synchronize()
+    ref2 = [t.clone() for t in flat()]
+    assert not torch.equal(ref2[2], ref[2])
+    for t in flat():
+        t.fill_(7.0)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for a, b in zip(flat(), ref2):
+        assert torch.equal(a, b), "replay after the weight update differs"
+    ctx.close()
