@@ -1111,25 +1111,42 @@ __global__ void __launch_bounds__(256) k_wgrad(const NetDev* __restrict__ nets, 
 #pragma unroll
   for (int u = 0; u < 4; ++u) acc[u] = V4<T>{0, 0, 0, 0};
   double bsum = 0.0;
-  for (int b = row0; b < row1; b += 16) {
+  // the loads of block b + 16 are issued before the products of block b
+  auto load = [&](int b, V4<T>& a4, V4<T> (&e4)[4]) {
     const int rb = b + 4 * g;
-    V4<T> a4 = *(gconst<V4<T>>)(colA + rb);
+    a4 = *(gconst<V4<T>>)(colA + rb);
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
-      if (rb + v >= wa.rows) a4[v] = (T)0;
-    if (wave == 0) bsum += (double)a4[0] + (double)a4[1] + (double)a4[2] + (double)a4[3];
+    for (int u = 0; u < 4; ++u) {
+      const int jt = wave + 4 * u;
+      if (jt < njt) e4[u] = *(gconst<V4<T>>)(tp + (size_t)(cg0 + jt * 16 + n) * rp + rb);
+    }
+  };
+  V4<T> a_c, e_c[4], a_n, e_n[4];
+  if (row0 < row1) load(row0, a_c, e_c);
+  for (int b = row0; b < row1; b += 16) {
+    if (b + 16 < row1) load(b + 16, a_n, e_n);
+    const int rb = b + 4 * g;
+    if (b + 16 > wa.rows) {   // the block holds rows past the last one: read them as zero
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (rb + v >= wa.rows) {
+          a_c[v] = (T)0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) e_c[u][v] = (T)0;
+        }
+    }
+    if (wave == 0) bsum += (double)a_c[0] + (double)a_c[1] + (double)a_c[2] + (double)a_c[3];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int jt = wave + 4 * u;
       if (jt < njt) {
-        V4<T> e4 = *(gconst<V4<T>>)(tp + (size_t)(cg0 + jt * 16 + n) * rp + rb);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-          if (rb + v >= wa.rows) e4[v] = (T)0;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u] = mfma16(a4[v], e4[v], acc[u]);
+        for (int v = 0; v < 4; ++v) acc[u] = mfma16(a_c[v], e_c[u][v], acc[u]);
       }
     }
+    a_c = a_n;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) e_c[u] = e_n[u];
   }
   T* part = (T*)wa.part + wa.poff[k - 1] + (size_t)chunk * npk * (npj + 1);
 #pragma unroll
@@ -1164,6 +1181,7 @@ __global__ void k_wgrad_reduce(const NetDev* __restrict__ nets, int net_index, W
   const T* part = (const T*)wa.part + wa.poff[k - 1];
   const size_t stride = (size_t)npk * (npj + 1);
   double sum = 0.0;
+#pragma unroll 8
   for (int c = 0; c < wa.n_chunks; ++c) sum += (double)part[c * stride + (size_t)m * (npj + 1) + j];
   if (jj < nj) wa.dW[k - 1][(size_t)m * nj + jj] = sum;
   else wa.db[k - 1][m] = sum;

@@ -308,7 +308,7 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   return DR_OK;
 }
 
-constexpr int kWgradChunk = 256;   // rows per workgroup of the contraction
+constexpr int kWgradChunk = 512;   // rows per workgroup of the contraction
 
 struct PgradLayout {
   size_t rows_pad = 0, cols = 0, tape_bytes = 0, part_off = 0, total = 0;
