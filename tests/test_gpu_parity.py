@@ -912,3 +912,45 @@ def test_training_step_graph_replay():
     for a, b in zip(flat(), ref2):
         assert torch.equal(a, b), "replay after the weight update differs"
     ctx.close()
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_replay_of_gpu_intermediate_bounds(cfg):
+    """Replay: the oracle's final bound (FP64, exact relaxation) computed from the GPU's own
+    intermediate bounds isolates the FP32 spec chains.  The GPU's rigorous lower bound may
+    not exceed it by more than the relaxation rounding (chord slope rounded to FP32,
+    intercept rounded up: ~1e-6 relative), and it lies below it by at most the GPU's
+    reported margin plus that rounding (the margin accounts for the gap)."""
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    n_sub = {2: 64, 3: 24}[cfg]
+    wl = config_workload(cfg, n_sub=n_sub)
+    net = wl.nets[0]
+    res = _run_crown(wl, "f32", margins=True)
+    offs = np.concatenate([[0], np.cumsum(net.hidden)])
+    gaps, used = [], 0
+    for s in range(n_sub):
+        if res["status"][s]:
+            continue
+        bounds = [(res["l"][s, offs[k]:offs[k + 1]], res["u"][s, offs[k]:offs[k + 1]]) for k in range(len(net.hidden))]
+        sp = wl.batch.splits_of(s)
+        o = crown.final_bounds(net, bounds, wl.batch.x_center[s], wl.batch.x_radius[s], splits=sp, tape=True)
+        q = o["lb"].size
+        lb_gpu = np.concatenate([res["lb"][s], -res["ub"][s]])
+        lb_rep = o["rowlb"]
+        marg = res["margin"][s, :2 * q]
+        # the two relaxations differ by FP32 rounding of the chord slope and intercept:
+        # at most ~2^-23 relative per unstable neuron, times |g| (|t| + max(|l|, |u|))
+        scale = np.ones(2 * q)
+        for tp, (kind, sl, t, _), (l, u) in zip(o["res"]["tape"], o["relax"], bounds):
+            uns = kind == crown.UNSTABLE
+            scale += (np.abs(tp["g"]) * np.where(uns, np.abs(t) + np.maximum(np.abs(l), np.abs(u)), 0.0)).sum(1)
+        slack = 1e-6 * scale
+        assert np.all(lb_gpu <= lb_rep + slack), (cfg, s, lb_gpu - lb_rep, slack)
+        # computed - exact is within the margin, so the gap is at most twice the margin
+        assert np.all(lb_rep - lb_gpu <= 2 * marg + slack), (cfg, s, lb_rep - lb_gpu, marg)
+        gaps.append((lb_rep - lb_gpu) / np.maximum(marg, 1e-300))
+        used += 1
+    print_stats(f"cfg{cfg} replay gap / margin", gaps)
+    assert used >= n_sub // 2
+    res["ctx"].close()
