@@ -72,6 +72,18 @@ def bound_init_flops(nets, net_id, rows):
     return tot
 
 
+def dense_flops(nets, net_id, status, R):
+    """Context count: every hidden neuron of layers 2..L-1 gets its two CROWN rows
+    (not only the IBP-unstable unsplit ones), plus the spec rows."""
+    tot = 0
+    for s in range(len(net_id)):
+        if status[s] & 9:
+            continue
+        w = nets[int(net_id[s])].widths
+        tot += sum(2 * w[k] * chain_flops_per_row(w, k) for k in range(2, len(w) - 1)) + R * final_flops_per_row(w)
+    return tot
+
+
 def final_flops(nets, net_id, status, R):
     tot = 0
     for s in range(len(net_id)):
@@ -160,7 +172,9 @@ def headline(torch, args, precision="f32"):
     # the spec rows run fused at the end of k_bound_init: its work is both
     flops_bi += flops_fin
     achieved = flops_bi / (bi_ms * 1e-3) / 1e12
+    flops_dense = dense_flops(wl.nets, wl.batch.net_id, status, ctx.R)
     res = dict(ms=ms, S=S, bi_ms=bi_ms, flops_bi=flops_bi, flops_final=flops_fin, achieved=achieved,
+               flops_dense=flops_dense, achieved_dense=flops_dense / (bi_ms * 1e-3) / 1e12,
                step_tflops=flops_bi / (ms * 1e-3) / 1e12, infeasible=int(np.sum(status & 1)))
     ctx.close()
     return res, wl
@@ -527,7 +541,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": hl["achieved"], "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
                      "frac": hl["achieved"] / PEAK_TFLOPS["f32"],
                      "traffic": TRAFFIC["k_bound_init_bytes"] if kernel_src_sha() == TRAFFIC["src_sha"] else None,
-                     "kernel": "k_bound_init", "kernel_ms": hl["bi_ms"], "flops_per_launch": hl["flops_bi"]},
+                     "kernel": "k_bound_init", "kernel_ms": hl["bi_ms"], "flops_per_launch": hl["flops_bi"],
+                     "flops_dense_rows_per_launch": hl["flops_dense"],
+                     "frac_dense_rows": hl["achieved_dense"] / PEAK_TFLOPS["f32"]},
         "cpu_baseline": cb,
         "extra": extra,
     }
