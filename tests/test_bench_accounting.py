@@ -1,0 +1,34 @@
+"""The benchmark's algorithmic FLOP counts against hand-computed values (CPU only)."""
+import numpy as np
+
+import bench
+
+
+def test_chain_and_spec_row_flops():
+    w = [6, 64, 64, 64, 3]                        # the headline network
+    # an intermediate row of layer 2 multiplies by W_1 only; of layer 3 by W_2 and W_1
+    assert bench.chain_flops_per_row(w, 2) == 2 * 64 * 6
+    assert bench.chain_flops_per_row(w, 3) == 2 * 64 * 6 + 2 * 64 * 64
+    # a spec row: W_3, W_2, W_1 (its product with W_4 is formed once per network)
+    assert bench.final_flops_per_row(w) == 2 * 64 * 6 + 2 * 64 * 64 * 2
+
+
+def test_dense_row_count_matches_the_closed_form():
+    """Dense rows: two per neuron of layers 2..L-1 plus 2q spec rows; 1.348 MFLOP per
+    subdomain of the headline network (6 spec rows)."""
+    class Net:
+        widths = [6, 64, 64, 64, 3]
+    per = 128 * (2 * 64 * 6) + 128 * (2 * 64 * 6 + 2 * 64 * 64) + 6 * (2 * 64 * 6 + 2 * 64 * 64 * 2)
+    assert per == 1_348_096
+    status = np.array([0, 0, 1, 8, 0])            # infeasible and bad-split subdomains are not counted
+    assert bench.dense_flops([Net()], np.zeros(5, np.int32), status, 6) == 3 * per
+
+
+def test_needed_row_count_uses_the_chain_rows():
+    class Net:
+        widths = [6, 64, 64, 64, 3]
+    rows = np.zeros((2, 8), np.int32)
+    rows[0, 1], rows[0, 2] = 10, 20               # rows of hidden layers 2 and 3
+    rows[1, 2] = 4
+    got = bench.bound_init_flops([Net()], np.zeros(2, np.int32), rows)
+    assert got == 10 * (2 * 64 * 6) + 20 * (2 * 64 * 6 + 2 * 64 * 64) + 4 * (2 * 64 * 6 + 2 * 64 * 64)
