@@ -254,11 +254,12 @@ constexpr int kPrefetchBytes = 256;
 constexpr int kWideSplit = 4;
 constexpr int kWideDist = 2;
 // The same for FP32 layers of 128 neurons (2 groups, distance 2: 5% faster ascent than
-// the whole-tile double buffer) and of 64 / 96 neurons.
+// the whole-tile double buffer) and of 64 / 96 neurons (2 groups, distance 2: 2-4% faster
+// candidate reach and mixed-batch kernels).
 constexpr int kMidSplit = 2;
 constexpr int kMidDist = 2;
-constexpr int kNarrowSplit = 1;
-constexpr int kNarrowDist = 1;
+constexpr int kNarrowSplit = 2;
+constexpr int kNarrowDist = 2;
 template <typename T> __host__ __device__ constexpr int prefetch_bytes() { return sizeof(T) == 4 ? kPrefetchBytes : 128; }
 template <typename T, int MT, int KT, typename P, typename B>
 __device__ __forceinline__ void gemm_k(P Wsw, const B& cur, T (&nxt)[MT][4], int lane) {
