@@ -7,7 +7,11 @@ fallback for it.  Parity status per function:
 * crown.relu_relaxation, ibp_next, affine_box, concretize_box, backward,
   intermediate_bounds, final_bounds, crown: pinned (closed forms, linear and
   all-stable networks, zero-radius boxes, brute force by pattern enumeration + LP,
-  dense sampling).
+  dense sampling).  The intermediate-bound values themselves: the exact affine
+  range of the second layer behind a stably active first layer (and equality with
+  the network whose two affine layers are merged), and equality of every
+  second-layer CROWN bound with max(interval bound, LP optimum over the first
+  layer's relaxation lines); deeper rows lie between CROWN and that LP.
 * crown.gradient / evaluate_duals: pinned (central finite differences, and an
   independent torch-FP64 autograd of the same bound).
 * crown.param_gradient: pinned (central finite differences of final_bounds at a
@@ -15,7 +19,11 @@ fallback for it.  Parity status per function:
   with its intermediate bounds recomputed, and the closed form of the affine map).
 * crown.optimize_duals: pinned (one-neuron and split hand cases, strong duality
   against the LP optimum, soundness against brute force).
-* tm.reach_dt: pinned (B = 0 closed form A^t x +- |A^t| r, all-stable linear
-  closed loop, dense sampled rollouts).
+* tm.reach_dt, tm.tm_intermediate_bounds: pinned (B = 0 closed form
+  A^t x +- |A^t| r, all-stable linear closed loop, dense sampled rollouts; the
+  hand-worked shared-slope steps of x' = +-relu(x) on [-1, 2] fixing the Taylor
+  model, both offsets and the interval product; a network whose second layer is
+  exactly zero over the TM; second-layer bounds = max(interval bound, LP over the
+  parallel relaxation)).
 """
 from . import crown, exact, tm  # noqa: F401
