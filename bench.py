@@ -39,7 +39,7 @@ TRAFFIC = {"src_sha": "4ff5e1f5bd6ff017", "k_bound_init_bytes": 2.16e6 + 30.93e6
 def kernel_src_sha():
     import hashlib
     h = hashlib.sha256()
-    for f in ("bound_kernels.hip", "kernels.hpp"):
+    for f in ("bound_kernels.hpp", "kernels.hpp"):
         with open(os.path.join(ROOT, "paper_2605_25346_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

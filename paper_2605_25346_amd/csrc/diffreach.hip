@@ -1,5 +1,6 @@
 // Host side of the C-ABI (libdiffreach.so): validation, context set-up, launches.
-// The kernels live in bound_kernels.hip, compiled into this translation unit.
+// The chain kernels are reached through the instance handles of instances.h (their own
+// translation units); the small kernels of aux_kernels.hpp are compiled in here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,8 +11,9 @@
 #include <string>
 #include <vector>
 
-#include "bound_kernels.hip"
+#include "aux_kernels.hpp"
 #include "diffreach.h"
+#include "instances.h"
 
 using dr::kMaxL;
 using dr::kMaxNets;
@@ -77,56 +79,34 @@ hipError_t ctx_alloc(dr_ctx* c, P** p, size_t bytes) {
 }
 
 // ---- kernel instance selection -------------------------------------------------
-// k_bound_init instances: narrow networks (NT <= 4) run one subdomain per wavefront
-// with the weights staged in LDS when they fit; wider ones one subdomain per workgroup.
-template <typename T, int NT>
-struct Inst {
-  static const void* bound() {
-    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, false, 64>;
-    return (const void*)&dr::k_bound_init<T, NT, false, 256>;
+// The instance set of one chain type and tile count (see instances.hip).
+template <typename T>
+const void* instance(int NT, int kind, int variant) {
+  constexpr bool F = sizeof(T) == 4;
+  switch (NT) {
+    case 2: return F ? dr_instance_float_2(kind, variant) : dr_instance_double_2(kind, variant);
+    case 4: return F ? dr_instance_float_4(kind, variant) : dr_instance_double_4(kind, variant);
+    case 6: return F ? dr_instance_float_6(kind, variant) : dr_instance_double_6(kind, variant);
+    case 8: return F ? dr_instance_float_8(kind, variant) : dr_instance_double_8(kind, variant);
+    case 16: return F ? dr_instance_float_16(kind, variant) : dr_instance_double_16(kind, variant);
+    default: return nullptr;
   }
-  static const void* bound_lds() {
-    if constexpr (NT <= 4) return (const void*)&dr::k_bound_init<T, NT, true, 64>;
-    return nullptr;
-  }
-  static const void* final_() { return (const void*)&dr::k_final<T, NT, false>; }
-  static const void* dual() { return (const void*)&dr::k_final<T, NT, true>; }
-  static const void* dual_cached() { return (const void*)&dr::k_final<T, NT, true, true>; }
-  static const void* reach() { return (const void*)&dr::k_reach_dt<T, NT>; }
-  static const void* pgrad(bool cache) {
-    return cache ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
-  }
-};
+}
 
 // k_final instance of the parameter gradient (the dual kernel that also writes the tapes)
 template <typename T>
 const void* pgrad_kernel_of(int NT, bool cache) {
-  switch (NT) {
-    case 2: return Inst<T, 2>::pgrad(cache);
-    case 4: return Inst<T, 4>::pgrad(cache);
-    case 6: return Inst<T, 6>::pgrad(cache);
-    case 8: return Inst<T, 8>::pgrad(cache);
-    case 16: return Inst<T, 16>::pgrad(cache);
-    default: return nullptr;
-  }
+  return instance<T>(NT, DR_KIND_PGRAD, cache ? 1 : 0);
 }
 
 // wlds: the bound kernel with LDS weights; for the dual ascent: the item-cached instance
 template <typename T>
 const void* kernel_of(int kind, int NT, bool wlds) {
-#define DR_CASE(N)                                  \
-  case N:                                           \
-    switch (kind) {                                 \
-      case Q_BOUND: return wlds ? Inst<T, N>::bound_lds() : Inst<T, N>::bound(); \
-      case Q_FINAL: return Inst<T, N>::final_();    \
-      case Q_DUAL: return wlds ? Inst<T, N>::dual_cached() : Inst<T, N>::dual(); \
-      default: return Inst<T, N>::reach();          \
-    }
-  switch (NT) {
-    DR_CASE(2) DR_CASE(4) DR_CASE(6) DR_CASE(8) DR_CASE(16)
-    default: return nullptr;
-  }
-#undef DR_CASE
+  static_assert(Q_BOUND == DR_KIND_BOUND && Q_FINAL == DR_KIND_FINAL && Q_DUAL == DR_KIND_DUAL &&
+                    Q_REACH == DR_KIND_REACH,
+                "queue kinds and kernel kinds share their numbering");
+  const bool variant = (kind == Q_BOUND || kind == Q_DUAL) && wlds;
+  return instance<T>(NT, kind, variant ? 1 : 0);
 }
 
 const void* kernel_for(const dr_ctx* c, int kind, int NT, bool wlds = false) {

@@ -373,4 +373,91 @@ __host__ __device__ inline int lds_w_offset(int k, int NT) {
 }
 __host__ __device__ inline int lds_w_count(int L, int NT) { return lds_w_offset(L, NT); }
 
+
+// ---------------------------------------------------------------------------
+// Per-subdomain shared state of k_bound_init / k_reach_dt (dynamic LDS).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SubLds {
+  V4<T>* rel;     // Hp, permuted
+  double* l;      // Hp natural
+  double* u;      // Hp natural
+  int* slot;      // Hp permuted
+  double* ibl;    // 16 NT
+  double* ibu;
+  double* v;
+  double* hc;     // 16 NT: centre of relu(h) of the previous layer
+  double* hr;     // 16 NT: radius
+  int* U;         // 16 NT
+  double* xc;     // 16
+  double* xr;     // 16
+  int* misc;      // 8 ints: [0] item, [1] flags, [2..5] wave counts
+  __host__ __device__ static size_t bytes(int Hp, int NT) {
+    size_t b = (size_t)Hp * (sizeof(V4<T>) + 2 * sizeof(double) + sizeof(int)) +
+               (size_t)16 * NT * (5 * sizeof(double) + sizeof(int)) + 32 * sizeof(double) + 8 * sizeof(int);
+    return (b + 63) & ~(size_t)63;
+  }
+  __device__ void carve(char* base, int Hp, int NT) {
+    rel = (V4<T>*)base; base += (size_t)Hp * sizeof(V4<T>);
+    l = (double*)base; base += (size_t)Hp * sizeof(double);
+    u = (double*)base; base += (size_t)Hp * sizeof(double);
+    ibl = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    ibu = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    v = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    hc = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    hr = (double*)base; base += (size_t)16 * NT * sizeof(double);
+    xc = (double*)base; base += 16 * sizeof(double);
+    xr = (double*)base; base += 16 * sizeof(double);
+    slot = (int*)base; base += (size_t)Hp * sizeof(int);
+    U = (int*)base; base += (size_t)16 * NT * sizeof(int);
+    misc = (int*)base;
+  }
+};
+
+struct FinalArgs {
+  BatchDev batch;
+  Scratch sc;
+  unsigned* queue;
+  // a5 outputs
+  double* lam_lo; double* acc_lo; double* lam_hi; double* acc_hi;
+  // a7
+  int iters; float lr; int init_duals;
+  float* alpha; float* beta; double* lb; double* ub; float* galpha; float* gbeta;
+  uint32_t* status;
+  void* tape;               // per-wave tape of g values (a7)
+  int H_max;                // alpha row stride
+  int max_splits;           // beta row stride
+  int q;
+  // parameter gradient (k_final with PGRAD): row weights, the column-major per-row
+  // tapes of multipliers a^(k) (weighted) and adjoints e^(k), input gradients
+  const double* g_lb; const double* g_ub;
+  void* ptape; size_t rows_pad;
+  double* dxc; double* dxr;
+};
+
+// LDS copy of a dual-ascent work item's relaxation and split slots (P subdomains):
+// they do not change over the iterations.
+template <typename T> __host__ __device__ constexpr size_t item_cache_bytes(int P, int Hp) {
+  return ((size_t)P * Hp * (sizeof(V4<T>) + sizeof(int)) + 15) & ~(size_t)15;
+}
+
+// Column offsets of the parameter-gradient tapes (rows_pad entries per column): the
+// multipliers a^(k) of layers k = 1..L, then the adjoints e^(k) of layers k = 0..L-1
+// (e^(0) = xc - sgn(w) xr); every hidden layer has 16 NT columns, the input 16.
+__host__ __device__ inline int ptape_col_a(int k, int NT) { return (k - 1) * 16 * NT; }
+__host__ __device__ inline int ptape_col_g(int k, int L, int NT, int npL) {
+  return (L - 1) * 16 * NT + npL + (k == 0 ? 0 : 16 + (k - 1) * 16 * NT);
+}
+
+struct ReachArgs {
+  BatchDev batch;
+  Scratch sc;
+  unsigned* queue;
+  int horizon;
+  double* boxes;            // S x (horizon + 1) x n_state x 2
+  uint32_t* status;
+  const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
+};
+
+
 }  // namespace dr
