@@ -61,6 +61,8 @@ class BoundContext:
                  margins=True, fuse_spec=True):
         self.lib = B.load()
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.precision = precision
         wdt = torch.float32 if precision == "f32" else torch.float64
         self._keep = []
@@ -114,6 +116,9 @@ class BoundContext:
         self.max_splits = max_splits
         self.n_layers = max(n.n_layers for n in nets)
         self.batch: Optional[DeviceBatch] = None
+        # bumped by every call that replaces the state later calls read (the batch, its
+        # relaxation or the weights), so holders of that state can tell it is stale
+        self.generation = 0
 
     def close(self):
         if getattr(self, "ctx", None) is not None:
@@ -133,6 +138,7 @@ class BoundContext:
     def dr_bound_init(self, batch: DeviceBatch, status=None) -> torch.Tensor:
         """a1-a4 for the batch; returns the per-subdomain status (every entry is written)."""
         self.batch = batch
+        self.generation += 1
         if status is None:
             status = torch.empty(max(batch.n_sub, 1), dtype=torch.int32, device=self.device)
         b = batch.struct()
@@ -167,7 +173,25 @@ class BoundContext:
         beta = torch.zeros(S, R, max(self.max_splits, 1), dtype=torch.float32, device=self.device)
         return alpha, beta
 
+    def _check_duals(self, alpha, beta):
+        """alpha: S x R x max(H_max, 1), beta: S x R x max(max_splits, 1), both contiguous
+        FP32 on this context's device (the kernels index them with these strides)."""
+        if self.batch is None:
+            raise RuntimeError("dr_bound_init has not been called")
+        S, R = self.batch.n_sub, self.R
+        for name, t, cols in (("alpha", alpha, max(self.H_max, 1)), ("beta", beta, max(self.max_splits, 1))):
+            if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.device != self.device:
+                raise ValueError(f"{name} must be a float32 tensor on {self.device}")
+            if tuple(t.shape) != (S, R, cols) or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous {S} x {R} x {cols} tensor, got {tuple(t.shape)}")
+
+    def _check_rows(self, name, t):
+        S, q = self.batch.n_sub, self.q
+        if tuple(t.shape) != (S, q):
+            raise ValueError(f"{name} must be {S} x {q}, got {tuple(t.shape)}")
+
     def dr_optimize_duals(self, iters, lr, alpha, beta, init_duals=True, grads=False, out=None):
+        self._check_duals(alpha, beta)
         S, q = self.batch.n_sub, self.q
         if out is None:
             out = (torch.empty(S, q, dtype=torch.float64, device=self.device),
@@ -196,6 +220,7 @@ class BoundContext:
         """Weighted gradient of the bounds w.r.t. weights, biases and boxes at a fixed
         relaxation.  Returns (lb, ub, dW list, db list, dxc, dxr, status); dW[k-1] is
         n_k x n_{k-1} FP64."""
+        self._check_duals(alpha, beta)
         S = self.batch.n_sub
         if out is None or workspace is None:
             out2, ws2 = self.param_grad_outputs()
@@ -204,6 +229,8 @@ class BoundContext:
         lb, ub, dW, db, dxc, dxr, status = out
         g_lb = torch.as_tensor(g_lb, dtype=torch.float64, device=self.device).contiguous()
         g_ub = torch.as_tensor(g_ub, dtype=torch.float64, device=self.device).contiguous()
+        self._check_rows("g_lb", g_lb)
+        self._check_rows("g_ub", g_ub)
         self._pg_keep = (g_lb, g_ub)
         Wp = (ctypes.c_void_p * len(dW))(*[t.data_ptr() for t in dW])
         bp = (ctypes.c_void_p * len(db))(*[t.data_ptr() for t in db])
@@ -217,6 +244,7 @@ class BoundContext:
         """Stepwise reach; ``u`` (S x horizon x (n_0 - n_state), FP64 device) selects
         dr_reach_dt_exo for networks with exogenous inputs."""
         self.batch = batch
+        self.generation += 1
         S = batch.n_sub
         if boxes is None:
             boxes = torch.empty(S, horizon + 1, max(self.n_state, 1), 2, dtype=torch.float64, device=self.device)
@@ -266,6 +294,7 @@ class BoundContext:
         nw.W, nw.b = Wp, bp
         self._keep_weights = (Ws, bs, Wp, bp)   # read by kernels queued on the stream
         self._check(self.lib.dr_set_weights(self.ctx, int(net_index), ctypes.byref(nw), _stream()))
+        self.generation += 1
 
     # ---- conveniences ----------------------------------------------------------------
     def crown(self, batch: DeviceBatch):
@@ -308,7 +337,9 @@ class CrownBounds(torch.autograd.Function):
     forward: dr_set_weights, dr_bound_init, and the bound at the adaptive slopes;
     backward: dr_param_grad with the incoming gradients as row weights, i.e. the
     gradient at a fixed relaxation (the intermediate bounds and slopes of the forward
-    pass are constants)."""
+    pass are constants).  The backward pass reads the context's state, so a context
+    serves one pending forward at a time: a backward after a later forward (or any call
+    that replaces the batch or the weights) on the same context raises RuntimeError."""
 
     @staticmethod
     def forward(ctx_, bctx: BoundContext, batch: DeviceBatch, *params):
@@ -319,12 +350,19 @@ class CrownBounds(torch.autograd.Function):
         alpha, beta = bctx.new_duals()
         lb, ub, _, _, _ = bctx.dr_optimize_duals(0, 0.0, alpha, beta, init_duals=True)
         ctx_.bctx, ctx_.duals = bctx, (alpha, beta)
+        ctx_.generation = bctx.generation
         ctx_.dtypes = [p.dtype for p in params]
         return lb, ub
 
     @staticmethod
     def backward(ctx_, g_lb, g_ub):
         bctx = ctx_.bctx
+        if bctx.generation != ctx_.generation:
+            # the backward pass differentiates the context's current relaxation and weights:
+            # another forward (or a weight or batch change) on the same context replaced them
+            raise RuntimeError("CrownBounds.backward: the context's state changed after this forward "
+                               "(another forward, dr_bound_init, dr_set_weights or dr_reach_dt ran on it); "
+                               "use one BoundContext per pending forward")
         alpha, beta = ctx_.duals
         g_lb = torch.zeros_like(g_lb) if g_lb is None else g_lb
         g_ub = torch.zeros_like(g_ub) if g_ub is None else g_ub

@@ -219,42 +219,67 @@ __global__ void k_swizzle(const T* __restrict__ Wn, int npk, int npkm1, int adjo
   out[e] = adjoint ? Wn[(size_t)m * npkm1 + kk] : Wn[(size_t)kk * npkm1 + m];
 }
 
-// Seeds of the final rows [c; -c]: a_L = c (or c B), g = a_L W_L, acc = a_L . b_L, skip = c A.
+// Seeds of the final rows [c; -c]: a_L = c (or c B), g = a_L W_L, acc = a_L . b_L, skip = c A,
+// and a priori bounds of their FP64 rounding (gamma_n = n u / (1 - n u), u = 2^-53, for a
+// dot product of n terms: |fl(x.y) - x.y| <= gamma_n |x|.|y|):
+//   |a_o - c.B_o| <= da_o = gamma_{n_target} sum_t |c_t| |B_to|,
+//   seedWe_m = gamma_{n_L} sum_o |a_o| |W_om| + sum_o da_o |W_om|   (bounds |g_m - (cB) W_L[:, m]|),
+//   seedBe   = gamma_{n_L} sum_o |a_o| |b_o|  + sum_o da_o |b_o|,
+//   skipE_m  = gamma_{n_target} sum_t |c_t| |A_tm|.
+// The sums of non-negative terms are inflated by 2^-40 relative to cover their own rounding.
+__device__ __forceinline__ double gamma64(int n) {
+  const double nu = n * 0x1p-53;
+  return nu / (1.0 - nu);
+}
 template <typename T>
 __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npLm1,
                         const double* __restrict__ C, int q, int n_target, const double* __restrict__ A,
                         const double* __restrict__ B, int n0, int npL, double* seedW, double* seedB, double* skip,
-                        double* seedA) {
+                        double* seedA, double* seedWe, double* seedBe, double* skipE) {
   const int R = 2 * q;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= R * npLm1) return;
   const int r = e / npLm1, m = e % npLm1;
   const int rr = r < q ? r : r - q;
   const double sg = r < q ? 1.0 : -1.0;
+  const double ga = gamma64(n_target), gl = gamma64(nL);
   // multipliers on the network output
-  double g = 0.0, acc = 0.0;
+  double g = 0.0, acc = 0.0, eg = 0.0, eb = 0.0;
   for (int o = 0; o < nL; ++o) {
-    double a = 0.0;
+    double a = 0.0, aa = 0.0;
     if (B) {
-      for (int t = 0; t < n_target; ++t) a += C[(size_t)rr * n_target + t] * B[(size_t)t * nL + o];
+      for (int t = 0; t < n_target; ++t) {
+        a += C[(size_t)rr * n_target + t] * B[(size_t)t * nL + o];
+        aa += fabs(C[(size_t)rr * n_target + t]) * fabs(B[(size_t)t * nL + o]);
+      }
     } else {
       a = C[(size_t)rr * n_target + o];
     }
     a *= sg;
+    const double da = B ? ga * aa : 0.0;
     if (m == 0) seedA[(size_t)r * npL + o] = a;
-    g += a * (double)WL[(size_t)o * npLm1 + m];
-    acc += a * (double)bL[o];
+    const double w = (double)WL[(size_t)o * npLm1 + m], bo = (double)bL[o];
+    g += a * w;
+    acc += a * bo;
+    eg += (gl * fabs(a) + da) * fabs(w);
+    eb += (gl * fabs(a) + da) * fabs(bo);
   }
   seedW[(size_t)r * npLm1 + m] = g;
+  seedWe[(size_t)r * npLm1 + m] = eg * (1.0 + 0x1p-40);
   if (m == 0) {
     seedB[r] = acc;
+    seedBe[r] = eb * (1.0 + 0x1p-40);
     for (int o = nL; o < npL; ++o) seedA[(size_t)r * npL + o] = 0.0;
   }
   if (m < 16) {
-    double sk = 0.0;
+    double sk = 0.0, ske = 0.0;
     if (A && m < n0)
-      for (int t = 0; t < n_target; ++t) sk += C[(size_t)rr * n_target + t] * A[(size_t)t * n0 + m];
+      for (int t = 0; t < n_target; ++t) {
+        sk += C[(size_t)rr * n_target + t] * A[(size_t)t * n0 + m];
+        ske += fabs(C[(size_t)rr * n_target + t]) * fabs(A[(size_t)t * n0 + m]);
+      }
     skip[(size_t)r * 16 + m] = sg * sk;
+    skipE[(size_t)r * 16 + m] = gamma64(n_target) * ske * (1.0 + 0x1p-40);
   }
 }
 
@@ -291,19 +316,26 @@ __global__ void k_order(int S, const int* __restrict__ net_id, int n_nets, int* 
   }
 }
 
-__global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __restrict__ nets, const int* net_id,
-                                const double* bl, const double* bu, double* l, double* u) {
+// Pre-activation bounds of the batch in natural order (diagnostics).  A single-network
+// context (direct) reads network 0 whatever net_id holds; a subdomain whose id is
+// outside [0, n_nets) was processed by no launch and gets NaN rows.
+__global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __restrict__ nets, int n_nets,
+                                int direct, const int* net_id, const double* bl, const double* bu, double* l,
+                                double* u) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= S * H_max) return;
   const int s = e / H_max, h = e % H_max;
-  const NetDev& net = nets[net_id ? net_id[s] : 0];
+  const int id = (direct || !net_id) ? 0 : net_id[s];
   double lo = NAN, hi = NAN;
-  if (h < net.H) {
-    int k = 1, hh = h;
-    while (k < net.L - 1 && hh >= net.n[k]) { hh -= net.n[k]; ++k; }
-    const size_t p = (size_t)s * Hp_max + (size_t)(k - 1) * 16 * net.NT + hh;
-    lo = bl[p];
-    hi = bu[p];
+  if (id >= 0 && id < n_nets) {
+    const NetDev& net = nets[id];
+    if (h < net.H) {
+      int k = 1, hh = h;
+      while (k < net.L - 1 && hh >= net.n[k]) { hh -= net.n[k]; ++k; }
+      const size_t p = (size_t)s * Hp_max + (size_t)(k - 1) * 16 * net.NT + hh;
+      lo = bl[p];
+      hi = bu[p];
+    }
   }
   l[e] = lo;
   u[e] = hi;

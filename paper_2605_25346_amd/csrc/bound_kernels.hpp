@@ -485,6 +485,7 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
       const bool valid = live && r < net.R;
       const int rr = r < net.R ? r : 0;
       gconst<double> seed = as_global(net.seedW + (size_t)rr * net.np[L - 1]);
+      gconst<double> seed_e = as_global(net.seedWe + (size_t)rr * net.np[L - 1]);
       const int lbase = (L - 2) * n16;
       auto g = make_stage<T, NT>(stage, lane);
       T marg = 0;
@@ -497,24 +498,27 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
           const T gt = (T)gd;
           g.set(tt, i, gt);
           const double hu = fmax(S.u[lbase + m], 0.0);
-          if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          if (sc.margin_on)
+            marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
           if (i == 3) tile_fence<T, NT>();
         }
       double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
       T w[1][4];
       chain_to_input<T, NT, false, WLDS>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
-      double wt[4], conc = 0.0, wabs = 0.0;
+      double wt[4], conc = 0.0, wabs = 0.0, ske = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = nrn<T>(gq, i);
         wt[i] = (double)w[0][i] + net.skip[(size_t)rr * 16 + m];
         conc += wt[i] * S.xc[m] - fabs(wt[i]) * S.xr[m];
         wabs += fabs(wt[i]) * (fabs(S.xc[m]) + S.xr[m]);
+        ske += net.skipE[(size_t)rr * 16 + m] * (fabs(S.xc[m]) + S.xr[m]);
       }
       conc = row_sum(conc);
       wabs = row_sum(wabs);
       const double accs = row_sum(acc);
-      const double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs);
+      const double seed_mg = sc.margin_on ? net.seedBe[rr] + row_sum(ske) : 0.0;
+      const double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs) + seed_mg;
       if (valid) {
         double* f = sc.fin + ((size_t)s * 16 + r) * 17;
 #pragma unroll
@@ -553,6 +557,13 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
 // ---------------------------------------------------------------------------
 // a5 / a7: final spec rows.  One wave = one N-tile holding P = 16 / R subdomains.
 // ---------------------------------------------------------------------------
+// The caller's duals are projected on read onto their feasible sets (alpha in [0, 1],
+// beta >= 0; NaN maps to 0, which both sets contain): every evaluated bound is then a
+// valid bound whatever the caller passes, and bound, gradient and ascent step are
+// those of the projected point.
+__device__ __forceinline__ float proj_alpha(float a) { return fminf(fmaxf(a, 0.0f), 1.0f); }
+__device__ __forceinline__ float proj_beta(float b) { return fmaxf(b, 0.0f); }
+
 // Per-lane inputs of one 16-neuron tile of a dual-ascent relaxation step: the
 // relaxation, the split slot and the current alpha / beta of the lane's row (alpha and
 // beta are read at clamped addresses and selected by the caller).
@@ -571,8 +582,8 @@ __device__ __forceinline__ void load_group(GroupIn<T>& g, RP rk, SP sk, gmut<flo
     g.rr[i] = rk[t * 16 + gq * 4 + i];
     g.sp[i] = sk[t * 16 + gq * 4 + i];
     const bool uns = g.rr[i][2] > (T)0 && c < nk;
-    g.a[i] = arow[uns ? hoff + c : 0];
-    g.b[i] = brow[g.sp[i] >= 0 ? (g.sp[i] >> 1) : 0];
+    g.a[i] = proj_alpha(arow[uns ? hoff + c : 0]);
+    g.b[i] = proj_beta(brow[g.sp[i] >= 0 ? (g.sp[i] >> 1) : 0]);
   }
 }
 
@@ -585,8 +596,8 @@ __device__ __forceinline__ void load_ab(float (&ao)[4], float (&bo)[4], RP rk, S
     const int c = t * 16 + nrn<T>(gq, i);
     const bool uns = rk[t * 16 + gq * 4 + i][2] > (T)0 && c < nk;
     const int sp = sk[t * 16 + gq * 4 + i];
-    ao[i] = arow[uns ? hoff + c : 0];
-    bo[i] = brow[sp >= 0 ? (sp >> 1) : 0];
+    ao[i] = proj_alpha(arow[uns ? hoff + c : 0]);
+    bo[i] = proj_beta(brow[sp >= 0 ? (sp >> 1) : 0]);
   }
 }
 // Pipeline depth (tiles) of the dual loads: deeper when the relaxation is in LDS.
@@ -677,6 +688,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     auto ptape_at = [&](int col) -> gmut<T> { return as_global_mut((T*)fa.ptape + (size_t)col * fa.rows_pad + prow); };
     // seed margin: rounding of the FP64 seed g = a_L W_L to the chain type, times |h_{L-1}|
     gconst<double> seed = as_global(net.seedW + (size_t)r * net.np[L - 1]);
+    gconst<double> seed_e = as_global(net.seedWe + (size_t)r * net.np[L - 1]);
     const int lbase = (L - 2) * 16 * NT;
     gmut<float> arow = as_global_mut(DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : (float*)nullptr);
     gmut<float> brow = as_global_mut(DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : (float*)nullptr);
@@ -692,7 +704,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
           const double gd = seed[m] * liveD;
           const T gt = (T)gd;
           const double hu = fmax(bu[m], 0.0) * liveD;
-          marg0 += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+          marg0 += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
           if (i == 3) tile_fence<T, NT>();
         }
     }
@@ -791,18 +803,20 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         }
       }
       double wt[4];
-      double conc = 0.0, wabs = 0.0;
+      double conc = 0.0, wabs = 0.0, ske = 0.0;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int m = nrn<T>(gq, i);
         wt[i] = (double)w[0][i] + net.skip[(size_t)r * 16 + m];
         conc += wt[i] * xcv[i] - fabs(wt[i]) * xrv[i];
         wabs += fabs(wt[i]) * (fabs(xcv[i]) + xrv[i]);
+        ske += net.skipE[(size_t)r * 16 + m] * (fabs(xcv[i]) + xrv[i]);
       }
       conc = row_sum(conc);
       wabs = row_sum(wabs);
       double accs = row_sum(acc);
-      double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs);
+      const double seed_mg = sc.margin_on ? (net.seedBe[r] + row_sum(ske)) * liveD : 0.0;
+      double mg = (double)row_sum(marg) * kMargInflate + 0x1p-48 * (fabs(accs) + wabs) + seed_mg;
       lbv = accs + conc - mg;
       mgv = mg;
       if (!DUALS) {
@@ -1193,6 +1207,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
         const int r = lane & 15;
         const bool valid = r < ns;
         gconst<double> seed = as_global(net.seedW + (size_t)(valid ? r : 0) * net.np[L - 1]);
+        gconst<double> seed_e = as_global(net.seedWe + (size_t)(valid ? r : 0) * net.np[L - 1]);
         const int lbase = (L - 2) * 16 * NT;
         auto g = make_stage<T, NT>(stage, lane);
         T marg = 0;
@@ -1205,7 +1220,8 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
             T gt = (T)gd;
             g.set(t, i, gt);
             double hu = fmax(S.u[lbase + m], 0.0);
-            if (sc.margin_on) marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd)) * hu * (1.0 + 0x1p-30));
+            if (sc.margin_on)
+              marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
             if (i == 3) tile_fence<T, NT>();
           }
         double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
@@ -1213,7 +1229,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
         chain_to_input<T, NT, true>(net, L, g, S.rel, acc, acc2, marg, w, lane, lds_b);
         // W_r = A_r + w (FP64); new TM row: c' = W c, P' = W P, I' = W (x) I + [acc, acc2] -+ margin
         double Wr[4];
-        double cpart = 0.0, il = 0.0, ih = 0.0, wabs = 0.0;
+        double cpart = 0.0, il = 0.0, ih = 0.0, wabs = 0.0, ske = 0.0;
         double pp[16];
 #pragma unroll
         for (int z = 0; z < 16; ++z) pp[z] = 0.0;
@@ -1225,12 +1241,14 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
           double a1 = Wr[i] * Ilo[m], a2 = Wr[i] * Ihi[m];
           il += fmin(a1, a2); ih += fmax(a1, a2);
           wabs += fabs(Wr[i]) * Xab[m];
+          ske += net.skipE[(size_t)(valid ? r : 0) * 16 + m] * Xab[m];
 #pragma unroll
           for (int z = 0; z < 16; ++z) pp[z] += Wr[i] * Pm[m * 16 + z];
         }
         cpart = row_sum(cpart); il = row_sum(il); ih = row_sum(ih); wabs = row_sum(wabs);
         acc = row_sum(acc); acc2 = row_sum(acc2);
-        double mg = (double)row_sum(marg) * kMargInflate + 0x1p-46 * (wabs + fabs(acc) + fabs(acc2));
+        const double seed_mg = sc.margin_on ? net.seedBe[valid ? r : 0] + row_sum(ske) : 0.0;
+        double mg = (double)row_sum(marg) * kMargInflate + 0x1p-46 * (wabs + fabs(acc) + fabs(acc2)) + seed_mg;
         double rad = 0.0;
 #pragma unroll
         for (int z = 0; z < 16; ++z) {

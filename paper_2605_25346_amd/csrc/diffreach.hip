@@ -253,15 +253,21 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   }
   // seeds of the final rows
   const int npLm1 = nd.np[L - 1];
-  double *seedW, *seedB, *skip, *seedA;
+  double *seedW, *seedB, *skip, *seedA, *seedWe, *seedBe, *skipE;
   if (alloc) {
-    if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess) return hip_fail(c, e, "hipMalloc");
-    if ((e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess) return hip_fail(c, e, "hipMalloc");
+    if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess ||
+        (e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess ||
+        (e = ctx_alloc(c, &skip, sizeof(double) * nd.R * 16)) != hipSuccess ||
+        (e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess ||
+        (e = ctx_alloc(c, &seedWe, sizeof(double) * nd.R * npLm1)) != hipSuccess ||
+        (e = ctx_alloc(c, &seedBe, sizeof(double) * nd.R)) != hipSuccess ||
+        (e = ctx_alloc(c, &skipE, sizeof(double) * nd.R * 16)) != hipSuccess)
+      return hip_fail(c, e, "hipMalloc");
     nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip; nd.seedA = seedA;
+    nd.seedWe = seedWe; nd.seedBe = seedBe; nd.skipE = skipE;
   } else {
     seedW = (double*)nd.seedW; seedB = (double*)nd.seedB; skip = (double*)nd.skip; seedA = (double*)nd.seedA;
+    seedWe = (double*)nd.seedWe; seedBe = (double*)nd.seedBe; skipE = (double*)nd.skipE;
   }
   // the spec: a context-owned copy of the caller's (or the default [I], q = n_target)
   const int n_target = nd.n_state > 0 ? nd.n_state : nd.n[L];
@@ -283,7 +289,7 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   const int tot = nd.R * npLm1;
   hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
                      (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nd.A, c->B_dev[net_i], nd.n[0], nd.np[L],
-                     seedW, seedB, skip, seedA);
+                     seedW, seedB, skip, seedA, seedWe, seedBe, skipE);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
   return DR_OK;
 }
@@ -634,9 +640,14 @@ size_t dr_param_grad_workspace(const dr_ctx* c, int n_sub) {
   return pgrad_layout(c, std::max(n_sub, 1)).total;
 }
 
-dr_status dr_param_grad(dr_ctx* c, float* alpha, float* beta, int init_duals, const double* g_lb, const double* g_ub,
-                        double* lb, double* ub, double* const* dW, double* const* db, double* dxc, double* dxr,
-                        void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream) {
+}  // extern "C"
+
+// The parameter gradient with its tapes and partial sums in `workspace` (the caller's
+// buffer, or the library's static scratch).
+static dr_status param_grad_impl(dr_ctx* c, float* alpha, float* beta, int init_duals, const double* g_lb,
+                                 const double* g_ub, double* lb, double* ub, double* const* dW, double* const* db,
+                                 double* dxc, double* dxr, void* workspace, size_t workspace_bytes, uint32_t* status,
+                                 hipStream_t stream) {
   if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
   if (!c->have_batch) return fail(c, DR_EINVAL, "dr_bound_init has not been called");
   if (c->n_nets != 1) return fail(c, DR_EINVAL, "the parameter gradient takes a single-network context");
@@ -701,6 +712,17 @@ dr_status dr_param_grad(dr_ctx* c, float* alpha, float* beta, int init_duals, co
   return DR_OK;
 }
 
+extern "C" {
+
+dr_status dr_param_grad(dr_ctx* c, float* alpha, float* beta, int init_duals, const double* g_lb, const double* g_ub,
+                        double* lb, double* ub, double* const* dW, double* const* db, double* dxc, double* dxr,
+                        void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream) {
+  return param_grad_impl(c, alpha, beta, init_duals, g_lb, g_ub, lb, ub, dW, db, dxc, dxr, workspace, workspace_bytes,
+                         status, stream);
+}
+
+}  // extern "C"
+
 static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, uint32_t* status,
                        hipStream_t stream) {
   if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
@@ -748,6 +770,8 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
   return DR_OK;
 }
 
+extern "C" {
+
 dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, uint32_t* status, hipStream_t stream) {
   return reach(c, b, horizon, nullptr, boxes, status, stream);
 }
@@ -764,7 +788,7 @@ dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {
   if (S == 0 || c->H_max == 0) return DR_OK;
   const int tot = S * c->H_max;
   hipLaunchKernelGGL(dr::k_export_bounds, dim3((tot + 255) / 256), dim3(256), 0, stream, S, c->Hp_max, c->H_max,
-                     c->dnet, c->batch.net_id, c->sc.bl, c->sc.bu, l, u);
+                     c->dnet, c->n_nets, c->sc.direct, c->batch.net_id, c->sc.bl, c->sc.bu, l, u);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "export kernel");
   return DR_OK;

@@ -87,6 +87,14 @@ struct NetDev {
   const double* seedB;       // R: a_L . b_L
   const double* seedA;       // R x np_L: a_L, the multipliers of every final row on the network output
   const double* skip;        // R x 16: (+-c) A for the closed loop, zeros otherwise
+  // a priori bounds of the FP64 rounding in the seeds (Higham's dot-product bound),
+  // covered by the rounding margin of every final row: seedWe R x np_{L-1} bounds
+  // |g - a W_L| including the error of a = c B itself (so it also covers the error of
+  // a . y through y = W_L h + b_L), seedBe R the same for a . b_L, skipE R x 16 the
+  // error of (+-c) A per input (times a bound on |x|)
+  const double* seedWe;
+  const double* seedBe;
+  const double* skipE;
   const double* A;           // n_state x n_0 (closed loop) or null
   int n_state;
   int q;                     // spec directions
