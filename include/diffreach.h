@@ -202,6 +202,21 @@ dr_status dr_param_grad(dr_ctx* ctx, float* alpha, float* beta, int init_duals, 
                         double* dxc, double* dxr, void* workspace, size_t workspace_bytes, uint32_t* status,
                         hipStream_t stream);
 
+/* dr_param_grad without a workspace argument, for callers that cannot allocate device
+ * memory (code under HIP graph capture that must not call hipMalloc, tight serving or
+ * training loops, harnesses that forbid allocation): the tapes and partial sums live in
+ * a static device array of the library, 64 MiB per device (each device the library
+ * runs on holds its own copy until the process ends), so the call allocates nothing
+ * and needs no buffer beyond its inputs and outputs.  Same arguments, results and
+ * errors as dr_param_grad; a batch whose dr_param_grad_workspace(ctx, S) exceeds
+ * 64 MiB returns DR_ECAPACITY before any launch.  Every call on a device shares that
+ * device's array (the call writes every byte it later reads, so nothing needs
+ * clearing): calls that overlap in time on one device, from any context or stream,
+ * race and must be ordered by the caller. */
+dr_status dr_param_grad_static(dr_ctx* ctx, float* alpha, float* beta, int init_duals, const double* g_lb,
+                               const double* g_ub, double* lb, double* ub, double* const* dW, double* const* db,
+                               double* dxc, double* dxr, uint32_t* status, hipStream_t stream);
+
 /* Replace the weights and biases of network `net_index` of the context in place
  * (same widths; W, b and wdtype read as in dr_create; the closed-loop A, B and the
  * spec stay those given at creation, and A, B must stay valid).  The copies, swizzles

@@ -240,6 +240,26 @@ class BoundContext:
                                            _stream()))
         return lb, ub, dW, db, dxc[:S], dxr[:S], status[:S]
 
+    def dr_param_grad_static(self, alpha, beta, g_lb, g_ub, init_duals=False, out=None):
+        """dr_param_grad with the library's static scratch instead of a workspace (the
+        entry point that allocates nothing; the outputs are the caller's)."""
+        self._check_duals(alpha, beta)
+        S = self.batch.n_sub
+        if out is None:
+            out, _ = self.param_grad_outputs()
+        lb, ub, dW, db, dxc, dxr, status = out
+        g_lb = torch.as_tensor(g_lb, dtype=torch.float64, device=self.device).contiguous()
+        g_ub = torch.as_tensor(g_ub, dtype=torch.float64, device=self.device).contiguous()
+        self._check_rows("g_lb", g_lb)
+        self._check_rows("g_ub", g_ub)
+        self._pg_keep = (g_lb, g_ub)
+        Wp = (ctypes.c_void_p * len(dW))(*[t.data_ptr() for t in dW])
+        bp = (ctypes.c_void_p * len(db))(*[t.data_ptr() for t in db])
+        self._check(self.lib.dr_param_grad_static(self.ctx, _ptr(alpha), _ptr(beta), int(bool(init_duals)),
+                                                  _ptr(g_lb), _ptr(g_ub), _ptr(lb), _ptr(ub), Wp, bp, _ptr(dxc),
+                                                  _ptr(dxr), _ptr(status), _stream()))
+        return lb, ub, dW, db, dxc[:S], dxr[:S], status[:S]
+
     def dr_reach_dt(self, batch: DeviceBatch, horizon: int, boxes=None, u=None):
         """Stepwise reach; ``u`` (S x horizon x (n_0 - n_state), FP64 device) selects
         dr_reach_dt_exo for networks with exogenous inputs."""

@@ -23,7 +23,7 @@ DR_MARGIN_RIGOROUS, DR_MARGIN_OFF = 0, 1
 
 EXPORTED = [
     "dr_create", "dr_bound_init", "dr_propagate_backward", "dr_concretize", "dr_optimize_duals",
-    "dr_param_grad_workspace", "dr_param_grad", "dr_set_weights",
+    "dr_param_grad_workspace", "dr_param_grad", "dr_param_grad_static", "dr_set_weights",
     "dr_reach_dt", "dr_reach_dt_exo", "dr_get_bounds", "dr_get_rows", "dr_get_margins", "dr_hidden_max", "dr_spec_rows",
     "dr_last_error", "dr_destroy",
 ]
@@ -92,6 +92,7 @@ def load():
         "dr_param_grad_workspace": (ctypes.c_size_t, [P, I]),
         "dr_set_weights": (I, [P, I, ctypes.POINTER(dr_network), P]),
         "dr_param_grad": (I, [P, P, P, I, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]),
+        "dr_param_grad_static": (I, [P, P, P, I, P, P, P, P, P, P, P, P, P, P]),
         "dr_reach_dt": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P]),
         "dr_reach_dt_exo": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P]),
         "dr_get_bounds": (I, [P, P, P, P]),

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -23,7 +24,19 @@ namespace {
 thread_local std::string g_create_error;
 enum { Q_BOUND = 0, Q_FINAL = 1, Q_DUAL = 2, Q_REACH = 3, Q_KINDS = 4 };
 int pad16(int n) { return (n + 15) / 16 * 16; }
+
+// Static scratch of dr_param_grad_static (the entry point that allocates nothing): each
+// device holds its own copy of this array, from the library's first use on that device
+// until the process ends.  Host code never uses the array's name as an address: the
+// device address of each copy is resolved once per device (hipGetSymbolAddress with
+// that device current, in dr_create) and kept in g_scratch_dev.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
 }  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct dr_ctx {
   int dev = 0;
@@ -55,6 +68,7 @@ struct dr_ctx {
   const double* B_dev[kMaxNets] = {};      // the caller's closed-loop B (valid for the context's lifetime)
   const void* pg_fn = nullptr;  // parameter-gradient instance of k_final (single network)
   int pg_grid = 0;
+  void* scratch = nullptr;      // device address of this device's static scratch
   std::string err;
 };
 
@@ -356,6 +370,18 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   hipDeviceProp_t prop;
   if ((e = hipGetDeviceProperties(&prop, c->dev)) != hipSuccess) return bail(hip_fail(c, e, "hipGetDeviceProperties"));
   c->cus = prop.multiProcessorCount;
+  {
+    // this device's copy of the static scratch, resolved once per device
+    if (c->dev < 0 || c->dev >= kMaxDevices) return bail(fail(c, DR_EDEVICE, "device index out of range"));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[c->dev]) {
+      void* p = nullptr;
+      if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess)
+        return bail(hip_fail(c, e, "hipGetSymbolAddress(scratch)"));
+      g_scratch_dev[c->dev] = p;
+    }
+    c->scratch = g_scratch_dev[c->dev];
+  }
   for (int i = 0; i < n_nets; ++i) {
     const dr_network& nw = nets[i];
     const int L = nw.n_layers;
@@ -719,6 +745,22 @@ dr_status dr_param_grad(dr_ctx* c, float* alpha, float* beta, int init_duals, co
                         void* workspace, size_t workspace_bytes, uint32_t* status, hipStream_t stream) {
   return param_grad_impl(c, alpha, beta, init_duals, g_lb, g_ub, lb, ub, dW, db, dxc, dxr, workspace, workspace_bytes,
                          status, stream);
+}
+
+dr_status dr_param_grad_static(dr_ctx* c, float* alpha, float* beta, int init_duals, const double* g_lb,
+                               const double* g_ub, double* lb, double* ub, double* const* dW, double* const* db,
+                               double* dxc, double* dxr, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->scratch) return fail(c, DR_EDEVICE, "the static scratch of this device was not resolved");
+  if (c->have_batch && c->n_nets == 1) {
+    const size_t need = pgrad_layout(c, std::max(c->batch.n_sub, 1)).total;
+    if (need > kStaticScratchBytes)
+      return fail(c, DR_ECAPACITY,
+                  "batch needs " + std::to_string(need) + " bytes of parameter-gradient scratch; the static buffer "
+                  "holds " + std::to_string(kStaticScratchBytes) + " (use dr_param_grad with a workspace)");
+  }
+  return param_grad_impl(c, alpha, beta, init_duals, g_lb, g_ub, lb, ub, dW, db, dxc, dxr, c->scratch,
+                         kStaticScratchBytes, status, stream);
 }
 
 }  // extern "C"

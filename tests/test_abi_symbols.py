@@ -59,6 +59,7 @@ def test_null_context_is_rejected_before_any_device_call():
     assert lib.dr_propagate_backward(N, N, N, N, N, N) == binding.DR_EINVAL
     assert lib.dr_optimize_duals(N, 0, 0.0, 0, N, N, N, N, N, N, N, N) == binding.DR_EINVAL
     assert lib.dr_param_grad(N, N, N, 0, N, N, N, N, N, N, N, N, N, 0, N, N) == binding.DR_EINVAL
+    assert lib.dr_param_grad_static(N, N, N, 0, N, N, N, N, N, N, N, N, N, N) == binding.DR_EINVAL
     assert lib.dr_set_weights(N, 0, N, N) == binding.DR_EINVAL
     assert lib.dr_param_grad_workspace(N, 16) == 0
     assert lib.dr_reach_dt(N, N, 1, N, N, N) == binding.DR_EINVAL
