@@ -235,7 +235,7 @@ template <typename T>
 __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int nL, int npLm1,
                         const double* __restrict__ C, int q, int n_target, const double* __restrict__ A,
                         const double* __restrict__ B, int n0, int npL, double* seedW, double* seedB, double* skip,
-                        double* seedA, double* seedWe, double* seedBe, double* skipE) {
+                        double* seedA, double* seedWe, double* seedBe, double* skipE, T* seedT, T* seedM) {
   const int R = 2 * q;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= R * npLm1) return;
@@ -266,6 +266,9 @@ __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int 
   }
   seedW[(size_t)r * npLm1 + m] = g;
   seedWe[(size_t)r * npLm1 + m] = eg * (1.0 + 0x1p-40);
+  const T gt = (T)g;
+  seedT[(size_t)r * npLm1 + m] = gt;
+  seedM[(size_t)r * npLm1 + m] = rup<T>((fabs(g - (double)gt) + 0x1p-50 * fabs(g) + eg * (1.0 + 0x1p-40)) * (1.0 + 0x1p-30));
   if (m == 0) {
     seedB[r] = acc;
     seedBe[r] = eb * (1.0 + 0x1p-40);

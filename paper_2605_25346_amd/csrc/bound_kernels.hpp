@@ -22,7 +22,13 @@
 
 namespace dr {
 
-constexpr double kAccEps = 0x1p-42;   // FP64 summation error of offsets (relative to |terms|)
+// Summation error of the offsets (bias and intercept terms) relative to sum |a'| (M + |b|):
+// per 16-neuron tile a lane sums its 8 terms (two per neuron) in the chain type with fused
+// multiply-adds (error <= gamma_8 sum |terms|, Higham's bound; gamma_8 < 2^-20 for FP32),
+// then adds the tile's partial to an FP64 accumulator (error far below 2^-42).  The terms
+// of a neuron are bounded by |a'| (M + |b|): |a' b| directly, and the intercept term
+// |g t| = |a'| |l| <= |a'| M (a' = s g, t = -s l) up to the rounding of a'.
+template <typename T> __host__ __device__ constexpr double acc_eps() { return sizeof(T) == 4 ? 0x1p-20 : 0x1p-42; }
 constexpr double kMargInflate = 1.0 + 0x1p-12;
 
 // ReLU relaxation of one neuron in the chain's arithmetic, with its margin
@@ -51,7 +57,7 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
   }
   if (!(M < INFINITY)) M = 0.0;  // non-finite bounds are reported through status bits
   double mu = gamma_n<T>(2 * K) * v + (inexact ? 2.0 * unit_round<T>() * M : 0.0) +
-              kAccEps * (fabs(bias) + M);
+              acc_eps<T>() * (fabs(bias) + M);
   mu *= 1.0 + 0x1p-40;
   if (!margin_on) mu = 0.0;
   V4<T> r;
@@ -60,8 +66,10 @@ __device__ V4<T> build_relax(double l, double u, double v, double bias, bool spl
 }
 
 // Relaxation of one layer applied in place to the chain state st: the multipliers g
-// over h_k become the row multipliers a' over z_k.  Offsets and margin accumulate
-// per lane.
+// over h_k become the row multipliers a' over z_k.  The offsets (a' b_k and the upper
+// intercepts g t where g < 0; in the shared-slope form the lower offset takes g t for
+// g < 0 and the upper one for g > 0) are summed per tile in the chain type and added to
+// the FP64 accumulators once per tile; the margin accumulates |a'| mu per lane.
 template <typename T, int NT, bool SHARED, typename RelPtr, typename Stage, typename BT>
 __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<BT> bias, int gq, double& acc,
                                             double& acc2, T& marg) {
@@ -75,22 +83,25 @@ __device__ __forceinline__ void relax_layer(Stage& st, RelPtr rel, lconst<BT> bi
 #pragma unroll
       for (int i = 0; i < 4; ++i) r_nxt[i] = rel[(t + 1) * 16 + gq * 4 + i];
     }
+    T pa = 0, pa2 = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const V4<T> r = r_cur[i];
-      T gv = st.get(t, i);
-      T a = (gv >= (T)0 ? r[0] : r[1]) * gv;
-      double bj = (double)bias[t * 16 + nrn<T>(gq, i)];
-      double gt = (double)gv * (double)r[2];
+      const T gv = st.get(t, i);
+      const bool neg = gv < (T)0;
+      const T a = (neg ? r[1] : r[0]) * gv;
+      const T bj = (T)bias[t * 16 + nrn<T>(gq, i)];
+      pa = fma(a, bj, pa);
+      pa = fma(gv, neg ? r[2] : (T)0, pa);
       if (SHARED) {
-        acc += fmin(gt, 0.0) + (double)a * bj;
-        acc2 += fmax(gt, 0.0) + (double)a * bj;
-      } else {
-        acc += fmin(gt, 0.0) + (double)a * bj;
+        pa2 = fma(a, bj, pa2);
+        pa2 = fma(gv, neg ? (T)0 : r[2], pa2);
       }
       marg += fabs(a) * r[3];
       st.set(t, i, a);
     }
+    acc += (double)pa;
+    if (SHARED) acc2 += (double)pa2;
     tile_fence<T, NT>();
     if (t + 1 < NT) {
 #pragma unroll
@@ -140,6 +151,105 @@ __device__ __forceinline__ void chain_to_input(const NetDev& net, int K, Stage& 
   }
 }
 
+// ---------------------------------------------------------------------------
+// NR row tiles of one subdomain processed together by one wavefront (register chain
+// states): the tiles share every load of the relaxation and of the weight tiles, and
+// their independent products and relaxation steps interleave, which hides the latency
+// of each tile's dependent chain behind the other's work.
+// ---------------------------------------------------------------------------
+template <typename T, int NT, int NR, typename RelPtr, typename BT>
+__device__ __forceinline__ void relax_layer_n(T (&st)[NR][NT][4], RelPtr rel, lconst<BT> bias, int gq,
+                                              double (&acc)[NR], T (&marg)[NR]) {
+  V4<T> r_cur[4], r_nxt[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r_cur[i] = rel[gq * 4 + i];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r_nxt[i] = rel[(t + 1) * 16 + gq * 4 + i];
+    }
+    T bj[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) bj[i] = (T)bias[t * 16 + nrn<T>(gq, i)];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      T pa = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const V4<T> rr = r_cur[i];
+        const T gv = st[r][t][i];
+        const bool neg = gv < (T)0;
+        const T a = (neg ? rr[1] : rr[0]) * gv;
+        pa = fma(a, bj[i], pa);
+        pa = fma(gv, neg ? rr[2] : (T)0, pa);
+        marg[r] += fabs(a) * rr[3];
+        st[r][t][i] = a;
+      }
+      acc[r] += (double)pa;
+    }
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) r_cur[i] = r_nxt[i];
+    }
+  }
+}
+
+// out[r][mt] = sum_kt A(mt, kt) in[r][kt] for NR row tiles (A loaded once per tile pair).
+template <typename T, int MT, int KT, int NR, typename P>
+__device__ __forceinline__ void gemm_n(P Wsw, const T (&in)[NR][KT][4], T (&out)[NR][MT][4], int lane) {
+  V4<T> acc[NR][MT];
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[r][mt] = V4<T>{0, 0, 0, 0};
+#pragma unroll
+  for (int kt = 0; kt < KT; ++kt) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const V4<T> a = Wsw[(mt * KT + kt) * 64 + lane];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < NR; ++r) acc[r][mt] = mfma16(a[i], in[r][kt][i], acc[r][mt]);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r)
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[r][mt][i] = acc[r][mt][i];
+}
+
+// chain_to_input for NR register-held row tiles (plain relaxation, no shared slope).
+template <typename T, int NT, int NR, bool WL, typename BT>
+__device__ __forceinline__ void chain_to_input_n(const NetDev& net, int K, T (&st)[NR][NT][4], const V4<T>* rel_all,
+                                                 double (&acc)[NR], T (&marg)[NR], T (&w)[NR][1][4], int lane,
+                                                 const BT* lds_b, const V4<T>* lds_w) {
+  const int gq = lane >> 4;
+  for (int k = K - 1; k >= 1; --k) {
+    relax_layer_n<T, NT, NR>(st, rel_all + (k - 1) * 16 * NT, (lconst<BT>)(lds_b + (k - 1) * 16 * NT), gq, acc,
+                             marg);
+    auto step = [&](auto Wp) {
+      if (k > 1) {
+        T nxt[NR][NT][4];
+        gemm_n<T, NT, NT, NR>(Wp, st, nxt, lane);
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) st[r][t][i] = nxt[r][t][i];
+      } else {
+        gemm_n<T, 1, NT, NR>(Wp, st, w, lane);
+      }
+    };
+    if constexpr (WL) step((lconst<V4<T>>)(lds_w + lds_w_offset(k, NT)));
+    else step(as_global(uniform_ptr((const V4<T>*)net.Wf[k - 1])));
+  }
+}
+
 // Stage the hidden biases (padded, layer k at (k - 1) 16 NT) into LDS, once per
 // workgroup: in FP64 (BT = double, saves a conversion per relaxed multiplier, the
 // offsets being summed in FP64) or in the chain type (less LDS and registers).
@@ -163,28 +273,49 @@ __device__ __forceinline__ T lds_weight(const V4<T>* lds_w, int k, int NT, int r
   return W[(((m >> 4) * NT + (r >> 4)) * 64 + g * 16 + (m & 15)) * 4 + c];
 }
 
-// Stage the forward-swizzled weights of layers 1..L-1 into LDS (once per workgroup).
+// Stage the forward-swizzled weights of layers 1..L-1 into LDS (once per workgroup):
+// the layers are one contiguous range of the staged block, and each thread issues up to
+// eight global loads before its LDS writes, so the copy costs few load round trips.
 template <typename T>
 __device__ void stage_weights(const NetDev& net, V4<T>* dst) {
-  const int NT = net.NT;
-  for (int k = 1; k <= net.L - 1; ++k) {
-    const int n = (k == 1 ? NT : NT * NT) * 64;
-    gconst<V4<T>> src = as_global((const V4<T>*)net.Wf[k - 1]);
-    V4<T>* d = dst + lds_w_offset(k, NT);
-    for (int e = threadIdx.x; e < n; e += kWG) d[e] = src[e];
+  const int NT = net.NT, total = lds_w_count(net.L, NT);
+  constexpr int kBatch = 8;
+  for (int e0 = threadIdx.x; e0 < total; e0 += kBatch * kWG) {
+    V4<T> v[kBatch];
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kWG;
+      if (e < total) {
+        const int k = e < NT * 64 ? 1 : 2 + (e - NT * 64) / (NT * NT * 64);   // layer of staged entry e
+        v[u] = as_global((const V4<T>*)net.Wf[k - 1])[e - lds_w_offset(k, NT)];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kBatch; ++u) {
+      const int e = e0 + u * kWG;
+      if (e < total) dst[e] = v[u];
+    }
   }
 }
 
 
 // Synchronisation of the threads that share one subdomain: the whole workgroup
 // (TPS = 256) or one wavefront (TPS = 64, where LDS operations of the wave are
-// processed in order and only compiler reordering must be prevented).
+// processed in order and only compiler reordering must be prevented).  Threads of a
+// workgroup exchange data only through LDS inside these kernels (global results are
+// written for later launches, or re-read only by the lane that wrote them), so the
+// fences order LDS accesses alone: they never wait for global loads or stores in flight.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 template <int TPS> __device__ __forceinline__ void sub_sync() {
   if (TPS == 64) {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup", "local");
     __builtin_amdgcn_wave_barrier();
   } else {
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -205,7 +336,7 @@ __device__ __forceinline__ int compact_flags(int n16, F flag_of, int* U, int* wc
     } else {
       const int wid = t >> 6;
       if (lane == 0) wcnt[wid] = __popcll(m);
-      __syncthreads();
+      lds_barrier();
       int base = total, tot = 0;
       for (int w = 0; w < TPS / 64; ++w) {
         if (w < wid) base += wcnt[w];
@@ -213,7 +344,7 @@ __device__ __forceinline__ int compact_flags(int n16, F flag_of, int* U, int* wc
       }
       if (flag) U[base + pre] = j;
       total += tot;
-      __syncthreads();
+      lds_barrier();
     }
   }
   sub_sync<TPS>();
@@ -266,11 +397,18 @@ __device__ __forceinline__ void relu_box(const double* l, const double* u, int n
 // a1-a4: intermediate bounds, persistent.  TPS threads own one subdomain at a time:
 // a whole workgroup (TPS = 256, wide networks: the chain tiles of a layer are spread
 // over its four waves) or one wavefront (TPS = 64, narrow networks: four subdomains
-// per workgroup progress independently, no workgroup barriers).
+// per workgroup progress independently, no workgroup barriers).  Narrow FP32 networks
+// process their row tiles in pairs and ask for two waves per SIMD (a register budget
+// of 256, which the paired tiles fill); the others keep one tile at a time.
 // ---------------------------------------------------------------------------
+template <typename T, int TPS> constexpr int bound_tiles_per_step() { return sizeof(T) == 4 && TPS == 64 ? 2 : 1; }
+template <typename T, int TPS> constexpr int bound_min_waves() { return bound_tiles_per_step<T, TPS>() == 2 ? 2 : 1; }
+
 template <typename T, int NT, bool WLDS, int TPS>
-__global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch,
-                                                    Scratch sc, unsigned* queue, int inter_mode, int max_splits) {
+__global__ void __launch_bounds__(kWG, (bound_min_waves<T, TPS>()))
+k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch, Scratch sc, int inter_mode,
+             int max_splits) {
+  constexpr int kWaves = kWavesPerWG;
   extern __shared__ __align__(16) char lds_raw[];
   const NetDev& net = nets[net_index];
   const int L = net.L, Hp = net.Hp, HpS = sc.Hp_max;
@@ -281,39 +419,30 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
   const size_t sub_bytes = SubLds<T>::bytes(Hp, NT);
   // dynamic LDS: per-wave chain stages, the subdomain state(s), staged weights, biases
   char* stage = lds_raw + (size_t)wid * stage_bytes<T, NT>();
-  char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
+  char* lds_base = lds_raw + kWaves * stage_bytes<T, NT>();
   SubLds<T> S;
   S.carve(lds_base + (TPS == 64 ? (size_t)wid * sub_bytes : 0), Hp, NT);
-  char* lds_tail = lds_base + (TPS == 64 ? kWavesPerWG : 1) * sub_bytes;
+  char* lds_tail = lds_base + (TPS == 64 ? kWaves : 1) * sub_bytes;
   V4<T>* lds_w = nullptr;
   if (WLDS) {
     lds_w = (V4<T>*)lds_tail;
     lds_tail += (size_t)lds_w_count(L, NT) * sizeof(V4<T>);
     stage_weights<T>(net, lds_w);
   }
-  double* lds_b = (double*)lds_tail;
-  stage_biases<T, double>(net, lds_b);
-  __syncthreads();
+  T* lds_b = (T*)lds_tail;
+  stage_biases<T, T>(net, lds_b);
+  lds_barrier();
   const int cnt = batch_count(sc, net_index);
   const int n0 = net.n[0];
   const int n16 = 16 * NT;
 
-  bool first = true;
-  for (;;) {
-    int item;
-    if (TPS == 64) {
-      item = next_item(queue, first, blockIdx.x * kWavesPerWG + wid, gridDim.x * kWavesPerWG);
-    } else {
-      if (first) {
-        first = false;
-        item = blockIdx.x;
-      } else {
-        if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(queue, 1u);
-        __syncthreads();
-        item = S.misc[0];
-        __syncthreads();
-      }
-    }
+  // static round-robin assignment of the work items (item = worker + round * workers):
+  // the per-subdomain costs are close to one another, and a shared queue counter would
+  // serialise every worker's fetch at the same moment (measured: ~35 us of a 4096-item
+  // launch whose items are short)
+  const int n_workers = TPS == 64 ? (int)gridDim.x * kWaves : (int)gridDim.x;
+  const int worker = TPS == 64 ? (int)blockIdx.x * kWaves + wid : (int)blockIdx.x;
+  for (int item = worker;; item += n_workers) {
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
 
@@ -413,47 +542,108 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
       const int nU = compact_flags<TPS>(n16, unstable, S.U, S.misc + 2);
       const int nrows = 2 * nU;
       const int ntiles = (nrows + 15) >> 4;
-      for (int tile = wave_in_team; tile < ntiles; tile += n_team_waves) {
-        const int row = tile * 16 + (lane & 15);
-        const bool valid = row < nrows;
-        const int neuron = valid ? S.U[row >> 1] : 0;
-        const T sgn = (row & 1) ? (T)-1 : (T)1;
-        auto g = make_stage<T, NT>(stage, lane);
-        const int gq = lane >> 4;
-        const T sg = valid ? sgn : (T)0;
-        if (WLDS) {
+      if constexpr (TPS == 64) {
+        // one subdomain per wavefront: row tiles in pairs (a last odd tile alone)
+        auto rows_n = [&](auto nr_tag, int tile0) {
+          constexpr int NR = decltype(nr_tag)::value;
+          const int gq = lane >> 4;
+          T g[NR][NT][4];
+          double acc[NR];
+          T marg[NR];
+          T w[NR][1][4];
+          int row[NR], neuron[NR];
+          bool valid[NR];
+          // seeds: rows +-e_j at z_k, i.e. +-W_k[j][:] over h_{k-1}, one vector load per
+          // 16-neuron tile from the adjoint-swizzled copy (block (j / 16, tile), lane
+          // j % 16 + 16 gq holds W_k[j][16 tile + nrn(gq, 0..3)])
+          gconst<V4<T>> Wa = as_global(uniform_ptr((const V4<T>*)net.Wa[k - 1]));
 #pragma unroll
-          for (int tt = 0; tt < NT; ++tt)
+          for (int r = 0; r < NR; ++r) {
+            row[r] = (tile0 + r) * 16 + (lane & 15);
+            valid[r] = row[r] < nrows;
+            neuron[r] = valid[r] ? S.U[row[r] >> 1] : 0;
+            const T sg = valid[r] ? ((row[r] & 1) ? (T)-1 : (T)1) : (T)0;
+            const int lb0 = ((neuron[r] >> 4) * NT) * 64 + (neuron[r] & 15) + 16 * gq;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g.set(tt, i, sg * lds_weight<T>(lds_w, k, NT, neuron, tt * 16 + nrn<T>(gq, i)));
-        } else {
-          gconst<T> Wr = as_global((const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1]);
+            for (int tt = 0; tt < NT; ++tt) {
+              const V4<T> wv = Wa[lb0 + tt * 64];
 #pragma unroll
-          for (int tt = 0; tt < NT; ++tt)
+              for (int i = 0; i < 4; ++i) g[r][tt][i] = sg * wv[i];
+            }
+            // the seed offset enters once per row (lane group 0)
+            acc[r] = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron[r]];
+            marg[r] = 0;
+          }
+          chain_to_input_n<T, NT, NR, WLDS>(net, k, g, S.rel, acc, marg, w, lane, lds_b, lds_w);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) g.set(tt, i, sg * Wr[tt * 16 + nrn<T>(gq, i)]);
-        }
-        // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
-        double acc = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron], acc2 = 0.0;
-        T marg = 0;
-        T w[1][4];
-        chain_to_input<T, NT, false, WLDS>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
-        double conc = 0.0, wabs = 0.0;
+          for (int r = 0; r < NR; ++r) {
+            double conc = 0.0, wabs = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int m = nrn<T>(gq, i);
-          double wm = (double)w[0][i];
-          conc += wm * S.xc[m] - fabs(wm) * S.xr[m];
-          wabs += fabs(wm) * (fabs(S.xc[m]) + S.xr[m]);
-        }
-        conc = row_sum(conc);
-        wabs = row_sum(wabs);
-        acc = row_sum(acc);
-        double mg = (double)row_sum(marg) * kMargInflate;
-        double lb = acc + conc - mg - 0x1p-48 * (fabs(acc) + wabs);
-        if (valid && lane < 16) {
-          if (row & 1) S.u[base + neuron] = fmin(S.ibu[neuron], -lb);
-          else S.l[base + neuron] = fmax(S.ibl[neuron], lb);
+            for (int i = 0; i < 4; ++i) {
+              const int m = nrn<T>(gq, i);
+              const double wm = (double)w[r][0][i];
+              conc += wm * S.xc[m] - fabs(wm) * S.xr[m];
+              wabs += fabs(wm) * (fabs(S.xc[m]) + S.xr[m]);
+            }
+            conc = row_sum(conc);
+            wabs = row_sum(wabs);
+            const double accs = row_sum(acc[r]);
+            const double mg = (double)row_sum(marg[r]) * kMargInflate;
+            const double lb = accs + conc - mg - 0x1p-48 * (fabs(accs) + wabs);
+            if (valid[r] && lane < 16) {
+              if (row[r] & 1) S.u[base + neuron[r]] = fmin(S.ibu[neuron[r]], -lb);
+              else S.l[base + neuron[r]] = fmax(S.ibl[neuron[r]], lb);
+            }
+          }
+        };
+        constexpr int NR = bound_tiles_per_step<T, TPS>();
+        int tile = 0;
+        if constexpr (NR == 2)
+          for (; tile + 1 < ntiles; tile += 2) rows_n(std::integral_constant<int, 2>{}, tile);
+        for (; tile < ntiles; ++tile) rows_n(std::integral_constant<int, 1>{}, tile);
+      } else {
+        for (int tile = wave_in_team; tile < ntiles; tile += n_team_waves) {
+          const int row = tile * 16 + (lane & 15);
+          const bool valid = row < nrows;
+          const int neuron = valid ? S.U[row >> 1] : 0;
+          const T sgn = (row & 1) ? (T)-1 : (T)1;
+          auto g = make_stage<T, NT>(stage, lane);
+          const int gq = lane >> 4;
+          const T sg = valid ? sgn : (T)0;
+          if (WLDS) {
+  #pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+  #pragma unroll
+              for (int i = 0; i < 4; ++i) g.set(tt, i, sg * lds_weight<T>(lds_w, k, NT, neuron, tt * 16 + nrn<T>(gq, i)));
+          } else {
+            gconst<T> Wr = as_global((const T*)net.Wn[k - 1] + (size_t)neuron * net.np[k - 1]);
+  #pragma unroll
+            for (int tt = 0; tt < NT; ++tt)
+  #pragma unroll
+              for (int i = 0; i < 4; ++i) g.set(tt, i, sg * Wr[tt * 16 + nrn<T>(gq, i)]);
+          }
+          // the seed offset enters once per row (lane group 0); the other groups add their neurons' terms
+          double acc = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron], acc2 = 0.0;
+          T marg = 0;
+          T w[1][4];
+          chain_to_input<T, NT, false, WLDS>(net, k, g, S.rel, acc, acc2, marg, w, lane, lds_b, lds_w);
+          double conc = 0.0, wabs = 0.0;
+  #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int m = nrn<T>(gq, i);
+            double wm = (double)w[0][i];
+            conc += wm * S.xc[m] - fabs(wm) * S.xr[m];
+            wabs += fabs(wm) * (fabs(S.xc[m]) + S.xr[m]);
+          }
+          conc = row_sum(conc);
+          wabs = row_sum(wabs);
+          acc = row_sum(acc);
+          double mg = (double)row_sum(marg) * kMargInflate;
+          double lb = acc + conc - mg - 0x1p-48 * (fabs(acc) + wabs);
+          if (valid && lane < 16) {
+            if (row & 1) S.u[base + neuron] = fmin(S.ibu[neuron], -lb);
+            else S.l[base + neuron] = fmax(S.ibl[neuron], lb);
+          }
         }
       }
       sub_sync<TPS>();
@@ -484,8 +674,8 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
       const int r = lane & 15, gq = lane >> 4;
       const bool valid = live && r < net.R;
       const int rr = r < net.R ? r : 0;
-      gconst<double> seed = as_global(net.seedW + (size_t)rr * net.np[L - 1]);
-      gconst<double> seed_e = as_global(net.seedWe + (size_t)rr * net.np[L - 1]);
+      gconst<T> seed = as_global((const T*)net.seedT + (size_t)rr * net.np[L - 1]);
+      gconst<T> seed_m = as_global((const T*)net.seedM + (size_t)rr * net.np[L - 1]);
       const int lbase = (L - 2) * n16;
       auto g = make_stage<T, NT>(stage, lane);
       T marg = 0;
@@ -494,12 +684,8 @@ __global__ void __launch_bounds__(kWG) k_bound_init(const NetDev* __restrict__ n
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = tt * 16 + nrn<T>(gq, i);
-          const double gd = seed[m] * (valid ? 1.0 : 0.0);
-          const T gt = (T)gd;
-          g.set(tt, i, gt);
-          const double hu = fmax(S.u[lbase + m], 0.0);
-          if (sc.margin_on)
-            marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
+          g.set(tt, i, valid ? seed[m] : (T)0);
+          if (sc.margin_on && valid) marg += seed_m[m] * (T)fmax(S.u[lbase + m], 0.0);
           if (i == 3) tile_fence<T, NT>();
         }
       double acc = net.seedB[rr] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = 0.0;
@@ -611,9 +797,12 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
   // dynamic LDS: per-wave chain stages, the hidden biases, then (CACHE) per-wave item copies
   char* stage = lds_raw + (size_t)(threadIdx.x >> 6) * stage_bytes<T, NT, true>();
   const NetDev& net = nets[net_index];
-  double* lds_b = (double*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
-  stage_biases<T, double>(net, lds_b);
-  __syncthreads();
+  // biases in the chain type for the plain spec rows (tile partials in T), in FP64 for
+  // the dual ascent (its offsets are summed in FP64 per neuron)
+  using BT = std::conditional_t<DUALS, double, T>;
+  BT* lds_b = (BT*)(lds_raw + kWavesPerWG * stage_bytes<T, NT, true>());
+  stage_biases<T, BT>(net, lds_b);
+  lds_barrier();
   const int Hp = net.Hp;
   char* cache = (char*)lds_b + (((size_t)Hp * sizeof(double) + 15) & ~(size_t)15) +
                 (size_t)(threadIdx.x >> 6) * item_cache_bytes<T>(16 / net.R, Hp);
@@ -687,8 +876,8 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
     }
     auto ptape_at = [&](int col) -> gmut<T> { return as_global_mut((T*)fa.ptape + (size_t)col * fa.rows_pad + prow); };
     // seed margin: rounding of the FP64 seed g = a_L W_L to the chain type, times |h_{L-1}|
-    gconst<double> seed = as_global(net.seedW + (size_t)r * net.np[L - 1]);
-    gconst<double> seed_e = as_global(net.seedWe + (size_t)r * net.np[L - 1]);
+    gconst<T> seed = as_global((const T*)net.seedT + (size_t)r * net.np[L - 1]);
+    gconst<T> seed_m = as_global((const T*)net.seedM + (size_t)r * net.np[L - 1]);
     const int lbase = (L - 2) * 16 * NT;
     gmut<float> arow = as_global_mut(DUALS ? fa.alpha + ((size_t)s * R + r) * fa.H_max : (float*)nullptr);
     gmut<float> brow = as_global_mut(DUALS ? fa.beta + ((size_t)s * R + r) * fa.max_splits : (float*)nullptr);
@@ -701,10 +890,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = t * 16 + nrn<T>(gq, i);
-          const double gd = seed[m] * liveD;
-          const T gt = (T)gd;
-          const double hu = fmax(bu[m], 0.0) * liveD;
-          marg0 += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
+          if (live) marg0 += seed_m[m] * (T)fmax(bu[m], 0.0);
           if (i == 3) tile_fence<T, NT>();
         }
     }
@@ -718,7 +904,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
       T marg = marg0;
       {
         // seeds of tile t + 1 are loaded while tile t is stored
-        double sd_cur[4], sd_nxt[4];
+        T sd_cur[4], sd_nxt[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) sd_cur[i] = seed[nrn<T>(gq, i)];
 #pragma unroll
@@ -728,7 +914,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
             for (int i = 0; i < 4; ++i) sd_nxt[i] = seed[(t + 1) * 16 + nrn<T>(gq, i)];
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) st.set(t, i, (T)(sd_cur[i] * liveD));
+          for (int i = 0; i < 4; ++i) st.set(t, i, live ? sd_cur[i] : (T)0);
           tile_fence<T, NT>();
           if (t + 1 < NT) {
 #pragma unroll
@@ -742,7 +928,7 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
         for (int k = L - 1; k >= 1; --k) {
           const RelP rk = relb + (k - 1) * 16 * NT;
           if (!DUALS) {
-            relax_layer<T, NT, false>(st, rk, (lconst<double>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
+            relax_layer<T, NT, false>(st, rk, (lconst<BT>)(lds_b + (k - 1) * 16 * NT), gq, acc, acc2, marg);
           } else {
             lconst<double> bias = (lconst<double>)(lds_b + (k - 1) * 16 * NT);
             const int hoff = net.hoff[k - 1], nk = net.n[k];
@@ -1061,9 +1247,9 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
       item = blockIdx.x;
     } else {
       if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(ra.queue, 1u);
-      __syncthreads();
+      lds_barrier();
       item = S.misc[0];
-      __syncthreads();
+      lds_barrier();
     }
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
@@ -1083,7 +1269,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
     for (int p = tid; p < Hp; p += kWG) S.slot[p] = -1;
     if (tid == 0) S.misc[1] = 0;
     if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
-    __syncthreads();
+    lds_barrier();
     for (int step = 0; step < H; ++step) {
       // |x_m| bound over the TM, and the input-centre/radius for the layer-1 bounds
       if (tid < 16) {
@@ -1093,7 +1279,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
         Xab[tid] = tid < n0 ? a : 0.0;
         S.xc[tid] = 0.0; S.xr[tid] = 0.0;
       }
-      __syncthreads();
+      lds_barrier();
       // ---- layer 1 on the TM input: exact range of W_1 (c + P z + r) + b_1
       {
         const int n1 = net.n[1];
@@ -1125,13 +1311,13 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
           S.rel[p] = build_relax<T>(lo, hi, v, bj, false, n1, true, sc.margin_on);
         }
       }
-      __syncthreads();
+      lds_barrier();
       // ---- deeper hidden layers: shared-slope CROWN on the TM input, intersected with IBP
       for (int k = 2; k <= L - 1; ++k) {
         const int nk = net.n[k];
         const int base = (k - 1) * 16 * NT, pbase = (k - 2) * 16 * NT;
         relu_box<kWG>(S.l + pbase, S.u + pbase, 16 * NT, S.hc, S.hr);
-        __syncthreads();
+        lds_barrier();
         if (tid < 16 * NT) {
           const int j = tid;
           double lo = 0.0, hi = 0.0, v = 0.0;
@@ -1139,7 +1325,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
           S.ibl[j] = lo; S.ibu[j] = hi; S.v[j] = v;
           S.l[base + j] = lo; S.u[base + j] = hi;
         }
-        __syncthreads();
+        lds_barrier();
         auto unstable = [&](int j) { return j < nk && S.ibl[j] < 0.0 && S.ibu[j] > 0.0; };
         const int nU = compact_flags<kWG>(16 * NT, unstable, S.U, S.misc + 2);
         const int ntiles = (nU + 15) >> 4;
@@ -1188,7 +1374,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
             S.u[base + neuron] = fmin(S.ibu[neuron], hi);
           }
         }
-        __syncthreads();
+        lds_barrier();
         if (tid < 16 * NT) {
           const int j = tid;
           const int p = base + (j & ~15) + pos_of<T>(j & 15);
@@ -1200,14 +1386,14 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
           S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, false, nk, true, sc.margin_on);
         }
         if (tid == 0) sc.rows[(size_t)s * 8 + (k - 1)] += nU;
-        __syncthreads();
+        lds_barrier();
       }
       // ---- output rows e_r on x' (r < n_state): multipliers B_r on y, skip A_r
       if (wid == 0) {
         const int r = lane & 15;
         const bool valid = r < ns;
-        gconst<double> seed = as_global(net.seedW + (size_t)(valid ? r : 0) * net.np[L - 1]);
-        gconst<double> seed_e = as_global(net.seedWe + (size_t)(valid ? r : 0) * net.np[L - 1]);
+        gconst<T> seed = as_global((const T*)net.seedT + (size_t)(valid ? r : 0) * net.np[L - 1]);
+        gconst<T> seed_m = as_global((const T*)net.seedM + (size_t)(valid ? r : 0) * net.np[L - 1]);
         const int lbase = (L - 2) * 16 * NT;
         auto g = make_stage<T, NT>(stage, lane);
         T marg = 0;
@@ -1216,12 +1402,8 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int m = t * 16 + nrn<T>(gq, i);
-            double gd = seed[m] * (valid ? 1.0 : 0.0);
-            T gt = (T)gd;
-            g.set(t, i, gt);
-            double hu = fmax(S.u[lbase + m], 0.0);
-            if (sc.margin_on)
-              marg += (T)((fabs(gd - (double)gt) + 0x1p-50 * fabs(gd) + seed_e[m]) * hu * (1.0 + 0x1p-30));
+            g.set(t, i, valid ? seed[m] : (T)0);
+            if (sc.margin_on && valid) marg += seed_m[m] * (T)fmax(S.u[lbase + m], 0.0);
             if (i == 3) tile_fence<T, NT>();
           }
         double acc = net.seedB[valid ? r : 0] * ((valid && gq == 0) ? 1.0 : 0.0), acc2 = acc;
@@ -1270,21 +1452,21 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
         }
         if (lane == 0) sc.rows[(size_t)s * 8 + (L - 1)] += ns;
       }
-      __syncthreads();
+      lds_barrier();
       if (tid < 16) {
         c[tid] = tid < ns ? nc[tid] : 0.0;
         Ilo[tid] = tid < ns ? nIlo[tid] : 0.0;
         Ihi[tid] = tid < ns ? nIhi[tid] : 0.0;
       }
       for (int e = tid; e < 256; e += kWG) Pm[e] = ((e >> 4) < ns) ? nP[e] : 0.0;
-      __syncthreads();
+      lds_barrier();
     }
     if (tid == 0) {
       sc.st[s] = (uint32_t)S.misc[1];
       if (ra.status) ra.status[s] = (uint32_t)S.misc[1];
       if (sc.st_out) sc.st_out[s] = (uint32_t)S.misc[1];
     }
-    __syncthreads();
+    lds_barrier();
   }
 }
 

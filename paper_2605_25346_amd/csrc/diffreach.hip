@@ -59,6 +59,9 @@ struct dr_ctx {
   hipEvent_t fork_ev = nullptr;
   hipEvent_t join_ev[kMaxNets] = {};
   int cus = 0;
+  // launch configuration of each kernel kind and network, fixed at creation
+  const void* fn[Q_KINDS][kMaxNets] = {};
+  int block[Q_KINDS][kMaxNets] = {};
   int grid[Q_KINDS][kMaxNets] = {};
   size_t lds[Q_KINDS][kMaxNets] = {};
   dr::BatchDev batch{};
@@ -113,18 +116,12 @@ const void* pgrad_kernel_of(int NT, bool cache) {
   return instance<T>(NT, DR_KIND_PGRAD, cache ? 1 : 0);
 }
 
-// wlds: the bound kernel with LDS weights; for the dual ascent: the item-cached instance
-template <typename T>
-const void* kernel_of(int kind, int NT, bool wlds) {
-  static_assert(Q_BOUND == DR_KIND_BOUND && Q_FINAL == DR_KIND_FINAL && Q_DUAL == DR_KIND_DUAL &&
-                    Q_REACH == DR_KIND_REACH,
-                "queue kinds and kernel kinds share their numbering");
-  const bool variant = (kind == Q_BOUND || kind == Q_DUAL) && wlds;
-  return instance<T>(NT, kind, variant ? 1 : 0);
-}
+static_assert(Q_BOUND == DR_KIND_BOUND && Q_FINAL == DR_KIND_FINAL && Q_DUAL == DR_KIND_DUAL &&
+                  Q_REACH == DR_KIND_REACH,
+              "queue kinds and kernel kinds share their numbering");
 
-const void* kernel_for(const dr_ctx* c, int kind, int NT, bool wlds = false) {
-  return c->prec == DR_PREC_F64 ? kernel_of<double>(kind, NT, wlds) : kernel_of<float>(kind, NT, wlds);
+const void* kernel_for(const dr_ctx* c, int kind, int NT, int variant) {
+  return c->prec == DR_PREC_F64 ? instance<double>(NT, kind, variant) : instance<float>(NT, kind, variant);
 }
 
 // LDS of one compute unit (gfx950).
@@ -158,15 +155,17 @@ bool use_item_cache(const dr_ctx* c, const dr::NetDev& n) {
   return c->R <= 16 && final_lds_base(c, n) + item_cache_total(c, n) <= kMaxLds;
 }
 
-size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
+// `block`: threads per workgroup.
+size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n, int block = kWG) {
   const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
   if (kind == Q_FINAL) return final_lds_base(c, n);
   if (kind == Q_DUAL) return final_lds_base(c, n) + (use_item_cache(c, n) ? item_cache_total(c, n) : 0);
-  const size_t stages = dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, false);
-  const size_t biases = (size_t)n.Hp * (kind == Q_REACH ? tsz : sizeof(double));   // see stage_biases
+  const int waves = block / 64;
+  const size_t stages = (size_t)waves * dr::stage_bytes_rt(tsz, n.NT, false);
+  const size_t biases = (size_t)n.Hp * tsz;   // hidden biases staged in the chain type
   size_t b = c->prec == DR_PREC_F64 ? dr::SubLds<double>::bytes(n.Hp, n.NT) : dr::SubLds<float>::bytes(n.Hp, n.NT);
   if (kind == Q_BOUND) {
-    const size_t teams = n.NT <= 4 ? dr::kWavesPerWG : 1;   // per-wavefront subdomains for narrow networks
+    const size_t teams = n.NT <= 4 ? waves : 1;   // per-wavefront subdomains for narrow networks
     return stages + teams * b + (use_lds_weights(c, n) ? lds_weight_bytes(c, n) : 0) + biases;
   }
   return stages + b + dr::kReachExtraLds + biases;   // Q_REACH
@@ -176,16 +175,16 @@ size_t lds_bytes(const dr_ctx* c, int kind, const dr::NetDev& n) {
 // calculator, optionally capped by the launch configuration chosen by the autotuner:
 // tile_cfg holds one 4-bit cap per kernel kind (bits 4*kind .. 4*kind+3; 0 = as many
 // workgroups per CU as fit).
-int persistent_grid(dr_ctx* c, const void* fn, size_t lds, int kind) {
+int persistent_grid(dr_ctx* c, const void* fn, size_t lds, int kind, int block = kWG) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kWG, lds) != hipSuccess || nb < 1) nb = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, block, lds) != hipSuccess || nb < 1) nb = 1;
   const int cap = (c->tile_cfg >> (4 * kind)) & 15;
   if (cap > 0) nb = std::min(nb, cap);
   return std::max(1, nb * c->cus);
 }
 
-dr_status launch(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, hipStream_t stream) {
-  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(kWG), args, lds, stream);
+dr_status launch(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, hipStream_t stream, int block = kWG) {
+  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(block), args, lds, stream);
   if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
   return DR_OK;
 }
@@ -213,11 +212,15 @@ dr_status join_nets(dr_ctx* c, hipStream_t s) {
 
 // A persistent launch: clear its queue, then launch (same stream, so in order).
 dr_status launch_persistent(dr_ctx* c, const void* fn, int grid, size_t lds, void** args, unsigned* q,
-                            hipStream_t stream) {
+                            hipStream_t stream, int block = kWG) {
   hipLaunchKernelGGL(dr::k_reset_queue, dim3(1), dim3(64), 0, stream, q);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(c, e, "queue reset");
-  return launch(c, fn, grid, lds, args, stream);
+  return launch(c, fn, grid, lds, args, stream, block);
+}
+// The persistent launch of kernel kind `kind` for network i with its stored configuration.
+dr_status launch_kind(dr_ctx* c, int kind, int i, void** args, unsigned* q, hipStream_t stream) {
+  return launch_persistent(c, c->fn[kind][i], c->grid[kind][i], c->lds[kind][i], args, q, stream, c->block[kind][i]);
 }
 
 dr_status check_batch(dr_ctx* c, const dr_batch* b) {
@@ -268,6 +271,7 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   // seeds of the final rows
   const int npLm1 = nd.np[L - 1];
   double *seedW, *seedB, *skip, *seedA, *seedWe, *seedBe, *skipE;
+  T *seedT, *seedM;
   if (alloc) {
     if ((e = ctx_alloc(c, &seedW, sizeof(double) * nd.R * npLm1)) != hipSuccess ||
         (e = ctx_alloc(c, &seedB, sizeof(double) * nd.R)) != hipSuccess ||
@@ -275,13 +279,16 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
         (e = ctx_alloc(c, &seedA, sizeof(double) * nd.R * nd.np[L])) != hipSuccess ||
         (e = ctx_alloc(c, &seedWe, sizeof(double) * nd.R * npLm1)) != hipSuccess ||
         (e = ctx_alloc(c, &seedBe, sizeof(double) * nd.R)) != hipSuccess ||
-        (e = ctx_alloc(c, &skipE, sizeof(double) * nd.R * 16)) != hipSuccess)
+        (e = ctx_alloc(c, &skipE, sizeof(double) * nd.R * 16)) != hipSuccess ||
+        (e = ctx_alloc(c, &seedT, sizeof(T) * nd.R * npLm1)) != hipSuccess ||
+        (e = ctx_alloc(c, &seedM, sizeof(T) * nd.R * npLm1)) != hipSuccess)
       return hip_fail(c, e, "hipMalloc");
     nd.seedW = seedW; nd.seedB = seedB; nd.skip = skip; nd.seedA = seedA;
-    nd.seedWe = seedWe; nd.seedBe = seedBe; nd.skipE = skipE;
+    nd.seedWe = seedWe; nd.seedBe = seedBe; nd.skipE = skipE; nd.seedT = seedT; nd.seedM = seedM;
   } else {
     seedW = (double*)nd.seedW; seedB = (double*)nd.seedB; skip = (double*)nd.skip; seedA = (double*)nd.seedA;
     seedWe = (double*)nd.seedWe; seedBe = (double*)nd.seedBe; skipE = (double*)nd.skipE;
+    seedT = (T*)nd.seedT; seedM = (T*)nd.seedM;
   }
   // the spec: a context-owned copy of the caller's (or the default [I], q = n_target)
   const int n_target = nd.n_state > 0 ? nd.n_state : nd.n[L];
@@ -303,7 +310,7 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
   const int tot = nd.R * npLm1;
   hipLaunchKernelGGL((dr::k_seeds<T>), dim3((tot + 255) / 256), dim3(256), 0, stream, (const T*)nd.Wn[L - 1],
                      (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nd.A, c->B_dev[net_i], nd.n[0], nd.np[L],
-                     seedW, seedB, skip, seedA, seedWe, seedBe, skipE);
+                     seedW, seedB, skip, seedA, seedWe, seedBe, skipE, seedT, seedM);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
   return DR_OK;
 }
@@ -469,17 +476,24 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
   for (int i = 0; i < n_nets; ++i) {
     const dr::NetDev& nd = c->hnet[i];
     for (int kind = 0; kind < Q_KINDS; ++kind) {
-      const void* fn = kernel_for(c, kind, nd.NT, (kind == Q_BOUND && use_lds_weights(c, nd)) ||
-                                                      (kind == Q_DUAL && use_item_cache(c, nd)));
+      int variant = 0, block = kWG;
+      if (kind == Q_BOUND) {
+        variant = use_lds_weights(c, nd) ? 1 : 0;
+      } else if (kind == Q_DUAL) {
+        variant = use_item_cache(c, nd) ? 1 : 0;
+      }
+      const void* fn = kernel_for(c, kind, nd.NT, variant);
       if (!fn) return bail(fail(c, DR_ESHAPE, "no kernel instance for this width"));
-      const size_t lds = lds_bytes(c, kind, nd);
+      const size_t lds = lds_bytes(c, kind, nd, block);
       if (lds > kMaxLds) return bail(fail(c, DR_ESHAPE, "network too deep for the on-chip state of its kernels"));
       if (lds > 0) {
         e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return bail(hip_fail(c, e, "hipFuncSetAttribute"));
       }
+      c->fn[kind][i] = fn;
+      c->block[kind][i] = block;
       c->lds[kind][i] = lds;
-      c->grid[kind][i] = persistent_grid(c, fn, lds, kind);
+      c->grid[kind][i] = persistent_grid(c, fn, lds, kind, block);
     }
     const size_t waves = (size_t)c->grid[Q_DUAL][i] * dr::kWavesPerWG;
     c->tape_off[i] = tape_bytes;
@@ -557,16 +571,14 @@ dr_status dr_bound_init(dr_ctx* c, const dr_batch* b, uint32_t* status, hipStrea
   }
   if ((st = fork_nets(c, stream)) != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
-    const dr::NetDev& nd = c->hnet[i];
-    const void* fn = kernel_for(c, Q_BOUND, nd.NT, use_lds_weights(c, nd));
     int net_index = i, inter = c->inter, ms = c->max_splits;
     dr::BatchDev bd = c->batch;
     dr::Scratch sc = c->sc;
     sc.st_out = status;
-    unsigned* q = queue_of(c, Q_BOUND, i);
-    void* args[] = {&c->dnet, &net_index, &bd, &sc, &q, &inter, &ms};
-    if ((st = launch_persistent(c, fn, c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, q, net_stream(c, stream, i))) !=
-        DR_OK)
+    void* args[] = {&c->dnet, &net_index, &bd, &sc, &inter, &ms};
+    // static item assignment: no queue to clear
+    if ((st = launch(c, c->fn[Q_BOUND][i], c->grid[Q_BOUND][i], c->lds[Q_BOUND][i], args, net_stream(c, stream, i),
+                     c->block[Q_BOUND][i])) != DR_OK)
       return st;
   }
   if ((st = join_nets(c, stream)) != DR_OK) return st;
@@ -589,14 +601,12 @@ static dr_status run_final(dr_ctx* c, bool duals, dr::FinalArgs fa, hipStream_t 
   dr_status st = fork_nets(c, stream);
   if (st != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
-    const dr::NetDev& nd = c->hnet[i];
     const int kind = duals ? Q_DUAL : Q_FINAL;
-    const void* fn = kernel_for(c, kind, nd.NT, duals && use_item_cache(c, nd));
     fa.queue = queue_of(c, kind, i);
     fa.tape = (char*)c->tape + c->tape_off[i];
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &fa};
-    st = launch_persistent(c, fn, c->grid[kind][i], c->lds[kind][i], args, fa.queue, net_stream(c, stream, i));
+    st = launch_kind(c, kind, i, args, fa.queue, net_stream(c, stream, i));
     if (st != DR_OK) return st;
   }
   return join_nets(c, stream);
@@ -797,16 +807,12 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
   }
   if ((st = fork_nets(c, stream)) != DR_OK) return st;
   for (int i = 0; i < c->n_nets; ++i) {
-    const dr::NetDev& nd = c->hnet[i];
-    const void* fn = kernel_for(c, Q_REACH, nd.NT);
     dr::ReachArgs ra{};
     ra.batch = c->batch; ra.sc = c->sc; ra.sc.st_out = nullptr; ra.queue = queue_of(c, Q_REACH, i);
     ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};
-    if ((st = launch_persistent(c, fn, c->grid[Q_REACH][i], c->lds[Q_REACH][i], args, ra.queue,
-                                 net_stream(c, stream, i))) != DR_OK)
-      return st;
+    if ((st = launch_kind(c, Q_REACH, i, args, ra.queue, net_stream(c, stream, i))) != DR_OK) return st;
   }
   if ((st = join_nets(c, stream)) != DR_OK) return st;
   return DR_OK;

@@ -95,6 +95,11 @@ struct NetDev {
   const double* seedWe;
   const double* seedBe;
   const double* skipE;
+  // the seeds g in the chain type (R x np_{L-1}) and, per entry, the margin coefficient
+  // of the seed (its rounding to the chain type plus seedWe, rounded up), so a final
+  // row's seed margin is sum_m seedM[m] max(u_m, 0) over the last hidden layer
+  const void* seedT;
+  const void* seedM;
   const double* A;           // n_state x n_0 (closed loop) or null
   int n_state;
   int q;                     // spec directions
@@ -164,11 +169,38 @@ __device__ __forceinline__ int next_item(unsigned* q, bool& first, int worker, i
   return n_workers + wave_fetch(q);
 }
 
-// Sum over the four lane groups holding the same row (lanes n, n+16, n+32, n+48).
+// Sum over the four lane groups holding the same row (lanes n, n+16, n+32, n+48):
+// (v + v[l ^ 16]) then the same with l ^ 32, exchanged with v_permlane16_swap and
+// v_permlane32_swap (VALU lane swaps, no LDS round trip).  With x = y = v, the two
+// results of a swap are, per lane, its own value and its partner's (in an order that
+// depends on the lane), so their sum is v + v[l ^ 16] (resp. l ^ 32) on every lane,
+// bit-identical on both partners (addition is commutative).
+__device__ __forceinline__ float xor_pair_sum16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float xor_pair_sum32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ double xor_pair_sum16(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)b, (uint32_t)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+  const double d0 = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+  const double d1 = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+  return d0 + d1;
+}
+__device__ __forceinline__ double xor_pair_sum32(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+  const double d0 = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+  const double d1 = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+  return d0 + d1;
+}
 template <typename S> __device__ __forceinline__ S row_sum(S v) {
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+  return xor_pair_sum32(xor_pair_sum16(v));
 }
 
 // ---------------------------------------------------------------------------
