@@ -1,0 +1,244 @@
+"""Parity of the benchmarked launches at their own sizes and arithmetic, on sampled
+work items (the oracle computes them one by one), plus reach cases where the
+controller's contribution to the next state is not small.
+
+* Dual ascent, 8-128x4-4, 2048 subdomains, 20 steps, FP32 chains with rigorous margins
+  (the benchmarked launch): the GPU's final duals and intermediate bounds are replayed
+  into the oracle (its bound of every row at those duals, Theorem "CROWN linear bounds
+  of NN" with the split multipliers of the preamble's notation).  The GPU bound at the
+  final iterate lies below the replayed value (the margin covers the rounding) by at
+  most its reported margin plus the FP32 rounding of the relaxation; the best-so-far
+  bound is at least the final iterate's; the iterates stay feasible.
+* Mixed persistent batch, 16384 subdomains over three networks, CROWN + 10 steps: the
+  same replay on a sample covering all three networks, and the plain-CROWN bounds of
+  the sample against the oracle (sound side, gap within the margin).
+* TM reach, 12-256x3-4 controller, 8192 boxes, horizon 10 (the 256-wide queue path of
+  the reach kernel): sampled boxes sound at every step with FP32 rigorous margins (the
+  first step within its margin; later steps carry the earlier margins through the
+  Taylor-model composition, the per-step gap is printed), and within the plain FP32
+  tolerance at every step with margins off (Algorithm "Reachability of DT Dynamics",
+  Theorem "CROWN bounds of NN with linear TM input").
+* Closed loops where |B f(x)| is comparable to |A x| (short horizon), so that the
+  controller's bounds, not the linear part, set the box widths.
+"""
+import numpy as np
+import pytest
+
+from oracle import crown, tm
+from paper_2605_25346_amd.workloads import config_workload, make_workload
+from tests.gpu_helpers import near_tie, print_stats, rel_gap, require_gpu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _layers(net, flat):
+    offs = np.concatenate([[0], np.cumsum(net.hidden)])
+    return [flat[offs[k]:offs[k + 1]] for k in range(len(net.hidden))]
+
+
+def _replay_final_duals(wl, ctx, idx, duals, lb_best, ub_best, tag):
+    """Re-evaluate the GPU's final iterate on the GPU (iters = 0) and replay it into the
+    oracle with the GPU's own intermediate bounds."""
+    alpha, beta = duals
+    lbf, ubf, _, _, _ = ctx.dr_optimize_duals(0, 0.0, alpha, beta, init_duals=False)
+    marg = ctx.dr_get_margins()
+    l, u = ctx.dr_get_bounds()
+    torch.cuda.synchronize()
+    lbf, ubf, marg = lbf.cpu().numpy(), ubf.cpu().numpy(), marg.cpu().numpy()
+    l, u = l.cpu().numpy(), u.cpu().numpy()
+    al, be = alpha.cpu().numpy().astype(np.float64), beta.cpu().numpy().astype(np.float64)
+    gaps, over = [], []
+    for s in idx:
+        net = wl.nets[int(wl.batch.net_id[s])]
+        H = sum(net.hidden)
+        sp = wl.batch.splits_of(s)
+        xc, xr = wl.batch.x_center[s], wl.batch.x_radius[s]
+        bounds = list(zip(_layers(net, l[s, :H]), _layers(net, u[s, :H])))
+        # the iterates stay in their feasible sets
+        uns = np.concatenate([crown.relu_relaxation(*b)[0] == crown.UNSTABLE for b in bounds])
+        assert np.all((al[s][:, :H][:, uns] >= 0) & (al[s][:, :H][:, uns] <= 1)), s
+        assert np.all(be[s][:, :len(sp)] >= 0), s
+        rowlb = crown.evaluate_duals(net, bounds, xc, xr, al[s][:, :H], be[s][:, :len(sp)], sp, grad=False)[0]
+        got = np.concatenate([lbf[s], -ubf[s]])
+        scale = np.maximum(1.0, np.abs(rowlb))
+        # sound side: the GPU bound at the iterate lies below the exact-arithmetic value
+        assert np.all(got <= rowlb + 1e-6 * scale), (tag, s, (got - rowlb).max())
+        # and by no more than its margin plus the FP32 rounding of chord slopes/intercepts
+        slack = rowlb - got
+        assert np.all(slack <= marg[s] * 1.01 + 1e-5 * scale), (tag, s, (slack - marg[s]).max())
+        # best-so-far is at least the final iterate's bound
+        assert np.all(lb_best[s] >= lbf[s] - 1e-12 * np.maximum(1, np.abs(lbf[s])))
+        assert np.all(ub_best[s] <= ubf[s] + 1e-12 * np.maximum(1, np.abs(ubf[s])))
+        gaps.append(slack / scale)
+        over.append(np.maximum(slack - marg[s], 0) / scale)
+    print_stats(f"{tag}: replay gap (rel, incl. margin)", gaps)
+    print_stats(f"{tag}: replay gap beyond the margin (rel)", over)
+
+
+def _ascent(ctx, iters, lr):
+    """The benchmarked ascent (init at plain CROWN); returns bounds, status and the
+    final duals (device tensors)."""
+    alpha, beta = ctx.new_duals()
+    lb, ub, st, _, _ = ctx.dr_optimize_duals(iters, lr, alpha, beta, init_duals=True)
+    torch.cuda.synchronize()
+    return lb.cpu().numpy(), ub.cpu().numpy(), st.cpu().numpy(), (alpha, beta)
+
+
+def test_cfg3_ascent_full_size_replay():
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(3)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision="f32", max_sub=S, max_splits=16)
+    db = DeviceBatch(wl.batch)
+    ctx.dr_bound_init(db)
+    print(f"[cfg3 full] S={S} iters={wl.iters} f32 rigorous", flush=True)
+    lb, ub, st, duals = _ascent(ctx, wl.iters, wl.lr)
+    live = np.nonzero((st & 9) == 0)[0]
+    assert live.size > S // 2
+    idx = np.random.default_rng(3).choice(live, 48, replace=False)
+    _replay_final_duals(wl, ctx, idx, duals, lb, ub, "cfg3 full f32 ascent")
+    ctx.close()
+
+
+def test_cfg5_mixed_full_size_sampled():
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(5)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision="f32", max_sub=S, max_splits=32)
+    db = DeviceBatch(wl.batch)
+    print(f"[cfg5 full] S={S} CROWN + {wl.iters} steps, f32 rigorous", flush=True)
+    lb0, ub0, st0, _ = ctx.crown(db)
+    marg0 = ctx.dr_get_margins()
+    torch.cuda.synchronize()
+    lb0, ub0, st0, marg0 = lb0.cpu().numpy(), ub0.cpu().numpy(), st0.cpu().numpy(), marg0.cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.concatenate([rng.choice(np.nonzero((wl.batch.net_id == k) & ((st0 & 9) == 0))[0], 8, replace=False)
+                          for k in range(3)])
+    q = ctx.q
+    gaps = []
+    for s in idx:
+        net = wl.nets[int(wl.batch.net_id[s])]
+        o = crown.crown(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.batch.splits_of(s))
+        if o["status"]:
+            continue
+        ref = np.concatenate([o["lb"], -o["ub"]])
+        got = np.concatenate([lb0[s], -ub0[s]])
+        scale = np.maximum(1.0, np.abs(ref))
+        if not near_tie(o["bounds"], 1e-4):
+            assert np.all(got <= ref + 1e-6 * scale), (s, (got - ref).max())
+        gaps.append(np.abs(got - ref) / scale)
+    print_stats("cfg5 full f32 plain CROWN gap (rel, incl. margin)", gaps)
+    lb, ub, st, duals = _ascent(ctx, wl.iters, wl.lr)
+    assert np.all(lb[idx] >= lb0[idx] - 1e-12 * np.maximum(1, np.abs(lb0[idx])))
+    _replay_final_duals(wl, ctx, idx, duals, lb, ub, "cfg5 full f32 ascent")
+    ctx.close()
+
+
+@pytest.mark.parametrize("margins", [True, False])
+def test_cfg4_reach_full_size_sampled(margins):
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(4)
+    S = wl.batch.n_sub
+    net = wl.nets[0]
+    ctx = BoundContext(wl.nets, precision="f32", max_sub=S, margins=margins)
+    print(f"[cfg4 full] S={S} horizon={wl.horizon} f32 margins={margins}", flush=True)
+    boxes, st = ctx.dr_reach_dt(DeviceBatch(wl.batch), wl.horizon)
+    torch.cuda.synchronize()
+    boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    gaps = []
+    for s in np.random.default_rng(4).choice(S, 24, replace=False):
+        ob, _ = tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], wl.horizon)
+        g = rel_gap(boxes[s], ob)
+        if margins:
+            assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0]))), s
+            assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1]))), s
+            assert np.all(g[1] <= 5e-3), (s, g[1].max())     # one step: the rigorous margin itself
+        else:
+            assert np.all(g <= 3e-5), (s, g.max(axis=(1, 2)))
+        gaps.append(g)
+    gaps = np.array(gaps)
+    print(f"[cfg4 full f32 margins={margins}] per-step max gap "
+          + " ".join(f"{v:.1e}" for v in gaps.max(axis=(0, 2, 3))), flush=True)
+    print(f"[cfg4 full f32 margins={margins}] per-step median gap "
+          + " ".join(f"{v:.1e}" for v in np.median(gaps.max(axis=(2, 3)), axis=0)), flush=True)
+
+
+@pytest.mark.parametrize("width", [64, 256])
+def test_reach_where_the_controller_matters(width):
+    """x' = A x + B f(x) with B ~ N(0, 0.3) (the recipe of the one-step closed loop) and
+    A of spectral radius 0.5: the controller term is of the same size as A x, so an
+    error in the controller's bounds shows in the boxes (horizon 3)."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = make_workload(f"cl{width}", 90 + width, [[8, width, width, 4]], 12, closed_loop=True, radius=0.02,
+                       horizon=3, shared_slope=True, A_mode="signed_perm", rho=0.5, b_var=0.3)
+    net = wl.nets[0]
+    xc, xr = wl.batch.x_center, wl.batch.x_radius
+    # the controller's share of the next state at the box centres
+    y = np.stack([crown_forward(net, xc[s]) for s in range(12)])
+    ctrl = np.abs(y @ net.B.T).mean()
+    lin = np.abs(xc @ net.A.T).mean()
+    print(f"[reach width {width}] mean |B f(x)| = {ctrl:.3f}, mean |A x| = {lin:.3f}", flush=True)
+    assert ctrl > 0.3 * lin
+    oracle = [tm.reach_dt(net, xc[s], xr[s], wl.horizon)[0] for s in range(12)]
+    # FP64 with margins: the margins (about 1e-12 relative per step) are carried and
+    # amplified by the expanding loop; FP32 without margins: the arithmetic alone
+    for precision, margins, tol in (("f64", False, 1e-9), ("f64", True, 1e-8), ("f32", False, 1e-5),
+                                    ("f32", True, None)):
+        ctx = BoundContext(wl.nets, precision=precision, max_sub=12, margins=margins)
+        boxes, st = ctx.dr_reach_dt(DeviceBatch(wl.batch), wl.horizon)
+        torch.cuda.synchronize()
+        boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        gaps = []
+        for s in range(12):
+            ob = oracle[s]
+            g = rel_gap(boxes[s], ob)
+            if margins:
+                assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
+                assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
+            if tol is not None:
+                assert np.all(g <= tol), (precision, margins, s, g.max(axis=(1, 2)))
+            gaps.append(g)
+        print_stats(f"reach width {width} {precision} margins={margins}", gaps)
+        ctx.close()
+
+
+def test_cfg1_f64_without_margins_to_1e12():
+    """The one-step closed loop in FP64 on both sides with the rounding margins off: the
+    chains' arithmetic itself agrees with the oracle to 1e-12 relative."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(1)
+    S = wl.batch.n_sub
+    ctx = BoundContext(wl.nets, precision="f64", max_sub=S, margins=False)
+    lb, ub, st, _ = ctx.crown(DeviceBatch(wl.batch))
+    torch.cuda.synchronize()
+    lb, ub = lb.cpu().numpy(), ub.cpu().numpy()
+    gaps, flagged = [], 0
+    for s in range(S):
+        o = crown.crown(wl.nets[0], wl.batch.x_center[s], wl.batch.x_radius[s])
+        if near_tie(o["bounds"], 1e-12):
+            flagged += 1
+            continue
+        g = np.concatenate([rel_gap(lb[s], o["lb"]), rel_gap(ub[s], o["ub"])])
+        assert np.all(g <= 1e-12), (s, g.max())
+        gaps.append(g)
+    print_stats(f"cfg1 f64 no margins ({flagged} tie-flagged)", gaps)
+    assert len(gaps) >= S - 2
+    ctx.close()
+
+
+def crown_forward(net, x):
+    """Plain forward pass of the network (FP64) at one point."""
+    h = np.asarray(x, np.float64)
+    for k, (W, b) in enumerate(zip(net.Ws, net.bs)):
+        h = W.astype(np.float64) @ h + b.astype(np.float64)
+        if k < len(net.Ws) - 1:
+            h = np.maximum(h, 0.0)
+    return h

@@ -423,13 +423,11 @@ def test_tm_reach_narrow_networks(width):
         ctx.close()
 
 
-def _step_tol(tol0, H, growth=3.0):
-    """Per-step tolerance of a reach comparison: a rounding difference of the first
-    step is carried by the Taylor-model composition of the later steps, whose
-    interval part grows by up to ~3x per step on the candidate-action workload (the
-    oracle's own widths grow up to 60x over 10 steps); tol(t) = tol0 growth^(t-1)."""
-    t = np.arange(H + 1)
-    return tol0 * growth ** np.maximum(t - 1, 0)
+# Per-step tolerance of the multi-step reach comparisons, set from the measured gaps of
+# the candidate-action loop (expanding: the oracle's own widths grow up to 60x in 10
+# steps): FP32 chains without margins stay within ~1e-5 of the oracle at every step
+# (measured 9.4e-6 at step 10), FP64 within ~3e-9 with margins and ~1e-12 without.
+REACH_TOL = {("f64", False): 1e-9, ("f64", True): 1e-8, ("f32", False): 3e-5}
 
 
 def test_exogenous_reach_candidates():
@@ -450,7 +448,6 @@ def test_exogenous_reach_candidates():
         with pytest.raises(B.DrError) as ei:
             ctx.dr_reach_dt(db, H)           # the inputs are required
         assert ei.value.status == B.DR_EINVAL
-        tol0 = 1e-9 if precision == "f64" else 1e-5
         for horizon in (1, H):
             boxes, st = ctx.dr_reach_dt(db, horizon, u=u[:, :horizon])
             torch.cuda.synchronize()
@@ -464,12 +461,12 @@ def test_exogenous_reach_candidates():
                 if margins:
                     assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0])))
                     assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1])))
-                if precision == "f64" or not margins:
-                    tol = _step_tol(tol0, horizon)
-                    if precision == "f64" and margins:
-                        tol = tol * 10          # the FP64 rounding margins ride on top
-                    assert np.all(g <= tol[:, None, None]), (precision, margins, horizon, s, g.max(axis=(1, 2)))
-            print_stats(f"cfg6 exogenous reach {precision} margins={margins} horizon={horizon}", gaps)
+                tol = REACH_TOL.get((precision, margins))
+                if tol is not None:
+                    assert np.all(g <= tol), (precision, margins, horizon, s, g.max(axis=(1, 2)))
+            gaps = np.array(gaps)
+            print(f"[cfg6 exogenous reach {precision} margins={margins} horizon={horizon}] per-step max gap "
+                  + " ".join(f"{v:.1e}" for v in gaps.max(axis=(0, 2, 3))), flush=True)
         ctx.close()
 
 
