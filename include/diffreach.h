@@ -109,15 +109,24 @@ typedef struct {
   int intermediate;           /* DR_INTER_CROWN_IBP (default) or DR_INTER_IBP */
   int max_sub;                /* capacity: largest batch S for this context */
   int max_splits;             /* capacity: splits per subdomain (beta columns) */
-  int tile_cfg;               /* launch configuration: 4-bit cap of workgroups per CU per kernel kind
-                                 (bits 0-3 bound_init, 4-7 spec chains, 8-11 dual ascent, 12-15
-                                 reach_dt; 0 = as many as fit), as chosen by the autotuner */
+  int tile_cfg;               /* launch and tile configuration, as chosen by the autotuner (0 = defaults):
+                                 bits 0-15: 4-bit cap of workgroups per CU per kernel kind (bits 0-3
+                                 bound_init, 4-7 spec chains, 8-11 dual ascent, 12-15 reach_dt; 0 = as
+                                 many as fit); DR_TILE_* flags below */
   int margin_mode;            /* DR_MARGIN_RIGOROUS (default) or DR_MARGIN_OFF (diagnostics only:
                                  rounding of the chains is then not covered, bounds may be unsound) */
   int fuse_spec;              /* 1: dr_bound_init also runs the plain-CROWN spec rows while each
                                  subdomain's relaxation is on chip, and dr_propagate_backward only
                                  lays them out; 0: dr_propagate_backward runs the spec chains */
 } dr_options;
+
+/* Flags of dr_options.tile_cfg (kernel variants; results are identical up to rounding):
+ *   DR_TILE_GLOBAL_WEIGHTS  bound kernel of narrow networks reads the weights from global
+ *                           memory instead of a per-workgroup LDS copy;
+ *   DR_TILE_PAIRED_TILES    bound kernel of narrow FP32 networks: two 16-row tiles per chain
+ *                           step of a wavefront instead of one (shared loads, more registers);
+ *   DR_TILE_NO_ITEM_CACHE   dual ascent without the per-item LDS copy of the relaxation. */
+enum { DR_TILE_GLOBAL_WEIGHTS = 1 << 16, DR_TILE_PAIRED_TILES = 1 << 17, DR_TILE_NO_ITEM_CACHE = 1 << 18 };
 
 /* Create a context for one or more networks sharing n_0 and the spec length.
  * Copies and re-lays-out the weights (asynchronously on `stream`) and allocates

@@ -98,11 +98,13 @@ class BoundContext:
         opt.max_sub = max_sub
         opt.max_splits = max_splits
         if tile_cfg == "auto":
+            # the autotuner's choice for these network shapes (defaults when not tuned)
             from .autotune import lookup
-            tile_cfg = lookup(nets, precision)
+            tile_cfg, fuse_spec = lookup(nets, precision)
         opt.tile_cfg = int(tile_cfg)
         opt.margin_mode = B.DR_MARGIN_RIGOROUS if margins else B.DR_MARGIN_OFF
         opt.fuse_spec = 1 if fuse_spec else 0
+        self.tile_cfg, self.fuse_spec = int(tile_cfg), bool(fuse_spec)
         ctx = ctypes.c_void_p()
         st = self.lib.dr_create(ctypes.byref(ctx), structs, len(nets), ctypes.byref(opt), _stream())
         B.check(st, None)

@@ -20,6 +20,7 @@ DR_PREC_F32, DR_PREC_F64 = 0, 1
 DR_DTYPE_F32, DR_DTYPE_F64 = 0, 1
 DR_INTER_CROWN_IBP, DR_INTER_IBP = 0, 1
 DR_MARGIN_RIGOROUS, DR_MARGIN_OFF = 0, 1
+DR_TILE_GLOBAL_WEIGHTS, DR_TILE_PAIRED_TILES, DR_TILE_NO_ITEM_CACHE = 1 << 16, 1 << 17, 1 << 18
 
 EXPORTED = [
     "dr_create", "dr_bound_init", "dr_propagate_backward", "dr_concretize", "dr_optimize_duals",

@@ -397,15 +397,15 @@ __device__ __forceinline__ void relu_box(const double* l, const double* u, int n
 // a1-a4: intermediate bounds, persistent.  TPS threads own one subdomain at a time:
 // a whole workgroup (TPS = 256, wide networks: the chain tiles of a layer are spread
 // over its four waves) or one wavefront (TPS = 64, narrow networks: four subdomains
-// per workgroup progress independently, no workgroup barriers).  Narrow FP32 networks
-// process their row tiles in pairs and ask for two waves per SIMD (a register budget
-// of 256, which the paired tiles fill); the others keep one tile at a time.
+// per workgroup progress independently, no workgroup barriers).  NR = 2 (a variant for
+// narrow FP32 networks) processes the row tiles of a wavefront in pairs and asks for two
+// waves per SIMD (a register budget of 256, which the paired tiles fill).
 // ---------------------------------------------------------------------------
-template <typename T, int TPS> constexpr int bound_tiles_per_step() { return sizeof(T) == 4 && TPS == 64 ? 2 : 1; }
-template <typename T, int TPS> constexpr int bound_min_waves() { return bound_tiles_per_step<T, TPS>() == 2 ? 2 : 1; }
+// NR: row tiles per chain step of a wavefront (1, or 2 for narrow FP32 networks).
+template <int NR> constexpr int bound_min_waves() { return NR == 2 ? 2 : 1; }
 
-template <typename T, int NT, bool WLDS, int TPS>
-__global__ void __launch_bounds__(kWG, (bound_min_waves<T, TPS>()))
+template <typename T, int NT, bool WLDS, int TPS, int NR = 1>
+__global__ void __launch_bounds__(kWG, (bound_min_waves<NR>()))
 k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch, Scratch sc, int inter_mode,
              int max_splits) {
   constexpr int kWaves = kWavesPerWG;
@@ -545,20 +545,20 @@ k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch, Scr
       if constexpr (TPS == 64) {
         // one subdomain per wavefront: row tiles in pairs (a last odd tile alone)
         auto rows_n = [&](auto nr_tag, int tile0) {
-          constexpr int NR = decltype(nr_tag)::value;
+          constexpr int NRS = decltype(nr_tag)::value;
           const int gq = lane >> 4;
-          T g[NR][NT][4];
-          double acc[NR];
-          T marg[NR];
-          T w[NR][1][4];
-          int row[NR], neuron[NR];
-          bool valid[NR];
+          T g[NRS][NT][4];
+          double acc[NRS];
+          T marg[NRS];
+          T w[NRS][1][4];
+          int row[NRS], neuron[NRS];
+          bool valid[NRS];
           // seeds: rows +-e_j at z_k, i.e. +-W_k[j][:] over h_{k-1}, one vector load per
           // 16-neuron tile from the adjoint-swizzled copy (block (j / 16, tile), lane
           // j % 16 + 16 gq holds W_k[j][16 tile + nrn(gq, 0..3)])
           gconst<V4<T>> Wa = as_global(uniform_ptr((const V4<T>*)net.Wa[k - 1]));
 #pragma unroll
-          for (int r = 0; r < NR; ++r) {
+          for (int r = 0; r < NRS; ++r) {
             row[r] = (tile0 + r) * 16 + (lane & 15);
             valid[r] = row[r] < nrows;
             neuron[r] = valid[r] ? S.U[row[r] >> 1] : 0;
@@ -574,9 +574,9 @@ k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch, Scr
             acc[r] = (gq == 0 ? (double)sg : 0.0) * (double)lds_b[(k - 1) * n16 + neuron[r]];
             marg[r] = 0;
           }
-          chain_to_input_n<T, NT, NR, WLDS>(net, k, g, S.rel, acc, marg, w, lane, lds_b, lds_w);
+          chain_to_input_n<T, NT, NRS, WLDS>(net, k, g, S.rel, acc, marg, w, lane, lds_b, lds_w);
 #pragma unroll
-          for (int r = 0; r < NR; ++r) {
+          for (int r = 0; r < NRS; ++r) {
             double conc = 0.0, wabs = 0.0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -596,7 +596,7 @@ k_bound_init(const NetDev* __restrict__ nets, int net_index, BatchDev batch, Scr
             }
           }
         };
-        constexpr int NR = bound_tiles_per_step<T, TPS>();
+        static_assert(NR == 1 || (NR == 2 && TPS == 64), "tile pairs need one subdomain per wavefront");
         int tile = 0;
         if constexpr (NR == 2)
           for (; tile + 1 < ntiles; tile += 2) rows_n(std::integral_constant<int, 2>{}, tile);

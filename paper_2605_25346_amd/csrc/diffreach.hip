@@ -134,7 +134,7 @@ size_t lds_weight_bytes(const dr_ctx* c, const dr::NetDev& n) {
   return (size_t)dr::lds_w_count(n.L, n.NT) * v4;
 }
 bool use_lds_weights(const dr_ctx* c, const dr::NetDev& n) {
-  return n.NT <= 4 && lds_weight_bytes(c, n) <= kLdsWeightBudget;
+  return n.NT <= 4 && lds_weight_bytes(c, n) <= kLdsWeightBudget && !(c->tile_cfg & DR_TILE_GLOBAL_WEIGHTS);
 }
 
 
@@ -152,7 +152,7 @@ size_t final_lds_base(const dr_ctx* c, const dr::NetDev& n) {
   return dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, true) + (((size_t)n.Hp * sizeof(double) + 15) & ~(size_t)15);
 }
 bool use_item_cache(const dr_ctx* c, const dr::NetDev& n) {
-  return c->R <= 16 && final_lds_base(c, n) + item_cache_total(c, n) <= kMaxLds;
+  return c->R <= 16 && final_lds_base(c, n) + item_cache_total(c, n) <= kMaxLds && !(c->tile_cfg & DR_TILE_NO_ITEM_CACHE);
 }
 
 // `block`: threads per workgroup.
@@ -478,7 +478,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     for (int kind = 0; kind < Q_KINDS; ++kind) {
       int variant = 0, block = kWG;
       if (kind == Q_BOUND) {
-        variant = use_lds_weights(c, nd) ? 1 : 0;
+        variant = (use_lds_weights(c, nd) ? 1 : 0) | ((c->tile_cfg & DR_TILE_PAIRED_TILES) ? 2 : 0);
       } else if (kind == Q_DUAL) {
         variant = use_item_cache(c, nd) ? 1 : 0;
       }

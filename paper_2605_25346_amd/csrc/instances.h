@@ -3,7 +3,7 @@
 #pragma once
 
 enum {
-  DR_KIND_BOUND = 0,   // k_bound_init (variant 1: weights staged in LDS)
+  DR_KIND_BOUND = 0,   // k_bound_init (variant bit 0: weights staged in LDS; bit 1: row tiles in pairs)
   DR_KIND_FINAL = 1,   // k_final, plain spec rows
   DR_KIND_DUAL = 2,    // k_final, dual ascent (variant 1: per-item LDS copy of the relaxation)
   DR_KIND_REACH = 3,   // k_reach_dt

@@ -21,10 +21,17 @@ const void* DR_CAT(dr_instance_, DR_T, DR_NT)(int kind, int variant) {
   constexpr int NT = DR_NT;
   switch (kind) {
     case DR_KIND_BOUND:
-      // narrow networks run one subdomain per wavefront (with the weights in LDS when
-      // variant != 0); wider ones one subdomain per workgroup
+      // narrow networks run one subdomain per wavefront (variant bit 0: weights staged in
+      // LDS; bit 1: FP32 row tiles in pairs); wider ones one subdomain per workgroup
       if constexpr (NT <= 4) {
-        return variant ? (const void*)&dr::k_bound_init<T, NT, true, 64> : (const void*)&dr::k_bound_init<T, NT, false, 64>;
+        constexpr int NR2 = sizeof(T) == 4 ? 2 : 1;
+        switch (variant) {
+          case 0: return (const void*)&dr::k_bound_init<T, NT, false, 64, 1>;
+          case 1: return (const void*)&dr::k_bound_init<T, NT, true, 64, 1>;
+          case 2: return (const void*)&dr::k_bound_init<T, NT, false, 64, NR2>;
+          case 3: return (const void*)&dr::k_bound_init<T, NT, true, 64, NR2>;
+          default: return nullptr;
+        }
       } else {
         return variant ? nullptr : (const void*)&dr::k_bound_init<T, NT, false, 256>;
       }

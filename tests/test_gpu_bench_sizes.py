@@ -24,7 +24,7 @@ controller's contribution to the next state is not small.
 import numpy as np
 import pytest
 
-from oracle import crown, tm
+from oracle import crown, exact, tm
 from paper_2605_25346_amd.workloads import config_workload, make_workload
 from tests.gpu_helpers import near_tie, print_stats, rel_gap, require_gpu
 
@@ -207,6 +207,50 @@ def test_reach_where_the_controller_matters(width):
             gaps.append(g)
         print_stats(f"reach width {width} {precision} margins={margins}", gaps)
         ctx.close()
+
+
+def test_cfg2_full_size_rigorous_sound_against_samples():
+    """The headline launch (4096 subdomains, FP32 chains with rigorous margins, the
+    autotuned configuration): sampled subdomains' bounds contain the network's values at
+    4000 sampled points each (the true range, the soundness that matters), and the
+    oracle's bound computed from the GPU's own intermediate bounds lies above the GPU's
+    by at most the GPU's margin (plus the FP32 rounding of the relaxation).  Where the
+    GPU bound is tighter than the oracle's end-to-end bound (possible: CROWN with
+    adaptive slopes is not monotone in the intermediate bounds) the count is printed."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(2)
+    S = wl.batch.n_sub
+    net = wl.nets[0]
+    ctx = BoundContext(wl.nets, precision="f32", max_sub=S, max_splits=8, tile_cfg="auto")
+    lb, ub, st, _ = ctx.crown(DeviceBatch(wl.batch))
+    marg = ctx.dr_get_margins()
+    l, u = ctx.dr_get_bounds()
+    torch.cuda.synchronize()
+    lb, ub, st, marg = lb.cpu().numpy(), ub.cpu().numpy(), st.cpu().numpy(), marg.cpu().numpy()
+    l, u = l.cpu().numpy(), u.cpu().numpy()
+    H = sum(net.hidden)
+    tighter, checked = 0, 0
+    for s in np.random.default_rng(2).choice(S, 64, replace=False):
+        if st[s] & 9:
+            continue
+        xc, xr, sp = wl.batch.x_center[s], wl.batch.x_radius[s], wl.batch.splits_of(s)
+        smin, smax = exact.sampled_extrema(net, xc, xr, np.eye(3), sp, n=4000, seed=int(s))
+        if smin is not None:
+            assert np.all(lb[s] <= smin) and np.all(ub[s] >= smax), s
+        bounds = list(zip(_layers(net, l[s, :H]), _layers(net, u[s, :H])))
+        rep = crown.final_bounds(net, bounds, xc, xr, splits=sp)["rowlb"]
+        got = np.concatenate([lb[s], -ub[s]])
+        scale = np.maximum(1.0, np.abs(rep))
+        assert np.all(got <= rep + 1e-6 * scale), s
+        assert np.all(rep - got <= 1.01 * marg[s] + 1e-5 * scale), s
+        o = crown.crown(net, xc, xr, sp)
+        tighter += int(np.sum(got > np.concatenate([o["lb"], -o["ub"]]) + 1e-9 * scale))
+        checked += 1
+    print(f"[cfg2 full f32 rigorous] {checked} subdomains sound against samples; {tighter} of {6 * checked} "
+          f"results tighter than the oracle's end-to-end bound", flush=True)
+    assert checked >= 48
+    ctx.close()
 
 
 def test_cfg1_f64_without_margins_to_1e12():
