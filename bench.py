@@ -310,6 +310,58 @@ def tm_reach(torch, args, precision="f32", cfg=4):
     return res
 
 
+def joint_flops(widths, n_state, rows):
+    """Algorithmic FLOPs of CROWN through the unrolled loop for one box, from its rows
+    (H x 8: rows[t][k-1] CROWN rows of hidden layer k at step t, rows[t][L-1] the state
+    rows).  A row of layer k at step t runs the products with W_{k-1} .. W_1 of step t
+    (its first product, W_k's row, is a gather), then t steps back; a state row of
+    x_{t+1} runs t + 1 steps back, the first without the boundary products (lam is a
+    unit vector there: they are gathers).  One step back = lam (B W_L) (n_state x
+    n_{L-1}), lam A (n_state x n_0) and the network's chain W_{L-1} .. W_1."""
+    L = len(widths) - 1
+    boundary = 2 * n_state * widths[L - 1] + 2 * n_state * widths[0]
+    per_step = boundary + chain_flops_per_row(widths, L)
+    tot = 0
+    for t in range(rows.shape[0]):
+        for k in range(1, L):
+            tot += int(rows[t, k - 1]) * (chain_flops_per_row(widths, k) + t * per_step)
+        tot += int(rows[t, L - 1]) * ((t + 1) * per_step - boundary)
+    return tot
+
+
+def joint_reach(torch, args, precision="f32", n_boxes=128):
+    """CROWN through the closed loop unrolled over the horizon against the stepwise TM
+    reach on the same boxes (the paper's DT comparison: 128 initial sets, a dynamics
+    network of three 96-wide layers, horizon 10): time, tube volume V (width sum over
+    steps 1..H) and the achieved FLOP rate of the joint kernel."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(6, n_sub=n_boxes)
+    S, H = wl.batch.n_sub, wl.horizon
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, tile_cfg="auto")
+    db = DeviceBatch(wl.batch)
+    u = torch.as_tensor(wl.meta["u"], dtype=torch.float64, device="cuda")
+    bj = torch.zeros(S, H + 1, ctx.n_state, 2, dtype=torch.float64, device="cuda")
+    bs = torch.zeros_like(bj)
+    rows = torch.zeros(S, H, 8, dtype=torch.int32, device="cuda")
+    reps = max(2, args.steps // 4)
+    ms_j, _ = time_graph(torch, lambda: ctx.dr_reach_dt_joint(db, H, boxes=bj, u=u, rows=rows), reps, 1)
+    ms_s, _ = time_graph(torch, lambda: ctx.dr_reach_dt(db, H, boxes=bs, u=u), reps, 1)
+    torch.cuda.synchronize()
+    rows_h = rows.cpu().numpy()
+    w = wl.nets[0].widths
+    flops = sum(joint_flops(w, ctx.n_state, rows_h[s]) for s in range(S))
+    vol = lambda b: (b[:, 1:, :, 1] - b[:, 1:, :, 0]).sum(axis=(1, 2))
+    vj, vs = vol(bj.cpu().numpy()), vol(bs.cpu().numpy())
+    res = dict(S=S, horizon=H, ms_joint=ms_j, ms_stepwise=ms_s, time_ratio=ms_j / ms_s,
+               box_steps_per_s=S * H / (ms_j * 1e-3), tflops=flops / (ms_j * 1e-3) / 1e12, flops=flops,
+               V_joint_median=float(np.median(vj)), V_stepwise_median=float(np.median(vs)),
+               V_ratio_median=float(np.median(vj / vs)), V_ratio_min=float((vj / vs).min()),
+               V_ratio_max=float((vj / vs).max()))
+    ctx.close()
+    return res
+
+
 def mixed_batch(torch, args, precision="f32"):
     from paper_2605_25346_amd.api import BoundContext, DeviceBatch
     from paper_2605_25346_amd.workloads import config_workload
@@ -606,7 +658,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default="", help="comma-separated extra legs to run (for profiling one leg): "
-                    "f64,sweep,ascent,pgrad,reach,candidates,tightness,mixed")
+                    "f64,sweep,ascent,pgrad,reach,candidates,joint,tightness,mixed")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -689,6 +741,13 @@ def main():
             box_steps_per_s=cr["box_steps_per_s"], ms_per_call=cr["ms"],
             roofline=dict(bound="mfma", achieved=cr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                           frac=cr["tflops"] / PEAK_TFLOPS["f32"]))
+    if leg("joint"):
+        print("bench: joint CROWN through the unrolled loop", file=sys.stderr, flush=True)
+        jr = joint_reach(torch, args, "f32")
+        print(f"bench: joint reach {jr}", file=sys.stderr, flush=True)
+        extra["joint_crown_vs_stepwise_8+4-96x3-8_S128_H10"] = dict(
+            jr, roofline=dict(bound="mfma", achieved=jr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                              frac=jr["tflops"] / PEAK_TFLOPS["f32"], kernel="k_reach_joint"))
     if leg("tightness"):
         for cfg_i, key in ((3, "equal_tightness_abcrown_8-128x4-4_vs_crown_input_splitting"),
                            (5, "equal_tightness_mixed_S16384_vs_crown_input_splitting")):

@@ -258,6 +258,31 @@ dr_status dr_reach_dt(dr_ctx* ctx, const dr_batch* batch, int horizon, double* b
 dr_status dr_reach_dt_exo(dr_ctx* ctx, const dr_batch* batch, int horizon, const double* u, double* boxes,
                           uint32_t* status, hipStream_t stream);
 
+/* Reachability by CROWN through the closed loop unrolled over the horizon: the joint,
+ * non-truncated DT baseline the paper compares its stepwise engine with (Section
+ * "Reachability Tool Evaluations", DT panel of the figure benchmarking the tool), tighter
+ * than the stepwise Taylor models because no intermediate set is re-formed, and with a
+ * cost that grows with the square of the horizon.  The graph is v_t = [x_t; u_t],
+ * x_{t+1} = A v_t + B f(v_t) (u_t as in dr_reach_dt_exo, absent when n_state == n_0).
+ * Relaxation as in dr_bound_init (chord upper line, adaptive lower slope; lower and
+ * upper bounds are separate rows).  Per step t: every hidden layer takes interval bounds
+ * from its input node (layer 1: the state box of step t, exact at t = 0) and each neuron
+ * they leave unstable gets the rows +-e_j carried back through steps t-1..0 to the
+ * initial box; then the state box of x_{t+1} from the rows +-e_i on x_{t+1} carried back
+ * to x_0.  The relaxation of every step stays in LDS: a horizon beyond what fits for the
+ * network returns DR_ECAPACITY (the message gives the limit).  Needs a context with one
+ * closed-loop network, no spec, no splits.
+ *   u      device FP64 S x horizon x (n_0 - n_state) or NULL (no exogenous inputs)
+ *   boxes  device FP64 S x (horizon + 1) x n_state x 2 (step 0 is the input box)
+ *   rows   device int S x horizon x 8 or NULL: CROWN rows of hidden layer k at step t
+ *          (index k - 1) and the 2 n_state state rows (index L - 1), for FLOP accounting
+ *   status device S or NULL: DR_RES_NONFINITE when a bound is not finite.
+ * Rounding: the chain products carry the rigorous margins of dr_bound_init (each step
+ * boundary adds the error of lam B W_L and lam A and of the seeds) unless margins are
+ * off.  Asynchronous on `stream`. */
+dr_status dr_reach_dt_joint(dr_ctx* ctx, const dr_batch* batch, int horizon, const double* u, double* boxes,
+                            int* rows, uint32_t* status, hipStream_t stream);
+
 /* Diagnostics of the last dr_bound_init / dr_propagate_backward /
  * dr_optimize_duals / dr_reach_dt on this context (device outputs):
  *   dr_get_bounds  l, u: S x H_max FP64 pre-activation bounds of hidden neurons;

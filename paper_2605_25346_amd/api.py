@@ -283,6 +283,26 @@ class BoundContext:
                                                  _ptr(status), _stream()))
         return boxes, status[:S]
 
+    def dr_reach_dt_joint(self, batch: DeviceBatch, horizon: int, boxes=None, u=None, rows=None):
+        """CROWN through the closed loop unrolled over the horizon; returns (boxes,
+        status, rows) with rows S x horizon x 8 (CROWN rows per hidden layer and step)."""
+        self.batch = batch
+        self.generation += 1
+        S = batch.n_sub
+        if boxes is None:
+            boxes = torch.empty(S, horizon + 1, max(self.n_state, 1), 2, dtype=torch.float64, device=self.device)
+        if rows is None:
+            rows = torch.zeros(max(S, 1), max(horizon, 1), 8, dtype=torch.int32, device=self.device)
+        status = torch.zeros(max(S, 1), dtype=torch.int32, device=self.device)
+        if u is not None:
+            u = torch.as_tensor(u, dtype=torch.float64, device=self.device).contiguous()
+            self._u = u
+        b = batch.struct()
+        self._batch_struct = b
+        self._check(self.lib.dr_reach_dt_joint(self.ctx, ctypes.byref(b), int(horizon), _ptr(u) if u is not None else None,
+                                               _ptr(boxes), _ptr(rows), _ptr(status), _stream()))
+        return boxes, status[:S], rows[:S]
+
     def dr_get_bounds(self):
         S = self.batch.n_sub
         l = torch.empty(S, max(self.H_max, 1), dtype=torch.float64, device=self.device)

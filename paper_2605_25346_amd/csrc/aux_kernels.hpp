@@ -286,6 +286,24 @@ __global__ void k_seeds(const T* __restrict__ WL, const T* __restrict__ bL, int 
   }
 }
 
+// Natural (row-major, padded) copies of the step-boundary matrices of the unrolled
+// closed loop, before their forward swizzle: Mn (16 x npLm1) = the seeds of the rows
+// +e_r (B_r W_L in the chain type) for r < n_state, zero rows beyond; An (16 x 16) = A
+// rounded to the chain type, rows r < n_state, columns m < n_0.
+template <typename T>
+__global__ void k_joint_mats(const T* __restrict__ seedT, int npLm1, const double* __restrict__ A, int ns, int n0,
+                             T* Mn, T* An) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < 16 * npLm1) {
+    const int r = e / npLm1;
+    Mn[e] = r < ns ? seedT[e] : (T)0;
+  }
+  if (e < 256) {
+    const int r = e >> 4, m = e & 15;
+    An[e] = (r < ns && m < n0) ? (T)A[(size_t)r * n0 + m] : (T)0;
+  }
+}
+
 // Counting sort of the batch by network id (one workgroup).
 __global__ void k_order(int S, const int* __restrict__ net_id, int n_nets, int* order, int* net_cnt,
                         int* net_off, uint32_t* st) {

@@ -72,6 +72,9 @@ struct dr_ctx {
   const void* pg_fn = nullptr;  // parameter-gradient instance of k_final (single network)
   int pg_grid = 0;
   void* scratch = nullptr;      // device address of this device's static scratch
+  void* jMn[kMaxNets] = {};     // natural copies of the unrolled loop's M and A (refilled by dr_set_weights)
+  void* jAn[kMaxNets] = {};
+  const void* joint_fn = nullptr;   // k_reach_joint instance (closed loop without a spec, one network)
   std::string err;
 };
 
@@ -312,6 +315,29 @@ dr_status setup_weights(dr_ctx* c, const dr_network& nw, dr::NetDev& nd, int net
                      (const T*)nd.bn[L - 1], nd.n[L], npLm1, Cdev, nd.q, n_target, nd.A, c->B_dev[net_i], nd.n[0], nd.np[L],
                      seedW, seedB, skip, seedA, seedWe, seedBe, skipE, seedT, seedM);
   if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "seed kernel");
+  // closed loop without a spec: the step-boundary matrices of the unrolled loop (M = B W_L
+  // from the seeds of the rows +e_r, and A), forward-swizzled like the weights
+  if (nd.A && !c->has_spec) {
+    T *Mn, *An, *jM, *jA;
+    if (alloc) {
+      if ((e = ctx_alloc(c, &Mn, sizeof(T) * 16 * npLm1)) != hipSuccess ||
+          (e = ctx_alloc(c, &An, sizeof(T) * 256)) != hipSuccess ||
+          (e = ctx_alloc(c, &jM, sizeof(T) * 16 * npLm1)) != hipSuccess ||
+          (e = ctx_alloc(c, &jA, sizeof(T) * 256)) != hipSuccess)
+        return hip_fail(c, e, "hipMalloc");
+      c->jMn[net_i] = Mn; c->jAn[net_i] = An;
+      nd.jM = jM; nd.jA = jA;
+    } else {
+      Mn = (T*)c->jMn[net_i]; An = (T*)c->jAn[net_i]; jM = (T*)nd.jM; jA = (T*)nd.jA;
+    }
+    const int tm = std::max(16 * npLm1, 256);
+    hipLaunchKernelGGL((dr::k_joint_mats<T>), dim3((tm + 255) / 256), dim3(256), 0, stream, (const T*)seedT, npLm1,
+                       nd.A, nd.n_state, nd.n[0], Mn, An);
+    hipLaunchKernelGGL((dr::k_swizzle<T>), dim3((16 * npLm1 + 255) / 256), dim3(256), 0, stream, (const T*)Mn, 16,
+                       npLm1, 0, jM);
+    hipLaunchKernelGGL((dr::k_swizzle<T>), dim3(1), dim3(256), 0, stream, (const T*)An, 16, 16, 0, jA);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(c, e, "step-boundary matrices");
+  }
   return DR_OK;
 }
 
@@ -511,6 +537,14 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     if (lds > 0 && (e = hipFuncSetAttribute(c->pg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
       return bail(hip_fail(c, e, "hipFuncSetAttribute"));
     c->pg_grid = std::min(persistent_grid(c, c->pg_fn, lds, Q_DUAL), c->grid[Q_DUAL][0]);
+  }
+  if (n_nets == 1 && c->closed && !c->has_spec) {
+    // CROWN through the unrolled loop: its LDS grows with the horizon, so the launch shape
+    // is fixed per call; the kernel may use all of a CU's LDS
+    c->joint_fn = kernel_for(c, DR_KIND_JOINT, c->hnet[0].NT, 0);
+    if (c->joint_fn &&
+        (e = hipFuncSetAttribute(c->joint_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
+      return bail(hip_fail(c, e, "hipFuncSetAttribute"));
   }
   if (n_nets > 1) {
     if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
@@ -818,7 +852,67 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
   return DR_OK;
 }
 
+// LDS of k_reach_joint over `horizon` steps: the chain stages and the per-box state
+// (the relaxation of every step is kept on chip).
+static size_t joint_lds(const dr_ctx* c, const dr::NetDev& n, int horizon) {
+  const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
+  const size_t st = (size_t)dr::kWavesPerWG * dr::stage_bytes_rt(tsz, n.NT, false);
+  return st + (c->prec == DR_PREC_F64 ? dr::JointLds<double>::bytes(horizon, n.Hp, n.NT)
+                                      : dr::JointLds<float>::bytes(horizon, n.Hp, n.NT));
+}
+
+static dr_status reach_joint(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, int* rows,
+                             uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->closed) return fail(c, DR_EINVAL, "reach_dt_joint needs a closed-loop network");
+  if (c->has_spec) return fail(c, DR_EINVAL, "reach_dt_joint bounds every state: create the context without a spec");
+  if (c->n_nets != 1) return fail(c, DR_EINVAL, "reach_dt_joint takes a context with one network");
+  const bool exo = c->q < c->n0;
+  if (exo && !u && horizon > 0 && b && b->n_sub > 0)
+    return fail(c, DR_EINVAL, "the network has exogenous inputs: u (the input sequences) is required");
+  if (!exo && u) return fail(c, DR_EINVAL, "u given but the network has no exogenous inputs");
+  if (horizon < 0 || horizon > 10000) return fail(c, DR_EINVAL, "horizon must be in 0..10000");
+  dr_status st = check_batch(c, b);
+  if (st != DR_OK) return st;
+  if (b->split_ptr) return fail(c, DR_EINVAL, "reach_dt_joint takes no split constraints");
+  if (!boxes) return fail(c, DR_EINVAL, "boxes is NULL");
+  if (!c->joint_fn) return fail(c, DR_ESHAPE, "no kernel instance for this width");
+  const dr::NetDev& nd = c->hnet[0];
+  if (nd.n[0] > 16 || nd.n_state > 16) return fail(c, DR_ESHAPE, "reach_dt_joint needs n_0 <= 16");
+  const size_t lds = joint_lds(c, nd, horizon);
+  if (lds > kMaxLds) {
+    int hmax = 0;
+    while (joint_lds(c, nd, hmax + 1) <= kMaxLds) ++hmax;
+    return fail(c, DR_ECAPACITY, "horizon too long for the on-chip relaxation store of this network: at most " +
+                                     std::to_string(hmax) + " steps");
+  }
+  c->batch.n_sub = b->n_sub;
+  c->batch.net_id = b->net_id;
+  c->batch.xc = b->x_center;
+  c->batch.xr = b->x_radius;
+  c->batch.sptr = nullptr;
+  c->batch.spk = nullptr;
+  c->have_batch = false;  // bound_init state is not valid for this batch
+  c->fused_ready = false;
+  c->sc.n_sub = b->n_sub;
+  if (b->n_sub == 0) return DR_OK;
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, c->joint_fn, kWG, lds) != hipSuccess || nb < 1) nb = 1;
+  const int grid = std::min(nb * c->cus, b->n_sub);
+  dr::JointArgs ja{};
+  ja.batch = c->batch; ja.sc = c->sc; ja.sc.st_out = nullptr;
+  ja.horizon = horizon; ja.boxes = boxes; ja.rows = rows; ja.status = status; ja.u = u;
+  int net_index = 0;
+  void* args[] = {&c->dnet, &net_index, &ja};
+  return launch(c, c->joint_fn, grid, lds, args, stream);
+}
+
 extern "C" {
+
+dr_status dr_reach_dt_joint(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, int* rows,
+                            uint32_t* status, hipStream_t stream) {
+  return reach_joint(c, b, horizon, u, boxes, rows, status, stream);
+}
 
 dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, uint32_t* status, hipStream_t stream) {
   return reach(c, b, horizon, nullptr, boxes, status, stream);

@@ -4,6 +4,7 @@
 // kernels through the function below (kernel handles are valid across translation
 // units of one shared library).
 #include "bound_kernels.hpp"
+#include "joint_kernels.hpp"
 #include "instances.h"
 
 #ifndef DR_T
@@ -41,6 +42,7 @@ const void* DR_CAT(dr_instance_, DR_T, DR_NT)(int kind, int variant) {
     case DR_KIND_REACH: return (const void*)&dr::k_reach_dt<T, NT>;
     case DR_KIND_PGRAD:
       return variant ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
+    case DR_KIND_JOINT: return variant ? nullptr : (const void*)&dr::k_reach_joint<T, NT>;
     default: return nullptr;
   }
 }

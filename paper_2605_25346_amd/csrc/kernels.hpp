@@ -101,6 +101,11 @@ struct NetDev {
   const void* seedT;
   const void* seedM;
   const double* A;           // n_state x n_0 (closed loop) or null
+  // closed loop: forward-swizzled M = B W_L (rows: the n_state state indices padded to
+  // 16, columns: h_{L-1}) and A (16 x 16, columns: the network input v), in the chain
+  // type, for carrying rows on x' back through a step (unrolled-loop CROWN); else null
+  const void* jM;
+  const void* jA;
   int n_state;
   int q;                     // spec directions
   int R;                     // 2q rows
@@ -499,5 +504,62 @@ struct ReachArgs {
   const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
 };
 
+
+// Arguments and per-box LDS state of k_reach_joint (CROWN through the unrolled loop).
+struct JointArgs {
+  BatchDev batch;
+  Scratch sc;
+  int horizon;
+  double* boxes;            // S x (horizon + 1) x n_state x 2
+  int* rows;                // S x horizon x 8 (nullable): CROWN rows per hidden layer and state rows
+  uint32_t* status;
+  const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
+};
+
+// Per-box LDS state of k_reach_joint.
+template <typename T>
+struct JointLds {
+  V4<T>* rel;     // H x Hp relaxation (lo, up, t, mu) of every step, permuted order
+  double* l;      // Hp natural: bounds of the current step
+  double* u;
+  double* ibl;    // 16 NT: IBP bounds of the current layer
+  double* ibu;
+  double* v;      // 16 NT: |W_k| H_{k-1} of the current layer (margin coefficients)
+  double* hc;     // 16 NT: centre/radius of relu of the previous layer
+  double* hr;
+  double* box;    // 6 x 16: initial centre, radius; current state box lo, hi; v box centre, radius
+  double* uv;     // H x 16: exogenous inputs at their input positions (zero elsewhere)
+  double* vab;    // H x 16: bound on |v_s|
+  T* mux;         // H x 16: margin coefficient of a row multiplier on x_{s+1} at the step boundary
+  T* bias;        // Hp: hidden biases in the chain type
+  int* U;         // 16 NT
+  int* misc;      // 8: [1] status flags, [2..] wave counts of the compaction
+  __host__ __device__ static size_t r16(size_t n) { return (n + 15) & ~(size_t)15; }
+  __host__ __device__ static size_t bytes(int H, int Hp, int NT) {
+    const size_t n16 = (size_t)16 * NT;
+    return r16((size_t)H * Hp * sizeof(V4<T>)) + 2 * r16((size_t)Hp * sizeof(double)) +
+           5 * r16(n16 * sizeof(double)) + r16(96 * sizeof(double)) + 2 * r16((size_t)H * 16 * sizeof(double)) +
+           r16((size_t)H * 16 * sizeof(T)) + r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) +
+           r16(8 * sizeof(int));
+  }
+  __device__ void carve(char* base, int H, int Hp, int NT) {
+    auto take = [&](size_t n) { char* p = base; base += r16(n); return p; };
+    rel = (V4<T>*)take((size_t)H * Hp * sizeof(V4<T>));
+    l = (double*)take((size_t)Hp * sizeof(double));
+    u = (double*)take((size_t)Hp * sizeof(double));
+    ibl = (double*)take((size_t)16 * NT * sizeof(double));
+    ibu = (double*)take((size_t)16 * NT * sizeof(double));
+    v = (double*)take((size_t)16 * NT * sizeof(double));
+    hc = (double*)take((size_t)16 * NT * sizeof(double));
+    hr = (double*)take((size_t)16 * NT * sizeof(double));
+    box = (double*)take(96 * sizeof(double));
+    uv = (double*)take((size_t)H * 16 * sizeof(double));
+    vab = (double*)take((size_t)H * 16 * sizeof(double));
+    mux = (T*)take((size_t)H * 16 * sizeof(T));
+    bias = (T*)take((size_t)Hp * sizeof(T));
+    U = (int*)take((size_t)16 * NT * sizeof(int));
+    misc = (int*)take(8 * sizeof(int));
+  }
+};
 
 }  // namespace dr

@@ -32,3 +32,16 @@ def test_needed_row_count_uses_the_chain_rows():
     rows[1, 2] = 4
     got = bench.bound_init_flops([Net()], np.zeros(2, np.int32), rows)
     assert got == 10 * (2 * 64 * 6) + 20 * (2 * 64 * 6 + 2 * 64 * 64) + 4 * (2 * 64 * 6 + 2 * 64 * 64)
+
+
+def test_joint_flops_hand_count():
+    """widths 3-4-5-2 with a 2-dimensional state: a chain through one step's network is
+    2*4*3 + 2*5*4 = 64 FLOPs, the step boundary 2*2*5 + 2*2*3 = 32.  Rows (H = 2):
+    t=0: 6 rows at layer 2 (24 each), 4 state rows (one step back without the boundary:
+    64); t=1: 2 rows at layer 1 (one step back: 96), 6 at layer 2 (24 + 96), 4 state
+    rows (two steps back less one boundary: 160) -> 144 + 256 + 192 + 720 + 640."""
+    import numpy as np
+    rows = np.zeros((2, 8), np.int64)
+    rows[0, :3] = [0, 6, 4]
+    rows[1, :3] = [2, 6, 4]
+    assert bench.joint_flops([3, 4, 5, 2], 2, rows) == 1952
