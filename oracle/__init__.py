@@ -25,5 +25,10 @@ fallback for it.  Parity status per function:
   model, both offsets and the interval product; a network whose second layer is
   exactly zero over the TM; second-layer bounds = max(interval bound, LP over the
   parallel relaxation)).
+* joint.reach_joint, back_through_step, to_initial: pinned (two systems worked by
+  hand in rational arithmetic, including a later step's intermediate row tighter
+  than interval propagation from the state box; B = 0 matrix powers with and
+  without exogenous inputs; an all-active affine loop; point initial sets on the
+  simulated trajectory; dense sampled rollouts; horizon 1 = closed-loop crown).
 """
-from . import crown, exact, tm  # noqa: F401
+from . import crown, exact, joint, tm  # noqa: F401
