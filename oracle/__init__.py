@@ -30,5 +30,10 @@ fallback for it.  Parity status per function:
   than interval propagation from the state box; B = 0 matrix powers with and
   without exogenous inputs; an all-active affine loop; point initial sets on the
   simulated trajectory; dense sampled rollouts; horizon 1 = closed-loop crown).
+* tm_grad.reach_volume, volume_gradient: pinned (forward = tm.reach_dt to 1e-13;
+  gradient = central finite differences of the independent numpy tm.reach_dt with
+  respect to actions, box centre and radius, A, B, weights and biases; closed forms of
+  dV/dr for B = 0 and for an all-active affine loop, and zero action/centre gradients
+  there).
 """
-from . import crown, exact, joint, tm  # noqa: F401
+from . import crown, exact, joint, tm, tm_grad  # noqa: F401
