@@ -283,6 +283,39 @@ dr_status dr_reach_dt_exo(dr_ctx* ctx, const dr_batch* batch, int horizon, const
 dr_status dr_reach_dt_joint(dr_ctx* ctx, const dr_batch* batch, int horizon, const double* u, double* boxes,
                             int* rows, uint32_t* status, hipStream_t stream);
 
+/* Gradient of the reach-tube volume through the stepwise reach: the training signal of
+ * the paper's reachability-aware loss (Section "Certified training of neural dynamics and
+ * controllers", Algorithm "Training of DT Neural Dynamics": L_reach = mean log(1 + V)
+ * with V the sum over steps t = 1..H and states of the widths of the boxes X_t) and the
+ * action gradient of its top-candidate refinement (Section "Reachability-aware MPC").
+ * Runs the reach of dr_reach_dt / dr_reach_dt_exo (same arguments and boxes output)
+ * recording each box's Taylor models and bounds into the workspace, then the reverse
+ * pass through every step: the output rows and the CROWN rows of the intermediate bounds
+ * in reverse on the matrix cores, the chord relaxation (s = u/(u-l), t = -s l), the
+ * intersections with the interval bounds and the interval bounds themselves, layer 1 over
+ * the Taylor model, and the Taylor-model composition.  With J = sum_s g_V[s] V_s:
+ *   g_V       device FP64 S: dJ/dV_s (for mean log(1 + V): 1 / (S (1 + V_s)))
+ *   boxes     device FP64 S x (horizon + 1) x n_state x 2 (the forward result)
+ *   du        device FP64 S x horizon x (n_0 - n_state) or NULL: dJ/du (exogenous inputs)
+ *   dxc, dxr  device FP64 S x n_state or NULL: dJ/d(box centre), dJ/d(box radius)
+ *   dA, dB    device FP64 n_state x n_0, n_state x n_L or NULL: dJ/dA, dJ/dB (overwritten)
+ *   dW, db    host arrays of L device pointers or NULL (and NULL entries): dJ/dW_k (n_k x
+ *             n_{k-1} row-major) and dJ/db_k (n_k), FP64, overwritten; accumulated per
+ *             workgroup in the chain type with atomic additions and summed in a fixed order
+ *   workspace device memory of at least dr_reach_grad_workspace(ctx, S, horizon) bytes
+ *             (caller-owned: the forward record and the reverse kernel's chain records).
+ * Rounding margins are constants of the gradient (it is the gradient of the bound in exact
+ * arithmetic, as autodiff of the engine gives it); discrete choices (stability, the side of
+ * an intersection, signs, a tie counts for the interval bound) are those of the forward
+ * pass.  Needs a context with one closed-loop network and no spec.  dA and dB sum over the
+ * batch with atomic additions (the order of the additions is not fixed).  Asynchronous on
+ * `stream`; allocates nothing. */
+size_t dr_reach_grad_workspace(const dr_ctx* ctx, int n_sub, int horizon);
+dr_status dr_reach_dt_grad(dr_ctx* ctx, const dr_batch* batch, int horizon, const double* u, const double* g_V,
+                           double* boxes, double* du, double* dxc, double* dxr, double* dA, double* dB,
+                           double* const* dW, double* const* db, void* workspace, size_t workspace_bytes,
+                           uint32_t* status, hipStream_t stream);
+
 /* Diagnostics of the last dr_bound_init / dr_propagate_backward /
  * dr_optimize_duals / dr_reach_dt on this context (device outputs):
  *   dr_get_bounds  l, u: S x H_max FP64 pre-activation bounds of hidden neurons;

@@ -303,6 +303,51 @@ class BoundContext:
                                                _ptr(boxes), _ptr(rows), _ptr(status), _stream()))
         return boxes, status[:S], rows[:S]
 
+    def dr_reach_dt_grad(self, batch: DeviceBatch, horizon: int, g_V, u=None, boxes=None, workspace=None,
+                         want=("du", "dxc", "dxr", "dA", "dB", "dW", "db")):
+        """Reach (boxes) and the gradient of J = sum_s g_V[s] V_s: returns (boxes, status,
+        grads) with grads a dict of the requested FP64 device tensors among du, dxc, dxr,
+        dA, dB, and the lists dW, db (one tensor per layer)."""
+        self.batch = batch
+        self.generation += 1
+        S = batch.n_sub
+        ns = max(self.n_state, 1)
+        dev = self.device
+        f64 = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device=dev)
+        if boxes is None:
+            boxes = f64(S, horizon + 1, ns, 2)
+        g_V = torch.as_tensor(g_V, dtype=torch.float64, device=dev).contiguous()
+        if g_V.shape != (S,):
+            raise ValueError(f"g_V must have shape ({S},)")
+        if u is not None:
+            u = torch.as_tensor(u, dtype=torch.float64, device=dev).contiguous()
+            self._u = u
+        nx = self.n0 - self.n_state
+        shapes = dict(du=(max(S, 1), max(horizon, 1), max(nx, 1)), dxc=(max(S, 1), ns), dxr=(max(S, 1), ns),
+                      dA=(ns, self.n0), dB=(ns, self.widths[-1]))
+        grads = {k: f64(*shapes[k]) for k in want if k in shapes and not (k == "du" and nx == 0)}
+        L = len(self.widths) - 1
+        dWp = dbp = None
+        if "dW" in want:
+            grads["dW"] = [f64(self.widths[k + 1], self.widths[k]) for k in range(L)]
+            dWp = (ctypes.c_void_p * L)(*[t.data_ptr() for t in grads["dW"]])
+        if "db" in want:
+            grads["db"] = [f64(self.widths[k + 1]) for k in range(L)]
+            dbp = (ctypes.c_void_p * L)(*[t.data_ptr() for t in grads["db"]])
+        self._wptrs = (dWp, dbp)
+        need = int(self.lib.dr_reach_grad_workspace(self.ctx, S, int(horizon)))
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        self._ws = workspace
+        status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+        b = batch.struct()
+        self._batch_struct = b
+        self._check(self.lib.dr_reach_dt_grad(
+            self.ctx, ctypes.byref(b), int(horizon), _ptr(u), _ptr(g_V), _ptr(boxes), _ptr(grads.get("du")),
+            _ptr(grads.get("dxc")), _ptr(grads.get("dxr")), _ptr(grads.get("dA")), _ptr(grads.get("dB")),
+            dWp, dbp, _ptr(workspace), ctypes.c_size_t(workspace.numel()), _ptr(status), _stream()))
+        return boxes, status[:S], grads
+
     def dr_get_bounds(self):
         S = self.batch.n_sub
         l = torch.empty(S, max(self.H_max, 1), dtype=torch.float64, device=self.device)

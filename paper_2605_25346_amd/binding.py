@@ -25,7 +25,8 @@ DR_TILE_GLOBAL_WEIGHTS, DR_TILE_PAIRED_TILES, DR_TILE_NO_ITEM_CACHE = 1 << 16, 1
 EXPORTED = [
     "dr_create", "dr_bound_init", "dr_propagate_backward", "dr_concretize", "dr_optimize_duals",
     "dr_param_grad_workspace", "dr_param_grad", "dr_param_grad_static", "dr_set_weights",
-    "dr_reach_dt", "dr_reach_dt_exo", "dr_reach_dt_joint", "dr_get_bounds", "dr_get_rows", "dr_get_margins", "dr_hidden_max", "dr_spec_rows",
+    "dr_reach_dt", "dr_reach_dt_exo", "dr_reach_dt_joint", "dr_reach_grad_workspace", "dr_reach_dt_grad",
+    "dr_get_bounds", "dr_get_rows", "dr_get_margins", "dr_hidden_max", "dr_spec_rows",
     "dr_last_error", "dr_destroy",
 ]
 
@@ -97,6 +98,8 @@ def load():
         "dr_reach_dt": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P]),
         "dr_reach_dt_exo": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P]),
         "dr_reach_dt_joint": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P, P]),
+        "dr_reach_grad_workspace": (ctypes.c_size_t, [P, I, I]),
+        "dr_reach_dt_grad": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]),
         "dr_get_bounds": (I, [P, P, P, P]),
         "dr_get_rows": (I, [P, P, P]),
         "dr_get_margins": (I, [P, P, P]),

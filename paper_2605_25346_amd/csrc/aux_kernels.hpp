@@ -304,6 +304,42 @@ __global__ void k_joint_mats(const T* __restrict__ seedT, int npLm1, const doubl
   }
 }
 
+// Zero n doubles (a kernel, not a memset node, so that graph replays of a call that
+// accumulates into a caller's buffer stay correct).
+__global__ void k_zero(double* p, size_t n) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) p[e] = 0.0;
+}
+
+// Sum of the per-workgroup weight-gradient regions of the reach gradient (chain type)
+// in a fixed order (FP64, deterministic) into the natural-layout outputs.
+struct ReachWreduceArgs {
+  const void* wreg;
+  size_t stride;            // chain-type elements per workgroup region
+  size_t woff[kMaxL];
+  int n_regions;
+  double* dW[kMaxL];        // n_k x n_{k-1} FP64, or null
+  double* db[kMaxL];        // n_k FP64, or null
+};
+template <typename T>
+__global__ void k_reach_wreduce(const NetDev* __restrict__ nets, int net_index, ReachWreduceArgs ra) {
+  const NetDev& net = nets[net_index];
+  const int k = blockIdx.y + 1;
+  if (k > net.L) return;
+  const int nk = net.n[k], nj = net.n[k - 1], ld = net.np[k - 1] + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nk * (nj + 1)) return;
+  const int i = e / (nj + 1), jj = e % (nj + 1);
+  const int j = jj < nj ? jj : ld - 1;   // the last column holds the bias
+  const T* reg = (const T*)ra.wreg + ra.woff[k - 1] + (size_t)i * ld + j;
+  double sum = 0.0;
+  for (int w = 0; w < ra.n_regions; ++w) sum += (double)reg[(size_t)w * ra.stride];
+  if (jj < nj) {
+    if (ra.dW[k - 1]) ra.dW[k - 1][(size_t)i * nj + jj] = sum;
+  } else if (ra.db[k - 1]) {
+    ra.db[k - 1][i] = sum;
+  }
+}
+
 // Counting sort of the batch by network id (one workgroup).
 __global__ void k_order(int S, const int* __restrict__ net_id, int n_nets, int* order, int* net_cnt,
                         int* net_off, uint32_t* st) {

@@ -1254,6 +1254,7 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
     if (item >= cnt) break;
     const int s = subdomain_of(sc, net_index, item);
     double* bx = ra.boxes + (size_t)s * (H + 1) * ns * 2;
+    double* tb = ra.tape ? ra.tape + (size_t)s * reach_tape_doubles(H, Hp) : nullptr;
     // TM normalisation of the state box: c = centre, P = diag(radius), I = [0, 0]; the
     // exogenous inputs (network inputs ns..n0-1) enter each step as points
     if (tid < 16) {
@@ -1280,6 +1281,10 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
         S.xc[tid] = 0.0; S.xr[tid] = 0.0;
       }
       lds_barrier();
+      if (tb) {
+        double* tt = tb + reach_tape_tm(step);
+        for (int e = tid; e < kTmDoubles; e += kWG) tt[e] = tm[e];
+      }
       // ---- layer 1 on the TM input: exact range of W_1 (c + P z + r) + b_1
       {
         const int n1 = net.n[1];
@@ -1309,6 +1314,10 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
           }
           S.l[j] = lo; S.u[j] = hi;
           S.rel[p] = build_relax<T>(lo, hi, v, bj, false, n1, true, sc.margin_on);
+          if (tb) {
+            double* tl = tb + reach_tape_bounds(step, H, Hp);
+            tl[j] = lo; tl[Hp + j] = hi; tl[2 * Hp + j] = lo; tl[3 * Hp + j] = hi;
+          }
         }
       }
       lds_barrier();
@@ -1384,6 +1393,10 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
             if (!(fabs(lo) < INFINITY) || !(fabs(hi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
           }
           S.rel[p] = build_relax<T>(lo, hi, S.v[j], bj, false, nk, true, sc.margin_on);
+          if (tb) {
+            double* tl = tb + reach_tape_bounds(step, H, Hp) + base;
+            tl[j] = lo; tl[Hp + j] = hi; tl[2 * Hp + j] = S.ibl[j]; tl[3 * Hp + j] = S.ibu[j];
+          }
         }
         if (tid == 0) sc.rows[(size_t)s * 8 + (k - 1)] += nU;
         lds_barrier();
@@ -1460,6 +1473,10 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
       }
       for (int e = tid; e < 256; e += kWG) Pm[e] = ((e >> 4) < ns) ? nP[e] : 0.0;
       lds_barrier();
+    }
+    if (tb) {
+      double* tt = tb + reach_tape_tm(H);
+      for (int e = tid; e < kTmDoubles; e += kWG) tt[e] = tm[e];
     }
     if (tid == 0) {
       sc.st[s] = (uint32_t)S.misc[1];

@@ -75,6 +75,9 @@ struct dr_ctx {
   void* jMn[kMaxNets] = {};     // natural copies of the unrolled loop's M and A (refilled by dr_set_weights)
   void* jAn[kMaxNets] = {};
   const void* joint_fn = nullptr;   // k_reach_joint instance (closed loop without a spec, one network)
+  const void* rg_fn = nullptr;      // k_reach_grad instance (same contexts), its LDS and full grid
+  size_t rg_lds = 0;
+  int rg_grid = 0;
   std::string err;
 };
 
@@ -545,6 +548,18 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     if (c->joint_fn &&
         (e = hipFuncSetAttribute(c->joint_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
       return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+    const dr::NetDev& nd = c->hnet[0];
+    c->rg_fn = kernel_for(c, DR_KIND_RGRAD, nd.NT, 0);
+    const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
+    c->rg_lds = (size_t)dr::kWavesPerWG * dr::stage_bytes_rt(tsz, nd.NT, false) +
+                (c->prec == DR_PREC_F64 ? dr::GradLds<double>::bytes(nd.Hp, nd.NT) : dr::GradLds<float>::bytes(nd.Hp, nd.NT));
+    if (c->rg_fn && c->rg_lds <= kMaxLds) {
+      if ((e = hipFuncSetAttribute(c->rg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->rg_lds)) != hipSuccess)
+        return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+      c->rg_grid = persistent_grid(c, c->rg_fn, c->rg_lds, Q_REACH);
+    } else {
+      c->rg_fn = nullptr;
+    }
   }
   if (n_nets > 1) {
     if ((e = hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming)) != hipSuccess)
@@ -810,7 +825,7 @@ dr_status dr_param_grad_static(dr_ctx* c, float* alpha, float* beta, int init_du
 }  // extern "C"
 
 static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, uint32_t* status,
-                       hipStream_t stream) {
+                       hipStream_t stream, double* tape = nullptr) {
   if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
   if (!c->closed) return fail(c, DR_EINVAL, "reach_dt needs a closed-loop network");
   if (c->has_spec) return fail(c, DR_EINVAL, "reach_dt bounds every state: create the context without a spec");
@@ -843,7 +858,7 @@ static dr_status reach(dr_ctx* c, const dr_batch* b, int horizon, const double* 
   for (int i = 0; i < c->n_nets; ++i) {
     dr::ReachArgs ra{};
     ra.batch = c->batch; ra.sc = c->sc; ra.sc.st_out = nullptr; ra.queue = queue_of(c, Q_REACH, i);
-    ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u;
+    ra.horizon = horizon; ra.boxes = boxes; ra.status = status; ra.u = u; ra.tape = tape;
     int net_index = i;
     void* args[] = {&c->dnet, &net_index, &ra};
     if ((st = launch_kind(c, Q_REACH, i, args, ra.queue, net_stream(c, stream, i))) != DR_OK) return st;
@@ -907,7 +922,118 @@ static dr_status reach_joint(dr_ctx* c, const dr_batch* b, int horizon, const do
   return launch(c, c->joint_fn, grid, lds, args, stream);
 }
 
+// Workspace of dr_reach_dt_grad: the forward record of every box, the per-wave chain
+// records and cotangent buffers of the reverse kernel, then one weight-gradient region
+// per workgroup.
+struct ReachGradLayout {
+  size_t gtape_off = 0, dgb_off = 0, wreg_off = 0, total = 0, wstride = 0;
+  size_t woff[dr::kMaxL] = {};
+  int grid = 0;
+};
+static ReachGradLayout reach_grad_layout(const dr_ctx* c, int S, int horizon) {
+  ReachGradLayout g;
+  const dr::NetDev& nd = c->hnet[0];
+  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  g.grid = std::max(1, std::min(c->rg_grid, std::max(S, 1)));
+  const size_t waves = (size_t)g.grid * dr::kWavesPerWG;
+  g.gtape_off = al((size_t)std::max(S, 1) * dr::reach_tape_doubles(horizon, nd.Hp) * sizeof(double));
+  g.dgb_off = g.gtape_off + waves * (nd.L - 1) * nd.NT * 256 * tsz;   // contiguous with the chain records
+  g.wreg_off = al(g.dgb_off + waves * nd.NT * 256 * tsz);
+  size_t w = 0;
+  for (int k = 1; k <= nd.L; ++k) {
+    g.woff[k - 1] = w;
+    w += (size_t)nd.np[k] * (nd.np[k - 1] + 1);
+  }
+  g.wstride = (w + 63) & ~(size_t)63;
+  g.total = g.wreg_off + (size_t)g.grid * g.wstride * tsz;
+  return g;
+}
+
 extern "C" {
+
+size_t dr_reach_grad_workspace(const dr_ctx* c, int n_sub, int horizon) {
+  if (!c || !c->rg_fn || n_sub < 0 || horizon < 0) return 0;
+  return reach_grad_layout(c, n_sub, horizon).total;
+}
+
+dr_status dr_reach_dt_grad(dr_ctx* c, const dr_batch* b, int horizon, const double* u, const double* g_V,
+                           double* boxes, double* du, double* dxc, double* dxr, double* dA, double* dB,
+                           double* const* dW, double* const* db, void* workspace, size_t workspace_bytes,
+                           uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  if (!c->closed || c->has_spec || c->n_nets != 1)
+    return fail(c, DR_EINVAL, "reach_dt_grad needs a context with one closed-loop network and no spec");
+  if (!c->rg_fn) return fail(c, DR_ESHAPE, "no reverse-pass kernel for this network (on-chip state too large)");
+  if (!b) return fail(c, DR_EINVAL, "batch is NULL");
+  if (b->n_sub > 0 && horizon > 0 && !g_V) return fail(c, DR_EINVAL, "g_V is NULL");
+  const bool exo = c->q < c->n0;
+  if (exo && du && !u && horizon > 0 && b->n_sub > 0) return fail(c, DR_EINVAL, "du needs the input sequences u");
+  const ReachGradLayout lay = reach_grad_layout(c, b->n_sub, horizon);
+  if (b->n_sub > 0 && (!workspace || workspace_bytes < lay.total))
+    return fail(c, DR_EINVAL, "workspace is NULL or smaller than dr_reach_grad_workspace(ctx, S, horizon)");
+  // the forward reach with its record
+  dr_status st = reach(c, b, horizon, u, boxes, status, stream, (double*)workspace);
+  if (st != DR_OK) return st;
+  const dr::NetDev& nd = c->hnet[0];
+  const int ns = nd.n_state;
+  if (dA) hipLaunchKernelGGL(dr::k_zero, dim3(1), dim3(256), 0, stream, dA, (size_t)ns * nd.n[0]);
+  if (dB) hipLaunchKernelGGL(dr::k_zero, dim3(1), dim3(256), 0, stream, dB, (size_t)ns * nd.n[nd.L]);
+  bool want_w = false;
+  for (int k = 0; k < nd.L; ++k) want_w = want_w || (dW && dW[k]) || (db && db[k]);
+  const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
+  if (want_w && b->n_sub > 0) {
+    const size_t words = (size_t)lay.grid * lay.wstride * tsz / sizeof(double);
+    hipLaunchKernelGGL(dr::k_zero, dim3(1024), dim3(256), 0, stream, (double*)((char*)workspace + lay.wreg_off), words);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, "zero kernel");
+  if (b->n_sub == 0) return DR_OK;
+  if (horizon == 0) {
+    // no step: the volume is 0 and every gradient is zero
+    if (dxc) hipLaunchKernelGGL(dr::k_zero, dim3(1), dim3(256), 0, stream, dxc, (size_t)b->n_sub * ns);
+    if (dxr) hipLaunchKernelGGL(dr::k_zero, dim3(1), dim3(256), 0, stream, dxr, (size_t)b->n_sub * ns);
+    for (int k = 0; want_w && k < nd.L; ++k) {
+      if (dW && dW[k]) hipLaunchKernelGGL(dr::k_zero, dim3(64), dim3(256), 0, stream, dW[k], (size_t)nd.n[k + 1] * nd.n[k]);
+      if (db && db[k]) hipLaunchKernelGGL(dr::k_zero, dim3(1), dim3(256), 0, stream, db[k], (size_t)nd.n[k + 1]);
+    }
+    e = hipGetLastError();
+    return e == hipSuccess ? DR_OK : hip_fail(c, e, "zero kernel");
+  }
+  dr::ReachGradArgs ga{};
+  ga.batch = c->batch; ga.sc = c->sc; ga.horizon = horizon;
+  ga.tape = (const double*)workspace;
+  ga.gV = g_V;
+  ga.gtape = (char*)workspace + lay.gtape_off;
+  ga.du = du; ga.dxc = dxc; ga.dxr = dxr; ga.dA = dA; ga.dB = dB;
+  ga.wreg = want_w ? (char*)workspace + lay.wreg_off : nullptr;
+  ga.wreg_stride = lay.wstride;
+  for (int k = 0; k < dr::kMaxL; ++k) ga.woff[k] = lay.woff[k];
+  int net_index = 0;
+  void* args[] = {&c->dnet, &net_index, &ga};
+  if ((st = launch(c, c->rg_fn, lay.grid, c->rg_lds, args, stream)) != DR_OK) return st;
+  if (want_w) {
+    dr::ReachWreduceArgs ra{};
+    ra.wreg = (char*)workspace + lay.wreg_off;
+    ra.stride = lay.wstride;
+    for (int k = 0; k < dr::kMaxL; ++k) ra.woff[k] = lay.woff[k];
+    ra.n_regions = lay.grid;
+    int maxe = 0;
+    for (int k = 0; k < nd.L; ++k) {
+      ra.dW[k] = dW ? dW[k] : nullptr;
+      ra.db[k] = db ? db[k] : nullptr;
+      maxe = std::max(maxe, nd.n[k + 1] * (nd.n[k] + 1));
+    }
+    const dim3 grid((maxe + 255) / 256, nd.L);
+    if (c->prec == DR_PREC_F64)
+      hipLaunchKernelGGL(dr::k_reach_wreduce<double>, grid, dim3(256), 0, stream, c->dnet, 0, ra);
+    else
+      hipLaunchKernelGGL(dr::k_reach_wreduce<float>, grid, dim3(256), 0, stream, c->dnet, 0, ra);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "weight-gradient reduction");
+  }
+  return DR_OK;
+}
 
 dr_status dr_reach_dt_joint(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, int* rows,
                             uint32_t* status, hipStream_t stream) {

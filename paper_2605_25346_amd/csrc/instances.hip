@@ -5,6 +5,7 @@
 // units of one shared library).
 #include "bound_kernels.hpp"
 #include "joint_kernels.hpp"
+#include "grad_kernels.hpp"
 #include "instances.h"
 
 #ifndef DR_T
@@ -43,6 +44,7 @@ const void* DR_CAT(dr_instance_, DR_T, DR_NT)(int kind, int variant) {
     case DR_KIND_PGRAD:
       return variant ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
     case DR_KIND_JOINT: return variant ? nullptr : (const void*)&dr::k_reach_joint<T, NT>;
+    case DR_KIND_RGRAD: return variant ? nullptr : (const void*)&dr::k_reach_grad<T, NT>;
     default: return nullptr;
   }
 }

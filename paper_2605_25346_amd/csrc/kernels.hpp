@@ -502,7 +502,19 @@ struct ReachArgs {
   double* boxes;            // S x (horizon + 1) x n_state x 2
   uint32_t* status;
   const double* u;          // S x horizon x (n_0 - n_state) exogenous inputs, or null
+  double* tape;             // null, or the record of the reach for its gradient (reach_tape_* layout)
 };
+
+// Record of one box's stepwise reach for the reverse pass (FP64): the Taylor model
+// entering every step and the final one (c 16, P 16 x 16, I_lo 16, I_hi 16 per step,
+// t = 0..H), then per step the final bounds l, u of every hidden neuron and the IBP
+// bounds of layers >= 2 (layer 1: its exact bounds again), natural order.
+constexpr int kTmDoubles = 304;
+__host__ __device__ inline size_t reach_tape_tm(int t) { return (size_t)t * kTmDoubles; }
+__host__ __device__ inline size_t reach_tape_bounds(int t, int H, int Hp) {
+  return (size_t)(H + 1) * kTmDoubles + (size_t)t * 4 * Hp;
+}
+__host__ __device__ inline size_t reach_tape_doubles(int H, int Hp) { return reach_tape_bounds(H, H, Hp); }
 
 
 // Arguments and per-box LDS state of k_reach_joint (CROWN through the unrolled loop).
@@ -558,6 +570,88 @@ struct JointLds {
     mux = (T*)take((size_t)H * 16 * sizeof(T));
     bias = (T*)take((size_t)Hp * sizeof(T));
     U = (int*)take((size_t)16 * NT * sizeof(int));
+    misc = (int*)take(8 * sizeof(int));
+  }
+};
+
+// Arguments and per-box LDS state of k_reach_grad (reverse pass through the stepwise reach).
+struct ReachGradArgs {
+  BatchDev batch;
+  Scratch sc;
+  int horizon;
+  const double* tape;       // per box reach_tape_doubles(H, Hp) doubles
+  const double* gV;         // S: dJ/dV_s
+  void* gtape;              // per wave: (L - 1) x NT x 256 chain-type values (multipliers g of a row tile)
+  double* du;               // S x H x (n_0 - n_state) or null
+  double* dxc;              // S x n_state or null
+  double* dxr;              // S x n_state or null
+  double* dA;               // n_state x n_0 (summed over the batch, atomically) or null
+  double* dB;               // n_state x n_L or null
+  // weight and bias gradients: one region per workgroup (chain type, summed later in a
+  // fixed order); layer k at woff[k-1], np_k rows of np_{k-1} + 1 entries (the last is
+  // the bias); null when not asked for
+  void* wreg;
+  size_t wreg_stride;       // chain-type elements per workgroup region
+  size_t woff[kMaxL];
+};
+
+// Per-box LDS state of k_reach_grad.
+template <typename T>
+struct GradLds {
+  V4<T>* rel;     // Hp relaxation of the current step (permuted order)
+  double* l;      // Hp natural: bounds of the current step
+  double* u;
+  double* ibl;
+  double* ibu;
+  double* ds;     // Hp: cotangents of the chord slopes and intercepts of the current step
+  double* dt;
+  double* dl;     // Hp: cotangents of the bounds of the current step
+  double* du;
+  double* tm;     // 304: model entering the step (c, P, I_lo, I_hi)
+  double* dO;     // 304: cotangent of the model leaving the step
+  double* dI;     // 304: cotangent of the model entering the step
+  double* Wr;     // 256: rows W_r = A_r + w_r of the output (r x v)
+  double* dWr;    // 256: their cotangents
+  double* rowc;   // 16 x 2: per-row cotangents of the offsets (output rows)
+  double* hcr;    // 2 x 16 NT: cotangents of the centre / radius of relu(h_{k-1}) (IBP in reverse)
+  signed char* wps;   // 16 NT x 16: signs of (W_1 P)_jz for layer 1 in reverse
+  T* ob;          // per wave 2 x 16 x 16: blocks of an outer product over a row tile (weight gradient)
+  double* orho;   // per wave 16: the rows' offset cotangents
+  T* bias;        // Hp: hidden biases in the chain type
+  int* U;         // 16 NT
+  int* misc;      // 8
+  __host__ __device__ static size_t r16(size_t n) { return (n + 15) & ~(size_t)15; }
+  __host__ __device__ static size_t bytes(int Hp, int NT) {
+    const size_t n16 = (size_t)16 * NT;
+    return r16((size_t)Hp * sizeof(V4<T>)) + 8 * r16((size_t)Hp * sizeof(double)) + 3 * r16(304 * sizeof(double)) +
+           2 * r16(256 * sizeof(double)) + r16(32 * sizeof(double)) + r16(2 * n16 * sizeof(double)) +
+           r16(n16 * 16) + r16(kWavesPerWG * 512 * sizeof(T)) + r16(kWavesPerWG * 16 * sizeof(double)) +
+           r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) + r16(8 * sizeof(int));
+  }
+  __device__ void carve(char* base, int Hp, int NT) {
+    auto take = [&](size_t n) { char* p = base; base += r16(n); return p; };
+    const size_t n16 = (size_t)16 * NT;
+    rel = (V4<T>*)take((size_t)Hp * sizeof(V4<T>));
+    l = (double*)take((size_t)Hp * sizeof(double));
+    u = (double*)take((size_t)Hp * sizeof(double));
+    ibl = (double*)take((size_t)Hp * sizeof(double));
+    ibu = (double*)take((size_t)Hp * sizeof(double));
+    ds = (double*)take((size_t)Hp * sizeof(double));
+    dt = (double*)take((size_t)Hp * sizeof(double));
+    dl = (double*)take((size_t)Hp * sizeof(double));
+    du = (double*)take((size_t)Hp * sizeof(double));
+    tm = (double*)take(304 * sizeof(double));
+    dO = (double*)take(304 * sizeof(double));
+    dI = (double*)take(304 * sizeof(double));
+    Wr = (double*)take(256 * sizeof(double));
+    dWr = (double*)take(256 * sizeof(double));
+    rowc = (double*)take(32 * sizeof(double));
+    hcr = (double*)take(2 * n16 * sizeof(double));
+    wps = (signed char*)take(n16 * 16);
+    ob = (T*)take(kWavesPerWG * 512 * sizeof(T));
+    orho = (double*)take(kWavesPerWG * 16 * sizeof(double));
+    bias = (T*)take((size_t)Hp * sizeof(T));
+    U = (int*)take(n16 * sizeof(int));
     misc = (int*)take(8 * sizeof(int));
   }
 };

@@ -63,4 +63,7 @@ def test_null_context_is_rejected_before_any_device_call():
     assert lib.dr_set_weights(N, 0, N, N) == binding.DR_EINVAL
     assert lib.dr_param_grad_workspace(N, 16) == 0
     assert lib.dr_reach_dt(N, N, 1, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_reach_dt_joint(N, N, 1, N, N, N, N, N) == binding.DR_EINVAL
+    assert lib.dr_reach_dt_grad(N, N, 1, N, N, N, N, N, N, N, N, N, N, N, 0, N, N) == binding.DR_EINVAL
+    assert lib.dr_reach_grad_workspace(N, 4, 2) == 0
     assert lib.dr_hidden_max(N) == 0 and lib.dr_spec_rows(N) == 0
