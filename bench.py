@@ -362,6 +362,42 @@ def joint_reach(torch, args, precision="f32", n_boxes=128):
     return res
 
 
+def reach_gradient(torch, args, precision="f32", n_boxes=128):
+    """Gradient of the tube volume through the stepwise reach (dr_reach_dt_grad: the
+    forward reach with its record, then the reverse pass) for the training batch shape of
+    the paper's DT comparison (128 initial sets of the 96-wide dynamics network with
+    actions, horizon 10), w.r.t. actions, boxes, A, B and all weights and biases; timed
+    against the forward reach alone.  Algorithmic FLOPs: three times the forward chain
+    FLOPs (the forward chains, the chains in reverse, and the weight-gradient outer
+    products, each of the size of the forward products)."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    from paper_2605_25346_amd.workloads import config_workload
+    wl = config_workload(6, n_sub=n_boxes)
+    S, H = wl.batch.n_sub, wl.horizon
+    ctx = BoundContext(wl.nets, precision=precision, max_sub=S, tile_cfg="auto")
+    db = DeviceBatch(wl.batch)
+    u = torch.as_tensor(wl.meta["u"], dtype=torch.float64, device="cuda")
+    boxes = torch.zeros(S, H + 1, ctx.n_state, 2, dtype=torch.float64, device="cuda")
+    gV = torch.full((S,), 1.0 / S, dtype=torch.float64, device="cuda")
+    ws = torch.empty(int(ctx.lib.dr_reach_grad_workspace(ctx.ctx, S, H)), dtype=torch.uint8, device="cuda")
+    reps = max(2, args.steps // 4)
+    ms_f, _ = time_graph(torch, lambda: ctx.dr_reach_dt(db, H, boxes=boxes, u=u), reps, 1)
+    rows = ctx.dr_get_rows().cpu().numpy()
+    ms_g, _ = time_graph(torch, lambda: ctx.dr_reach_dt_grad(db, H, gV, u=u, boxes=boxes, workspace=ws), reps, 1)
+    # the same without the weight and bias gradients (actions, boxes, A, B only: the MPC use)
+    ms_u, _ = time_graph(torch, lambda: ctx.dr_reach_dt_grad(db, H, gV, u=u, boxes=boxes, workspace=ws,
+                                                             want=("du", "dxc", "dxr", "dA", "dB")), reps, 1)
+    w = wl.nets[0].widths
+    L = len(w) - 1
+    fwd = sum(int(rows[:, k - 1].sum()) * chain_flops_per_row(w, k) for k in range(2, L))
+    fwd += int(rows[:, L - 1].sum()) * final_flops_per_row(w)
+    res = dict(S=S, horizon=H, ms_gradient=ms_g, ms_gradient_without_weights=ms_u, ms_forward=ms_f, ratio=ms_g / ms_f,
+               box_steps_per_s=S * H / (ms_g * 1e-3), flops=3 * fwd, tflops=3 * fwd / (ms_g * 1e-3) / 1e12,
+               workspace_bytes=int(ws.numel()))
+    ctx.close()
+    return res
+
+
 def mixed_batch(torch, args, precision="f32"):
     from paper_2605_25346_amd.api import BoundContext, DeviceBatch
     from paper_2605_25346_amd.workloads import config_workload
@@ -658,7 +694,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default="", help="comma-separated extra legs to run (for profiling one leg): "
-                    "f64,sweep,ascent,pgrad,reach,candidates,joint,tightness,mixed")
+                    "f64,sweep,ascent,pgrad,reach,candidates,joint,reachgrad,tightness,mixed")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -748,6 +784,13 @@ def main():
         extra["joint_crown_vs_stepwise_8+4-96x3-8_S128_H10"] = dict(
             jr, roofline=dict(bound="mfma", achieved=jr["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                               frac=jr["tflops"] / PEAK_TFLOPS["f32"], kernel="k_reach_joint"))
+    if leg("reachgrad"):
+        print("bench: reach-tube gradient", file=sys.stderr, flush=True)
+        rg = reach_gradient(torch, args, "f32")
+        print(f"bench: reach gradient {rg}", file=sys.stderr, flush=True)
+        extra["reach_volume_gradient_8+4-96x3-8_S128_H10"] = dict(
+            rg, roofline=dict(bound="mfma", achieved=rg["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
+                              frac=rg["tflops"] / PEAK_TFLOPS["f32"], kernel="k_reach_dt + k_reach_grad"))
     if leg("tightness"):
         for cfg_i, key in ((3, "equal_tightness_abcrown_8-128x4-4_vs_crown_input_splitting"),
                            (5, "equal_tightness_mixed_S16384_vs_crown_input_splitting")):

@@ -41,6 +41,19 @@ class DeviceBatch:
             self.split_packed = None
         self.max_splits = int(np.max(np.diff(batch.split_ptr))) if batch.n_sub else 0
 
+    @classmethod
+    def from_tensors(cls, x_center: torch.Tensor, x_radius: torch.Tensor):
+        """A batch of boxes without splits from FP64 device tensors (S x n_0)."""
+        self = cls.__new__(cls)
+        self.n_sub = int(x_center.shape[0])
+        self.x_center = x_center.detach().to(torch.float64).contiguous()
+        self.x_radius = x_radius.detach().to(torch.float64).contiguous()
+        self.net_id = torch.zeros(max(self.n_sub, 1), dtype=torch.int32, device=self.x_center.device)
+        self.split_ptr = None
+        self.split_packed = None
+        self.max_splits = 0
+        return self
+
     def struct(self) -> B.dr_batch:
         b = B.dr_batch()
         b.n_sub = self.n_sub
@@ -457,3 +470,53 @@ class CrownBounds(torch.autograd.Function):
                                                    init_duals=False)
         grads = [g.to(dt) for g, dt in zip(list(dW) + list(db), ctx_.dtypes)]
         return (None, None, *grads)
+
+
+class ReachVolume(torch.autograd.Function):
+    """Tube volume V_s (sum over steps 1..H and states of the widths of the reachable
+    boxes of the stepwise reach) of every box, as a differentiable function of the box
+    centres and radii (S x n_0: entries n_state.. of an exogenous network are ignored),
+    the action sequences u (S x H x (n_0 - n_state), or None) and a single-network
+    closed-loop context's weights and biases: the reachability-aware loss of the paper is
+    mean(log(1 + V)).
+
+    forward: dr_set_weights and the reach (dr_reach_dt / dr_reach_dt_exo);
+    backward: dr_reach_dt_grad with g_V = the incoming gradient (the reverse pass
+    through every step, intermediate bounds included).  The backward pass reruns the
+    reach with the weights set at forward time; like CrownBounds it refuses a context
+    whose state a later call replaced."""
+
+    @staticmethod
+    def forward(ctx_, bctx: BoundContext, x_center, x_radius, u, horizon: int, *params):
+        L = len(params) // 2
+        Ws, bs = params[:L], params[L:]
+        bctx.dr_set_weights(0, [W.detach() for W in Ws], [b.detach() for b in bs])
+        batch = DeviceBatch.from_tensors(x_center, x_radius)
+        ud = u.detach().to(torch.float64).contiguous() if u is not None else None
+        boxes, _ = bctx.dr_reach_dt(batch, horizon, u=ud)
+        V = (boxes[:, 1:, :, 1] - boxes[:, 1:, :, 0]).sum(dim=(1, 2))
+        ctx_.bctx, ctx_.batch, ctx_.u, ctx_.horizon = bctx, batch, ud, horizon
+        ctx_.generation = bctx.generation
+        ctx_.shapes = (x_center.shape, x_radius.shape, None if u is None else u.shape)
+        ctx_.dtypes = [p.dtype for p in params]
+        return V
+
+    @staticmethod
+    def backward(ctx_, g_V):
+        bctx = ctx_.bctx
+        if bctx.generation != ctx_.generation:
+            raise RuntimeError("ReachVolume.backward: the context's state changed after this forward; "
+                               "use one BoundContext per pending forward")
+        _, _, g = bctx.dr_reach_dt_grad(ctx_.batch, ctx_.horizon, g_V.detach().contiguous(), u=ctx_.u,
+                                        want=("du", "dxc", "dxr", "dW", "db"))
+        bctx.generation = ctx_.generation      # the rerun reproduces the forward's state
+        xs, rs, us = ctx_.shapes
+        ns = bctx.n_state
+        dxc = torch.zeros(xs, dtype=torch.float64, device=bctx.device)
+        dxr = torch.zeros(rs, dtype=torch.float64, device=bctx.device)
+        dxc[:, :ns] = g["dxc"][: xs[0]]
+        dxr[:, :ns] = g["dxr"][: rs[0]]
+        du = g["du"][: us[0], : us[1]].reshape(us) if us is not None else None
+        grads = [t.to(dt) for t, dt in zip(list(g["dW"]) + list(g["db"]), ctx_.dtypes)]
+        return (None, dxc, dxr, du, None, *grads)
+

@@ -554,7 +554,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     c->rg_lds = (size_t)dr::kWavesPerWG * dr::stage_bytes_rt(tsz, nd.NT, false) +
                 (c->prec == DR_PREC_F64 ? dr::GradLds<double>::bytes(nd.Hp, nd.NT) : dr::GradLds<float>::bytes(nd.Hp, nd.NT));
     if (c->rg_fn && c->rg_lds <= kMaxLds) {
-      if ((e = hipFuncSetAttribute(c->rg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->rg_lds)) != hipSuccess)
+      if ((e = hipFuncSetAttribute(c->rg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
         return bail(hip_fail(c, e, "hipFuncSetAttribute"));
       c->rg_grid = persistent_grid(c, c->rg_fn, c->rg_lds, Q_REACH);
     } else {
@@ -982,7 +982,10 @@ dr_status dr_reach_dt_grad(dr_ctx* c, const dr_batch* b, int horizon, const doub
   bool want_w = false;
   for (int k = 0; k < nd.L; ++k) want_w = want_w || (dW && dW[k]) || (db && db[k]);
   const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
-  if (want_w && b->n_sub > 0) {
+  // the weight-gradient regions: accumulated in LDS and stored once per workgroup when they
+  // fit beside the kernel's state, else accumulated in global memory (cleared first)
+  const bool wacc_lds = want_w && c->rg_lds + lay.wstride * tsz <= kMaxLds;
+  if (want_w && !wacc_lds && b->n_sub > 0) {
     const size_t words = (size_t)lay.grid * lay.wstride * tsz / sizeof(double);
     hipLaunchKernelGGL(dr::k_zero, dim3(1024), dim3(256), 0, stream, (double*)((char*)workspace + lay.wreg_off), words);
   }
@@ -1008,10 +1011,12 @@ dr_status dr_reach_dt_grad(dr_ctx* c, const dr_batch* b, int horizon, const doub
   ga.du = du; ga.dxc = dxc; ga.dxr = dxr; ga.dA = dA; ga.dB = dB;
   ga.wreg = want_w ? (char*)workspace + lay.wreg_off : nullptr;
   ga.wreg_stride = lay.wstride;
+  ga.wacc_lds = wacc_lds ? 1 : 0;
   for (int k = 0; k < dr::kMaxL; ++k) ga.woff[k] = lay.woff[k];
   int net_index = 0;
   void* args[] = {&c->dnet, &net_index, &ga};
-  if ((st = launch(c, c->rg_fn, lay.grid, c->rg_lds, args, stream)) != DR_OK) return st;
+  const size_t lds = c->rg_lds + (wacc_lds ? lay.wstride * tsz : 0);
+  if ((st = launch(c, c->rg_fn, lay.grid, lds, args, stream)) != DR_OK) return st;
   if (want_w) {
     dr::ReachWreduceArgs ra{};
     ra.wreg = (char*)workspace + lay.wreg_off;

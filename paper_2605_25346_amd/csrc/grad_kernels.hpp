@@ -43,7 +43,7 @@ __device__ __forceinline__ double sum16(double v) {
 // cotangents (each lane reads back only its own entries).
 template <typename T>
 struct WgradTile {
-  gmut<T> reg;
+  T* reg;             // LDS accumulator or global region (generic address)
   const size_t* woff;
   lmut<T> A;          // 16 rows x 16 outputs of W_k
   lmut<T> B;          // 16 rows x 16 inputs of W_k
@@ -59,7 +59,7 @@ template <typename T, typename FA, typename FB>
 __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int ld, int ti, int tj, int ni, int nj,
                                              FA a_of, FB b_of, bool bias, int lane) {
   const int r = lane & 15, g = lane >> 4;
-  gmut<T> reg = W.reg + W.woff[k - 1];
+  T* reg = W.reg + W.woff[k - 1];
   for (int it = 0; it < ti; ++it) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) W.A[r * 16 + nrn<T>(g, i)] = a_of(it, i);
@@ -76,7 +76,7 @@ __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int l
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int i = it * 16 + 4 * g + c, j = jt * 16 + r;
-        if (i < ni && j < nj && acc[c] != (T)0) atomicAdd((T*)(reg + (size_t)i * ld + j), acc[c]);
+        if (i < ni && j < nj && acc[c] != (T)0) atomicAdd(reg + (size_t)i * ld + j, acc[c]);
       }
       if (bias && jt == 0 && r == 0) {
 #pragma unroll
@@ -84,7 +84,7 @@ __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int l
           double bsum = 0.0;
           for (int rr = 0; rr < 16; ++rr) bsum += W.rho[rr] * (double)W.A[rr * 16 + 4 * g + c];
           const int i = it * 16 + 4 * g + c;
-          if (i < ni && bsum != 0.0) atomicAdd((T*)(reg + (size_t)i * ld + (ld - 1)), (T)bsum);
+          if (i < ni && bsum != 0.0) atomicAdd(reg + (size_t)i * ld + (ld - 1), (T)bsum);
         }
       }
       sub_sync<64>();
@@ -205,7 +205,11 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
   const int wave_global = blockIdx.x * kWavesPerWG + wid;
   gmut<T> tape = as_global_mut((T*)ga.gtape + (size_t)wave_global * (L - 1) * NT * 256);
   WgradTile<T> W;
-  W.reg = ga.wreg ? as_global_mut((T*)ga.wreg + (size_t)blockIdx.x * ga.wreg_stride) : nullptr;
+  T* wglob = ga.wreg ? (T*)ga.wreg + (size_t)blockIdx.x * ga.wreg_stride : nullptr;
+  if (ga.wreg && ga.wacc_lds) {
+    for (size_t e = tid; e < ga.wreg_stride; e += kWG) G.wacc[e] = (T)0;
+  }
+  W.reg = ga.wreg ? (ga.wacc_lds ? G.wacc : wglob) : nullptr;
   W.woff = ga.woff;
   W.A = (lmut<T>)(G.ob + wid * 512);
   W.B = (lmut<T>)(G.ob + wid * 512 + 256);
@@ -215,7 +219,7 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
   const bool wg = W.reg != nullptr;
   // atomic add into this workgroup's weight-gradient region: layer k, entry (i, j)
   auto wadd = [&](int k, int i, int j, double v) {
-    if (v != 0.0) atomicAdd((T*)(W.reg + ga.woff[k - 1] + (size_t)i * (net.np[k - 1] + 1) + j), (T)v);
+    if (v != 0.0) atomicAdd(W.reg + ga.woff[k - 1] + (size_t)i * (net.np[k - 1] + 1) + j, (T)v);
   };
   const double* c = G.tm;
   const double* Pm = G.tm + 16;
@@ -528,6 +532,11 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
       if (ga.dxr) ga.dxr[(size_t)b * ns + tid] = G.dO[16 + tid * 16 + tid];
     }
     lds_barrier();
+  }
+  if (wglob && ga.wacc_lds) {
+    // the workgroup's sums, stored once (its own region: plain stores)
+    __syncthreads();
+    for (size_t e = tid; e < ga.wreg_stride; e += kWG) wglob[e] = G.wacc[e];
   }
 }
 

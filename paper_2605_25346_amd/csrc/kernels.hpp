@@ -593,6 +593,7 @@ struct ReachGradArgs {
   void* wreg;
   size_t wreg_stride;       // chain-type elements per workgroup region
   size_t woff[kMaxL];
+  int wacc_lds;             // 1: the region is accumulated in LDS and stored once per workgroup
 };
 
 // Per-box LDS state of k_reach_grad.
@@ -620,6 +621,7 @@ struct GradLds {
   T* bias;        // Hp: hidden biases in the chain type
   int* U;         // 16 NT
   int* misc;      // 8
+  T* wacc;        // the workgroup's weight-gradient accumulator (when it fits in LDS)
   __host__ __device__ static size_t r16(size_t n) { return (n + 15) & ~(size_t)15; }
   __host__ __device__ static size_t bytes(int Hp, int NT) {
     const size_t n16 = (size_t)16 * NT;
@@ -653,6 +655,7 @@ struct GradLds {
     bias = (T*)take((size_t)Hp * sizeof(T));
     U = (int*)take(n16 * sizeof(int));
     misc = (int*)take(8 * sizeof(int));
+    wacc = (T*)base;    // beyond bytes(): present when the launch added its size
   }
 };
 
