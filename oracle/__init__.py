@@ -35,5 +35,13 @@ fallback for it.  Parity status per function:
   respect to actions, box centre and radius, A, B, weights and biases; closed forms of
   dV/dr for B = 0 and for an all-active affine loop, and zero action/centre gradients
   there).
+* ct.picard_step, flowpipe, precondition, controller_tm, closed_loop: pinned (constant
+  fields: the exact translate of the box; linear fields: the Picard polynomial equals
+  the second-order Taylor expansion of exp(F s) and every box contains the exact image
+  exp(F t) X_0; the scalar Riccati equation x' = -x^2 against its exact interval;
+  ODE-solver trajectories inside every time-point and segment box and inside the Taylor
+  model itself; a controller with zero output weights reduces the closed loop to the
+  open-loop flowpipe with a constant input; sampled zero-order-hold closed loops inside
+  every box).
 """
-from . import crown, exact, joint, tm, tm_grad  # noqa: F401
+from . import crown, ct, exact, joint, tm, tm_grad  # noqa: F401

@@ -24,8 +24,8 @@ i.e. c + A z + B s z with z = (y, s).  Readings where the paper is silent:
     [0, h] and j in J of f(p + j) - d/ds p, computed in TM arithmetic so that the
     polynomial terms of f(p) cancel d/ds p before the remaining ones are bounded;
     J is valid once J' is inside J (starting from [-eps, eps] and widening to the
-    image plus eps while it is not, at most `tries` times), then refined by R more
-    images;
+    image plus eps while it is not, at most `tries` times, and giving up once J is
+    unbounded: the theorem asks for a bounded interval), then refined by R more images;
   * preconditioning (linear reparameterisation of the step-end model c + S y + r,
     r in J): the centre of J moves into c and the rest is absorbed into the linear part,
     S y + r = S D y' with D = diag(1 + |S^-1| rad J) and y' = D^-1 (y + S^-1 r) in
@@ -230,6 +230,8 @@ def picard_step(f: QuadDynamics, c, S, I0lo, I0hi, h, U=None, order=2, eps=1e-9,
 
     Jlo, Jhi = I0lo - eps, I0hi + eps
     ok = False
+    if not (np.all(np.isfinite(I0lo)) and np.all(np.isfinite(I0hi))):
+        tries = 0   # an unbounded initial set has no bounded remainder
     for _ in range(tries):
         nlo, nhi = image(Jlo, Jhi)
         if np.all(nlo >= Jlo) and np.all(nhi <= Jhi):
@@ -240,6 +242,8 @@ def picard_step(f: QuadDynamics, c, S, I0lo, I0hi, h, U=None, order=2, eps=1e-9,
         wid = np.maximum(nhi - nlo, eps)
         Jlo = np.minimum(Jlo, nlo) - 0.5 * wid
         Jhi = np.maximum(Jhi, nhi) + 0.5 * wid
+        if not (np.all(np.isfinite(Jlo)) and np.all(np.isfinite(Jhi))):
+            break   # an unbounded set is no remainder of the theorem
     if not ok:
         return QTM(p.c, p.L, p.l, p.M, p.w, np.full(n, -np.inf), np.full(n, np.inf)), False
     for _ in range(rounds):
