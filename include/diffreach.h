@@ -11,7 +11,11 @@
  *     box enclosure) at every step, with the TM--CROWN interface of Theorem
  *     "CROWN bounds of NN with linear TM input" and the shared-slope constraint;
  *   - "Gradient" refinement of the table "Refinement strategies": projected
- *     gradient ascent on the relaxation slopes alpha and split multipliers beta.
+ *     gradient ascent on the relaxation slopes alpha and split multipliers beta;
+ *   - Algorithms "Reachability of CT Dynamics with TM Flowpipe" and "Reachability
+ *     of CT NN Control Systems": Taylor-model flowpipes of polynomial vector fields,
+ *     alone or with a network controller (dr_flowpipe_ct, dr_reach_ct; these carry
+ *     no rounding margin, see there).
  *
  * Conventions shared by every entry point
  *   - All array arguments are DEVICE pointers owned by the caller unless stated
@@ -315,6 +319,65 @@ dr_status dr_reach_dt_grad(dr_ctx* ctx, const dr_batch* batch, int horizon, cons
                            double* boxes, double* du, double* dxc, double* dxr, double* dA, double* dB,
                            double* const* dW, double* const* db, void* workspace, size_t workspace_bytes,
                            uint32_t* status, hipStream_t stream);
+
+/* Continuous-time reachability with Taylor-model flowpipes (Section "Propagation under
+ * Continuous-Time Analytical Dynamics", Theorem "TM flowpipe step via Picard iteration",
+ * appendix Algorithm "Reachability of CT Dynamics with TM Flowpipe"; the closed loop of
+ * Algorithm "Reachability of CT NN Control Systems").
+ *
+ * The vector field is polynomial of degree <= 2 in the state and affine in the input:
+ *   f_i(x, u) = a_i + sum_j F_ij x_j + sum_k G_ik u_k + sum_jk Q_ijk x_j x_k.
+ * Each box [c - r, c + r] is carried as a Taylor model of the paper's quasi-quadratic
+ * fixed shape, X(y, s) = c + L y + l s + s (M y) + w s^2 (+) [lo, hi] over the box's
+ * generators y in [-1, 1]^n and the time s in [0, h]: per step two Picard iterations of
+ * the polynomial part, a remainder validated by the Picard operator (widened at most
+ * `tries` times, then refined `rounds` times), the step-end model, and the remainder
+ * absorbed into the linear part when that is well conditioned.  All arithmetic is FP64
+ * without outward rounding of the flowpipe steps.  A box whose step found no validated
+ * remainder gets DR_RES_NONFINITE and unbounded boxes from that step on. */
+typedef struct {
+  int n;              /* state dimension, 1..16 */
+  int n_u;            /* input dimension, 0..16 (0: no input) */
+  const double* a;    /* device n */
+  const double* F;    /* device n x n, row-major */
+  const double* G;    /* device n x n_u, row-major; NULL when n_u == 0 */
+  const double* Q;    /* device n x n x n (Q_ijk at (i n + j) n + k), or NULL: linear field */
+} dr_ct_field;
+
+typedef struct {
+  double h;           /* flowpipe step, 0 < h < inf */
+  int steps;          /* flowpipe steps per control interval, K >= 1 */
+  int intervals;      /* control intervals N >= 0 (N K steps in all; K N <= 100000) */
+  int tries;          /* widenings of the remainder guess, 1..1000 (40 is ample) */
+  int rounds;         /* refinements of a validated remainder, 0..100 (3) */
+  double eps;         /* half-width of the first remainder guess, > 0 (1e-9) */
+} dr_ct_options;
+
+/* The flowpipe of x' = f(x) (n_u must be 0) from n_sub boxes (x_center, x_radius: device
+ * n_sub x n; x_radius >= 0).  Outputs (device, FP64, written in full):
+ *   boxes     n_sub x (N K + 1) x n x 2: the boxes of the time points 0, h, .., N K h;
+ *   segments  n_sub x N K x n x 2: the box of every step's segment [t, t + h], or NULL;
+ *   status    n_sub: DR_RES_* bits, or NULL.
+ * Takes no context: errors are described by dr_last_error(NULL).  One wavefront per box.
+ * Asynchronous on `stream`; allocates nothing. */
+dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* opt, int n_sub, const double* x_center,
+                         const double* x_radius, double* boxes, double* segments, uint32_t* status,
+                         hipStream_t stream);
+
+/* The closed loop x' = f(x, u) with the network of `ctx` as the controller, its output
+ * held over each control interval of K steps (zero-order hold).  At every control
+ * boundary the controller is certified on the state's Taylor model by the step of
+ * dr_reach_dt (Theorem "CROWN bounds of NN with linear TM input"): `ctx` must be a
+ * closed-loop context with one network, no spec, n_0 = f->n inputs and n_state = f->n_u
+ * (so n_u <= n), whose loop matrices A (n_u x n) and B (n_u x n_u) make the held input
+ * u = A x + B net(x); pass A = 0 and B = I for a plain network controller.  The
+ * controller's chains run in the context's precision (rigorous margins as configured);
+ * the input's model is linear over the same generators, its interval part centred.
+ * Batch as for dr_reach_dt (no splits; x_center, x_radius n_sub x n); outputs as for
+ * dr_flowpipe_ct; status also carries the controller step's bits.  One workgroup per
+ * box.  Asynchronous on `stream`; allocates nothing. */
+dr_status dr_reach_ct(dr_ctx* ctx, const dr_ct_field* f, const dr_ct_options* opt, const dr_batch* batch,
+                      double* boxes, double* segments, uint32_t* status, hipStream_t stream);
 
 /* Diagnostics of the last dr_bound_init / dr_propagate_backward /
  * dr_optimize_duals / dr_reach_dt on this context (device outputs):

@@ -65,6 +65,57 @@ class DeviceBatch:
         return b
 
 
+class CtField:
+    """A polynomial vector field f_i(x, u) = a_i + F_i x + G_i u + x^T Q_i x resident in
+    device memory (FP64), for dr_flowpipe_ct and dr_reach_ct."""
+
+    def __init__(self, a, F, G=None, Q=None, device="cuda"):
+        f64 = lambda v: torch.as_tensor(np.asarray(v, np.float64), dtype=torch.float64, device=device).contiguous()
+        self.a, self.F = f64(a), f64(F)
+        self.n = int(self.F.shape[0])
+        self.G = f64(G) if G is not None and np.asarray(G).size else None
+        self.n_u = int(self.G.shape[1]) if self.G is not None else 0
+        self.Q = f64(Q) if Q is not None and np.any(np.asarray(Q)) else None
+
+    @classmethod
+    def from_dynamics(cls, f, device="cuda"):
+        """From an object with attributes a, F, G, Q (G n x n_u, Q n x n x n)."""
+        return cls(f.a, f.F, getattr(f, "G", None), getattr(f, "Q", None), device=device)
+
+    def struct(self) -> B.dr_ct_field:
+        s = B.dr_ct_field()
+        s.n, s.n_u = self.n, self.n_u
+        s.a, s.F = self.a.data_ptr(), self.F.data_ptr()
+        s.G = self.G.data_ptr() if self.G is not None else None
+        s.Q = self.Q.data_ptr() if self.Q is not None else None
+        return s
+
+
+def ct_options(h, steps, intervals=1, tries=40, rounds=3, eps=1e-9) -> B.dr_ct_options:
+    o = B.dr_ct_options()
+    o.h, o.steps, o.intervals, o.tries, o.rounds, o.eps = float(h), int(steps), int(intervals), int(tries), int(rounds), float(eps)
+    return o
+
+
+def dr_flowpipe_ct(field: CtField, x_center, x_radius, h, steps, intervals=1, segments=True, **kw):
+    """Flowpipe of x' = f(x) from the boxes [x_center - x_radius, x_center + x_radius]
+    (S x n): returns (boxes S x (N K + 1) x n x 2, segments S x N K x n x 2 or None,
+    status S)."""
+    lib = B.load()
+    dev = field.F.device
+    xc = torch.as_tensor(x_center, dtype=torch.float64, device=dev).contiguous()
+    xr = torch.as_tensor(x_radius, dtype=torch.float64, device=dev).contiguous()
+    S, n = int(xc.shape[0]), field.n
+    N = int(steps) * int(intervals)
+    boxes = torch.empty(S, N + 1, n, 2, dtype=torch.float64, device=dev)
+    segs = torch.empty(S, N, n, 2, dtype=torch.float64, device=dev) if segments else None
+    status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+    fs, o = field.struct(), ct_options(h, steps, intervals, **kw)
+    B.check(lib.dr_flowpipe_ct(ctypes.byref(fs), ctypes.byref(o), S, _ptr(xc), _ptr(xr), _ptr(boxes), _ptr(segs),
+                               _ptr(status), _stream()), None)
+    return boxes, segs, status[:S]
+
+
 class BoundContext:
     """dr_create + the per-batch entry points, holding the device copies of the
     networks and the output tensors."""
@@ -360,6 +411,25 @@ class BoundContext:
             _ptr(grads.get("dxc")), _ptr(grads.get("dxr")), _ptr(grads.get("dA")), _ptr(grads.get("dB")),
             dWp, dbp, _ptr(workspace), ctypes.c_size_t(workspace.numel()), _ptr(status), _stream()))
         return boxes, status[:S], grads
+
+    def dr_reach_ct(self, field: CtField, batch: DeviceBatch, h, steps, intervals, segments=True, **kw):
+        """CT closed loop with this context's network as the controller (held over each
+        control interval of `steps` flowpipe steps): returns (boxes, segments, status)
+        as dr_flowpipe_ct."""
+        self.batch = batch
+        self.generation += 1
+        S, n = batch.n_sub, field.n
+        N = int(steps) * int(intervals)
+        dev = self.device
+        boxes = torch.empty(S, N + 1, n, 2, dtype=torch.float64, device=dev)
+        segs = torch.empty(S, N, n, 2, dtype=torch.float64, device=dev) if segments else None
+        status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+        fs, o = field.struct(), ct_options(h, steps, intervals, **kw)
+        b = batch.struct()
+        self._batch_struct = b
+        self._check(self.lib.dr_reach_ct(self.ctx, ctypes.byref(fs), ctypes.byref(o), ctypes.byref(b), _ptr(boxes),
+                                         _ptr(segs), _ptr(status), _stream()))
+        return boxes, segs, status[:S]
 
     def dr_get_bounds(self):
         S = self.batch.n_sub

@@ -26,6 +26,7 @@ EXPORTED = [
     "dr_create", "dr_bound_init", "dr_propagate_backward", "dr_concretize", "dr_optimize_duals",
     "dr_param_grad_workspace", "dr_param_grad", "dr_param_grad_static", "dr_set_weights",
     "dr_reach_dt", "dr_reach_dt_exo", "dr_reach_dt_joint", "dr_reach_grad_workspace", "dr_reach_dt_grad",
+    "dr_flowpipe_ct", "dr_reach_ct",
     "dr_get_bounds", "dr_get_rows", "dr_get_margins", "dr_hidden_max", "dr_spec_rows",
     "dr_last_error", "dr_destroy",
 ]
@@ -69,6 +70,28 @@ class dr_options(ctypes.Structure):
     ]
 
 
+class dr_ct_field(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int),
+        ("n_u", ctypes.c_int),
+        ("a", ctypes.c_void_p),
+        ("F", ctypes.c_void_p),
+        ("G", ctypes.c_void_p),
+        ("Q", ctypes.c_void_p),
+    ]
+
+
+class dr_ct_options(ctypes.Structure):
+    _fields_ = [
+        ("h", ctypes.c_double),
+        ("steps", ctypes.c_int),
+        ("intervals", ctypes.c_int),
+        ("tries", ctypes.c_int),
+        ("rounds", ctypes.c_int),
+        ("eps", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -100,6 +123,9 @@ def load():
         "dr_reach_dt_joint": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P, P]),
         "dr_reach_grad_workspace": (ctypes.c_size_t, [P, I, I]),
         "dr_reach_dt_grad": (I, [P, ctypes.POINTER(dr_batch), I, P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P, P]),
+        "dr_flowpipe_ct": (I, [ctypes.POINTER(dr_ct_field), ctypes.POINTER(dr_ct_options), I, P, P, P, P, P, P]),
+        "dr_reach_ct": (I, [P, ctypes.POINTER(dr_ct_field), ctypes.POINTER(dr_ct_options), ctypes.POINTER(dr_batch),
+                            P, P, P, P]),
         "dr_get_bounds": (I, [P, P, P, P]),
         "dr_get_rows": (I, [P, P, P]),
         "dr_get_margins": (I, [P, P, P]),

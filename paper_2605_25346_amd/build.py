@@ -24,7 +24,8 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 INSTANCES = [(t, nt) for t in ("float", "double") for nt in (2, 4, 6, 8, 16)]
-HEADERS = ["kernels.hpp", "bound_kernels.hpp", "aux_kernels.hpp", "joint_kernels.hpp", "grad_kernels.hpp", "instances.h"]
+HEADERS = ["kernels.hpp", "bound_kernels.hpp", "aux_kernels.hpp", "joint_kernels.hpp", "grad_kernels.hpp", "ct_flow.hpp", "ct_kernels.hpp",
+           "instances.h"]
 
 
 def _units():

@@ -1,7 +1,8 @@
 // gfx950 kernels of batched CROWN-style bound propagation: the small kernels launched
 // directly by the host side of the C-ABI (parameter-gradient contraction, concretization,
 // layout of the fused spec rows, queue reset, weight copies and swizzles, final-row
-// seeds, batch ordering, diagnostics export).
+// seeds, batch ordering, diagnostics export, the continuous-time flowpipe without a
+// controller).
 //   k_concretize   a6: FP64 box concretization with outward rounding.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -9,6 +10,7 @@
 #include <stdint.h>
 
 #include "kernels.hpp"
+#include "ct_flow.hpp"
 #include "diffreach.h"
 
 namespace dr {
@@ -396,6 +398,29 @@ __global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __re
   }
   l[e] = lo;
   u[e] = hi;
+}
+
+// The flowpipe without a controller: one wavefront per box (Algorithm "Reachability of
+// CT Dynamics with TM Flowpipe").
+__global__ void __launch_bounds__(64) k_flowpipe_ct(CtArgs ca) {
+  extern __shared__ __align__(16) char ct_raw[];
+  CtLds C;
+  C.carve((double*)ct_raw);
+  const int i = threadIdx.x, n = ca.dyn.n;
+  const int N = ca.n_ctl * ca.K;
+  for (int b = blockIdx.x; b < ca.batch.n_sub; b += gridDim.x) {
+    ct_seed(C, ca, b, n);
+    if (i < n) {
+      double lo, hi;
+      ct_point_box(C, i, lo, hi);
+      double* bo = ca.boxes + (size_t)b * (N + 1) * n * 2;
+      bo[i * 2 + 0] = lo; bo[i * 2 + 1] = hi;
+    }
+    bool ok = true;
+    for (int k = 0; k < ca.n_ctl; ++k) ok = ct_steps(C, ca, false, b, k * ca.K) && ok;
+    if (i == 0 && ca.status) ca.status[b] = ok ? 0u : (uint32_t)DR_RES_NONFINITE;
+    ct_sync();
+  }
 }
 
 }  // namespace dr

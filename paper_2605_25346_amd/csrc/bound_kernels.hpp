@@ -1202,89 +1202,27 @@ __global__ void __launch_bounds__(kWG) k_final(const NetDev* __restrict__ nets, 
 
 // ---------------------------------------------------------------------------
 // a8: stepwise closed-loop reachability with linear TMs (one WG per box).
-// ---------------------------------------------------------------------------
-// Two workgroups per CU for the FP32 reach of 64- and 96-wide networks: the register
-// budget of 256 costs a few spills there and doubles the boxes in flight (measured);
-// wider or FP64 instances keep one.
-template <typename T, int NT> constexpr int reach_waves_per_eu() { return sizeof(T) == 4 && (NT == 4 || NT == 6) ? 2 : 1; }
-
+// One step of the stepwise reach on the Taylor model tm = (c 16, P 16 x 16, I_lo 16,
+// I_hi 16, |x| bound 16) entering the step: the intermediate bounds of the network over
+// the model (layer 1 exact, deeper layers shared-slope CROWN intersected with IBP) and
+// the model of x' = A v + B f(v) in (nc, nP, nI_lo, nI_hi) at tm + 320 .. (see
+// k_reach_dt).  Records the step into the tape tb (if not null) and writes the box of
+// x' to bx (if not null).  Called by the whole workgroup.
 template <typename T, int NT>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(reach_waves_per_eu<T, NT>())))
-k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
-  extern __shared__ __align__(16) char lds_raw[];
-  const NetDev& net = nets[net_index];
-  const Scratch& sc = ra.sc;
+__device__ __forceinline__ void tm_crown_step(const NetDev& net, const Scratch& sc, SubLds<T>& S, char* stage,
+                                              T* lds_b, double* tm, double* tb, int step, int H, int s, double* bx) {
   const int L = net.L, Hp = net.Hp;
-  const int wid_ = threadIdx.x >> 6;
-  // dynamic LDS: per-wave chain stages, the subdomain state, then the TM state
-  char* stage = lds_raw + (size_t)wid_ * stage_bytes<T, NT>();
-  char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
-  SubLds<T> S;
-  S.carve(lds_base, Hp, NT);
-  T* lds_b = (T*)(lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds);
-  stage_biases<T, T>(net, lds_b);
-  // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
-  // (offsets stay on the LDS base pointer so that every access is an LDS access)
-  double* tm = (double*)(lds_base + ((SubLds<T>::bytes(Hp, NT) + 64 + 15) & ~(size_t)15));
-  double* c = tm;            // 16
-  double* Pm = tm + 16;      // 256 (row-major n x n)
-  double* Ilo = tm + 272;    // 16
-  double* Ihi = tm + 288;    // 16
-  double* Xab = tm + 304;    // 16: bound on |x_m| over the TM
-  double* nc = tm + 320;     // next state
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, gq = lane >> 4;
+  const int n0 = net.n[0], ns = net.n_state;
+  double* c = tm;
+  double* Pm = tm + 16;
+  double* Ilo = tm + 272;
+  double* Ihi = tm + 288;
+  double* Xab = tm + 304;
+  double* nc = tm + 320;
   double* nP = tm + 336;
   double* nIlo = tm + 592;
   double* nIhi = tm + 608;
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, gq = lane >> 4;
-  const int cnt = batch_count(sc, net_index);
-  const int n0 = net.n[0], ns = net.n_state, H = ra.horizon;
-
-  bool first = true;
-  for (;;) {
-    int item;
-    if (first) {
-      first = false;
-      item = blockIdx.x;
-    } else {
-      if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(ra.queue, 1u);
-      lds_barrier();
-      item = S.misc[0];
-      lds_barrier();
-    }
-    if (item >= cnt) break;
-    const int s = subdomain_of(sc, net_index, item);
-    double* bx = ra.boxes + (size_t)s * (H + 1) * ns * 2;
-    double* tb = ra.tape ? ra.tape + (size_t)s * reach_tape_doubles(H, Hp) : nullptr;
-    // TM normalisation of the state box: c = centre, P = diag(radius), I = [0, 0]; the
-    // exogenous inputs (network inputs ns..n0-1) enter each step as points
-    if (tid < 16) {
-      double cc = tid < ns ? ra.batch.xc[(size_t)s * n0 + tid] : 0.0;
-      double rr = tid < ns ? ra.batch.xr[(size_t)s * n0 + tid] : 0.0;
-      c[tid] = cc; Ilo[tid] = 0.0; Ihi[tid] = 0.0;
-      if (tid < ns) { bx[tid * 2 + 0] = cc - rr; bx[tid * 2 + 1] = cc + rr; }
-    }
-    for (int e = tid; e < 256; e += kWG) {
-      int a = e >> 4, b = e & 15;
-      Pm[e] = (a == b && a < ns) ? ra.batch.xr[(size_t)s * n0 + a] : 0.0;
-    }
-    for (int p = tid; p < Hp; p += kWG) S.slot[p] = -1;
-    if (tid == 0) S.misc[1] = 0;
-    if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
-    lds_barrier();
-    for (int step = 0; step < H; ++step) {
-      // |x_m| bound over the TM, and the input-centre/radius for the layer-1 bounds
-      if (tid < 16) {
-        if (tid >= ns && tid < n0) c[tid] = ra.u[((size_t)s * H + step) * (n0 - ns) + (tid - ns)];
-        double a = fabs(c[tid]) + fmax(fabs(Ilo[tid]), fabs(Ihi[tid]));
-        for (int z = 0; z < n0; ++z) a += fabs(Pm[tid * 16 + z]);
-        Xab[tid] = tid < n0 ? a : 0.0;
-        S.xc[tid] = 0.0; S.xr[tid] = 0.0;
-      }
-      lds_barrier();
-      if (tb) {
-        double* tt = tb + reach_tape_tm(step);
-        for (int e = tid; e < kTmDoubles; e += kWG) tt[e] = tm[e];
-      }
       // ---- layer 1 on the TM input: exact range of W_1 (c + P z + r) + b_1
       {
         const int n1 = net.n[1];
@@ -1458,13 +1396,101 @@ k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
 #pragma unroll
           for (int z = 0; z < 16; ++z) nP[r * 16 + z] = (z < n0) ? pp[z] : 0.0;
           double blo = cpart - rad + nIlo[r], bhi = cpart + rad + nIhi[r];
-          double* bo = bx + (size_t)(step + 1) * ns * 2;
-          bo[r * 2 + 0] = blo;
-          bo[r * 2 + 1] = bhi;
+          if (bx) {
+            double* bo = bx + (size_t)(step + 1) * ns * 2;
+            bo[r * 2 + 0] = blo;
+            bo[r * 2 + 1] = bhi;
+          }
           if (!(fabs(blo) < INFINITY) || !(fabs(bhi) < INFINITY)) atomicOr(&S.misc[1], DR_RES_NONFINITE);
         }
         if (lane == 0) sc.rows[(size_t)s * 8 + (L - 1)] += ns;
       }
+}
+
+// ---------------------------------------------------------------------------
+// Two workgroups per CU for the FP32 reach of 64- and 96-wide networks: the register
+// budget of 256 costs a few spills there and doubles the boxes in flight (measured);
+// wider or FP64 instances keep one.
+template <typename T, int NT> constexpr int reach_waves_per_eu() { return sizeof(T) == 4 && (NT == 4 || NT == 6) ? 2 : 1; }
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(reach_waves_per_eu<T, NT>())))
+k_reach_dt(const NetDev* __restrict__ nets, int net_index, ReachArgs ra) {
+  extern __shared__ __align__(16) char lds_raw[];
+  const NetDev& net = nets[net_index];
+  const Scratch& sc = ra.sc;
+  const int L = net.L, Hp = net.Hp;
+  const int wid_ = threadIdx.x >> 6;
+  // dynamic LDS: per-wave chain stages, the subdomain state, then the TM state
+  char* stage = lds_raw + (size_t)wid_ * stage_bytes<T, NT>();
+  char* lds_base = lds_raw + kWavesPerWG * stage_bytes<T, NT>();
+  SubLds<T> S;
+  S.carve(lds_base, Hp, NT);
+  T* lds_b = (T*)(lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds);
+  stage_biases<T, T>(net, lds_b);
+  // TM state after the SubLds block: c[16], P[16*16], Ilo[16], Ihi[16], plus the next state
+  // (offsets stay on the LDS base pointer so that every access is an LDS access)
+  double* tm = (double*)(lds_base + ((SubLds<T>::bytes(Hp, NT) + 64 + 15) & ~(size_t)15));
+  double* c = tm;            // 16
+  double* Pm = tm + 16;      // 256 (row-major n x n)
+  double* Ilo = tm + 272;    // 16
+  double* Ihi = tm + 288;    // 16
+  double* Xab = tm + 304;    // 16: bound on |x_m| over the TM
+  double* nc = tm + 320;     // next state
+  double* nP = tm + 336;
+  double* nIlo = tm + 592;
+  double* nIhi = tm + 608;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, gq = lane >> 4;
+  const int cnt = batch_count(sc, net_index);
+  const int n0 = net.n[0], ns = net.n_state, H = ra.horizon;
+
+  bool first = true;
+  for (;;) {
+    int item;
+    if (first) {
+      first = false;
+      item = blockIdx.x;
+    } else {
+      if (tid == 0) S.misc[0] = (int)gridDim.x + (int)atomicAdd(ra.queue, 1u);
+      lds_barrier();
+      item = S.misc[0];
+      lds_barrier();
+    }
+    if (item >= cnt) break;
+    const int s = subdomain_of(sc, net_index, item);
+    double* bx = ra.boxes + (size_t)s * (H + 1) * ns * 2;
+    double* tb = ra.tape ? ra.tape + (size_t)s * reach_tape_doubles(H, Hp) : nullptr;
+    // TM normalisation of the state box: c = centre, P = diag(radius), I = [0, 0]; the
+    // exogenous inputs (network inputs ns..n0-1) enter each step as points
+    if (tid < 16) {
+      double cc = tid < ns ? ra.batch.xc[(size_t)s * n0 + tid] : 0.0;
+      double rr = tid < ns ? ra.batch.xr[(size_t)s * n0 + tid] : 0.0;
+      c[tid] = cc; Ilo[tid] = 0.0; Ihi[tid] = 0.0;
+      if (tid < ns) { bx[tid * 2 + 0] = cc - rr; bx[tid * 2 + 1] = cc + rr; }
+    }
+    for (int e = tid; e < 256; e += kWG) {
+      int a = e >> 4, b = e & 15;
+      Pm[e] = (a == b && a < ns) ? ra.batch.xr[(size_t)s * n0 + a] : 0.0;
+    }
+    for (int p = tid; p < Hp; p += kWG) S.slot[p] = -1;
+    if (tid == 0) S.misc[1] = 0;
+    if (tid < 8) sc.rows[(size_t)s * 8 + tid] = 0;
+    lds_barrier();
+    for (int step = 0; step < H; ++step) {
+      // |x_m| bound over the TM, and the input-centre/radius for the layer-1 bounds
+      if (tid < 16) {
+        if (tid >= ns && tid < n0) c[tid] = ra.u[((size_t)s * H + step) * (n0 - ns) + (tid - ns)];
+        double a = fabs(c[tid]) + fmax(fabs(Ilo[tid]), fabs(Ihi[tid]));
+        for (int z = 0; z < n0; ++z) a += fabs(Pm[tid * 16 + z]);
+        Xab[tid] = tid < n0 ? a : 0.0;
+        S.xc[tid] = 0.0; S.xr[tid] = 0.0;
+      }
+      lds_barrier();
+      if (tb) {
+        double* tt = tb + reach_tape_tm(step);
+        for (int e = tid; e < kTmDoubles; e += kWG) tt[e] = tm[e];
+      }
+      tm_crown_step<T, NT>(net, sc, S, stage, lds_b, tm, tb, step, H, s, bx);
       lds_barrier();
       if (tid < 16) {
         c[tid] = tid < ns ? nc[tid] : 0.0;

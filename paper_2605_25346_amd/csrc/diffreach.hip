@@ -78,6 +78,9 @@ struct dr_ctx {
   const void* rg_fn = nullptr;      // k_reach_grad instance (same contexts), its LDS and full grid
   size_t rg_lds = 0;
   int rg_grid = 0;
+  const void* ct_fn = nullptr;      // k_reach_ct instance (the context's network as a CT controller)
+  size_t ct_lds = 0;
+  int ct_grid = 0;
   std::string err;
 };
 
@@ -559,6 +562,17 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       c->rg_grid = persistent_grid(c, c->rg_fn, c->rg_lds, Q_REACH);
     } else {
       c->rg_fn = nullptr;
+    }
+    // the CT closed loop: the stepwise reach's on-chip state plus the flowpipe's
+    c->ct_fn = kernel_for(c, DR_KIND_CT, nd.NT, 0);
+    c->ct_lds = lds_bytes(c, Q_REACH, nd) - (size_t)nd.Hp * tsz + (((size_t)nd.Hp * tsz + 15) & ~(size_t)15) +
+                dr::CtLds::bytes();
+    if (c->ct_fn && c->ct_lds <= kMaxLds) {
+      if ((e = hipFuncSetAttribute(c->ct_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->ct_lds)) != hipSuccess)
+        return bail(hip_fail(c, e, "hipFuncSetAttribute"));
+      c->ct_grid = persistent_grid(c, c->ct_fn, c->ct_lds, Q_REACH);
+    } else {
+      c->ct_fn = nullptr;
     }
   }
   if (n_nets > 1) {
@@ -1052,6 +1066,88 @@ dr_status dr_reach_dt(dr_ctx* c, const dr_batch* b, int horizon, double* boxes, 
 dr_status dr_reach_dt_exo(dr_ctx* c, const dr_batch* b, int horizon, const double* u, double* boxes, uint32_t* status,
                           hipStream_t stream) {
   return reach(c, b, horizon, u, boxes, status, stream);
+}
+
+// ---- continuous time ------------------------------------------------------------
+static dr_status check_ct(dr_ctx* c, const dr_ct_field* f, const dr_ct_options* o) {
+  if (!f || !o) return fail(c, DR_EINVAL, "field or options is NULL");
+  if (f->n < 1 || f->n > dr::kCtMax) return fail(c, DR_ESHAPE, "the CT state dimension n must be in 1..16");
+  if (f->n_u < 0 || f->n_u > dr::kCtMax) return fail(c, DR_ESHAPE, "the CT input dimension n_u must be in 0..16");
+  if (!f->a || !f->F) return fail(c, DR_EINVAL, "the field's a and F are required");
+  if ((f->n_u > 0) != (f->G != nullptr)) return fail(c, DR_EINVAL, "G is required exactly when n_u > 0");
+  if (!(o->h > 0.0) || !std::isfinite(o->h)) return fail(c, DR_EINVAL, "h must be positive and finite");
+  if (o->steps < 1 || o->intervals < 0 || (long long)o->steps * o->intervals > 100000)
+    return fail(c, DR_EINVAL, "steps >= 1, intervals >= 0 and steps * intervals <= 100000 are required");
+  if (o->tries < 1 || o->tries > 1000 || o->rounds < 0 || o->rounds > 100)
+    return fail(c, DR_EINVAL, "tries must be in 1..1000 and rounds in 0..100");
+  if (!(o->eps > 0.0) || !std::isfinite(o->eps)) return fail(c, DR_EINVAL, "eps must be positive and finite");
+  return DR_OK;
+}
+
+static dr::CtArgs ct_args(const dr_ct_field* f, const dr_ct_options* o, double* boxes, double* segs, uint32_t* status) {
+  dr::CtArgs ca{};
+  ca.dyn.n = f->n; ca.dyn.n_u = f->n_u;
+  ca.dyn.a = f->a; ca.dyn.F = f->F; ca.dyn.G = f->G; ca.dyn.Q = f->Q;
+  ca.h = o->h; ca.K = o->steps; ca.n_ctl = o->intervals;
+  ca.tries = o->tries; ca.rounds = o->rounds; ca.eps = o->eps;
+  ca.boxes = boxes; ca.segs = segs; ca.status = status;
+  return ca;
+}
+
+dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* o, int n_sub, const double* xc, const double* xr,
+                         double* boxes, double* segs, uint32_t* status, hipStream_t stream) {
+  dr_status st = check_ct(nullptr, f, o);
+  if (st != DR_OK) return st;
+  if (f->n_u != 0) return fail(nullptr, DR_EINVAL, "dr_flowpipe_ct takes a field without an input (n_u = 0)");
+  if (n_sub < 0) return fail(nullptr, DR_EINVAL, "n_sub must be >= 0");
+  if (n_sub == 0) return DR_OK;
+  if (!xc || !xr || !boxes) return fail(nullptr, DR_EINVAL, "x_center, x_radius and boxes are required");
+  dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
+  ca.batch.n_sub = n_sub; ca.batch.xc = xc; ca.batch.xr = xr;
+  int dev = 0, cus = 0, nb = 0;
+  hipError_t e;
+  if ((e = hipGetDevice(&dev)) != hipSuccess ||
+      (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return hip_fail(nullptr, e, "device query");
+  const size_t lds = dr::CtLds::bytes();
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)dr::k_flowpipe_ct, 64, lds) != hipSuccess || nb < 1)
+    nb = 1;
+  const int grid = (int)std::min<long long>((long long)nb * std::max(cus, 1), n_sub);
+  hipLaunchKernelGGL(dr::k_flowpipe_ct, dim3(grid), dim3(64), lds, stream, ca);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(nullptr, e, "kernel launch");
+  return DR_OK;
+}
+
+dr_status dr_reach_ct(dr_ctx* c, const dr_ct_field* f, const dr_ct_options* o, const dr_batch* b, double* boxes,
+                      double* segs, uint32_t* status, hipStream_t stream) {
+  if (!c) return fail(nullptr, DR_EINVAL, "ctx is NULL");
+  dr_status st = check_ct(c, f, o);
+  if (st != DR_OK) return st;
+  if (!c->closed || c->has_spec || c->n_nets != 1)
+    return fail(c, DR_EINVAL, "reach_ct needs a context with one closed-loop network and no spec");
+  const dr::NetDev& nd = c->hnet[0];
+  if (f->n_u < 1) return fail(c, DR_EINVAL, "reach_ct needs a field with an input (n_u >= 1)");
+  if (nd.n[0] != f->n || nd.n_state != f->n_u)
+    return fail(c, DR_ESHAPE, "the controller context needs n_0 = n (the state) and n_state = n_u (its outputs)");
+  if ((st = check_batch(c, b)) != DR_OK) return st;
+  if (b->split_ptr) return fail(c, DR_EINVAL, "reach_ct takes no split constraints");
+  if (!boxes) return fail(c, DR_EINVAL, "boxes is NULL");
+  if (!c->ct_fn) return fail(c, DR_ESHAPE, "no kernel instance for this width, or its on-chip state does not fit");
+  c->batch.n_sub = b->n_sub;
+  c->batch.net_id = b->net_id;
+  c->batch.xc = b->x_center;
+  c->batch.xr = b->x_radius;
+  c->batch.sptr = nullptr;
+  c->batch.spk = nullptr;
+  c->have_batch = false;  // bound_init state is not valid for this batch
+  c->fused_ready = false;
+  c->sc.n_sub = b->n_sub;
+  if (b->n_sub == 0) return DR_OK;
+  dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
+  ca.batch = c->batch; ca.sc = c->sc; ca.sc.st_out = nullptr;
+  int net_index = 0;
+  void* args[] = {&c->dnet, &net_index, &ca};
+  return launch(c, c->ct_fn, std::min(c->ct_grid, b->n_sub), c->ct_lds, args, stream);
 }
 
 dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {

@@ -9,7 +9,8 @@ enum {
   DR_KIND_REACH = 3,   // k_reach_dt
   DR_KIND_PGRAD = 4,   // k_final, dual adjoint with parameter-gradient tapes (variant 1: item copy)
   DR_KIND_JOINT = 5,   // k_reach_joint (CROWN through the unrolled closed loop)
-  DR_KIND_RGRAD = 6    // k_reach_grad (reverse pass through the stepwise reach)
+  DR_KIND_RGRAD = 6,   // k_reach_grad (reverse pass through the stepwise reach)
+  DR_KIND_CT = 7       // k_reach_ct (continuous-time closed loop with the controller of the context)
 };
 
 #define DR_DECLARE_INSTANCE(T, NT) const void* dr_instance_##T##_##NT(int kind, int variant);

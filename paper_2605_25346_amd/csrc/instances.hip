@@ -6,6 +6,7 @@
 #include "bound_kernels.hpp"
 #include "joint_kernels.hpp"
 #include "grad_kernels.hpp"
+#include "ct_kernels.hpp"
 #include "instances.h"
 
 #ifndef DR_T
@@ -45,6 +46,7 @@ const void* DR_CAT(dr_instance_, DR_T, DR_NT)(int kind, int variant) {
       return variant ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
     case DR_KIND_JOINT: return variant ? nullptr : (const void*)&dr::k_reach_joint<T, NT>;
     case DR_KIND_RGRAD: return variant ? nullptr : (const void*)&dr::k_reach_grad<T, NT>;
+    case DR_KIND_CT: return variant ? nullptr : (const void*)&dr::k_reach_ct<T, NT>;
     default: return nullptr;
   }
 }

@@ -35,6 +35,9 @@ def test_struct_layouts():
     assert ctypes.sizeof(binding.dr_network) == 80
     assert ctypes.sizeof(binding.dr_batch) == 48
     assert ctypes.sizeof(binding.dr_options) == 28
+    # dr_ct_field: int, int, 4 ptr; dr_ct_options: double, 4 int, double
+    assert ctypes.sizeof(binding.dr_ct_field) == 40
+    assert ctypes.sizeof(binding.dr_ct_options) == 32
 
 
 def test_last_error_without_context():
@@ -67,3 +70,35 @@ def test_null_context_is_rejected_before_any_device_call():
     assert lib.dr_reach_dt_grad(N, N, 1, N, N, N, N, N, N, N, N, N, N, N, 0, N, N) == binding.DR_EINVAL
     assert lib.dr_reach_grad_workspace(N, 4, 2) == 0
     assert lib.dr_hidden_max(N) == 0 and lib.dr_spec_rows(N) == 0
+    assert lib.dr_reach_ct(N, N, N, N, N, N, N, N) == binding.DR_EINVAL
+
+
+def test_ct_arguments_are_checked_before_any_device_call():
+    """dr_flowpipe_ct validates the field and the options on the host (the device
+    pointers are only passed on, never read here)."""
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("library not built")
+    lib = binding.load()
+    fake = 0x1000
+    f = binding.dr_ct_field(n=3, n_u=0, a=fake, F=fake, G=None, Q=None)
+    o = binding.dr_ct_options(h=0.1, steps=2, intervals=1, tries=40, rounds=3, eps=1e-9)
+    call = lambda f, o: lib.dr_flowpipe_ct(ctypes.byref(f), ctypes.byref(o), 0, None, None, None, None, None, None)
+    assert lib.dr_flowpipe_ct(None, None, 0, None, None, None, None, None, None) == binding.DR_EINVAL
+    assert call(f, o) == binding.DR_OK                       # an empty batch launches nothing
+    bad = [("h", -1.0, binding.DR_EINVAL), ("h", float("inf"), binding.DR_EINVAL), ("steps", 0, binding.DR_EINVAL),
+           ("intervals", -1, binding.DR_EINVAL), ("tries", 0, binding.DR_EINVAL), ("rounds", 101, binding.DR_EINVAL),
+           ("eps", 0.0, binding.DR_EINVAL)]
+    for name, v, want in bad:
+        o2 = binding.dr_ct_options(h=0.1, steps=2, intervals=1, tries=40, rounds=3, eps=1e-9)
+        setattr(o2, name, v)
+        assert call(f, o2) == want, name
+        assert name.encode() in lib.dr_last_error(None)
+    for kw, want in ((dict(n=17), binding.DR_ESHAPE), (dict(n=0), binding.DR_ESHAPE), (dict(n_u=1), binding.DR_EINVAL),
+                     (dict(F=None), binding.DR_EINVAL)):
+        f2 = binding.dr_ct_field(n=3, n_u=0, a=fake, F=fake, G=None, Q=None)
+        for k, v in kw.items():
+            setattr(f2, k, v)
+        assert call(f2, o) == want, kw
+    f3 = binding.dr_ct_field(n=3, n_u=1, a=fake, F=fake, G=fake, Q=None)
+    assert call(f3, o) == binding.DR_EINVAL                  # the flowpipe takes no input
+    assert b"n_u = 0" in lib.dr_last_error(None)

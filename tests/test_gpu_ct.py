@@ -1,0 +1,215 @@
+"""Parity of the continuous-time entry points (dr_flowpipe_ct, dr_reach_ct) with the
+oracle ``oracle/ct.py``, through the C-ABI.
+
+Both sides compute in FP64 and take the same steps; they differ in the order of the sums
+of the TM arithmetic, in the inversion of the linear part (Gauss-Jordan on the device,
+LAPACK on the host) and, in the closed loop, by the rounding margins of the controller's
+CROWN chains.  Tolerance: 1e-9 relative to max(1, |b|) for every time-point and segment
+box with an FP64 controller (margins on or off); 1e-4 with an FP32 controller without
+margins (chains on FP32 matrix cores, bounds within 1e-5 of FP64 at each control
+boundary and carried through the flow).  An FP32 controller with rigorous margins widens
+the input's interval by the a priori rounding bound of its chains, which the closed loop
+feeds back into the state: there sampled zero-order-hold trajectories must stay inside
+every box, and the gap to the oracle is printed.  Status bits (whether every step found
+a validated remainder) are compared exactly; after a failed step only the non-finite
+pattern is compared.
+"""
+import numpy as np
+import pytest
+
+from oracle import ct, exact
+from paper_2605_25346_amd.workloads import Network, make_network
+from tests.gpu_helpers import rel_gap, require_gpu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-9, 1e-4
+
+
+def _field(f):
+    from paper_2605_25346_amd.api import CtField
+    return CtField(f.a, f.F, f.G if f.G.shape[1] else None, f.Q)
+
+
+def _lv():
+    Q = np.zeros((2, 2, 2)); Q[0, 0, 1] = -0.5; Q[1, 0, 1] = 0.25
+    return ct.QuadDynamics(np.zeros(2), np.array([[1.0, 0.0], [0.0, -0.75]]), Q=Q)
+
+
+def _quad(rng, n, n_u=0, q=0.1):
+    F = rng.normal(0, 0.5, (n, n)) - np.eye(n)
+    G = rng.normal(0, 0.5, (n, n_u)) if n_u else None
+    Q = rng.normal(0, q, (n, n, n)) if q else None
+    return ct.QuadDynamics(rng.normal(0, 0.1, n), F, G, Q)
+
+
+def _boxes(rng, S, n, centre=0.5, radius=(0.01, 0.05)):
+    return rng.uniform(-centre, centre, (S, n)), rng.uniform(*radius, (S, n))
+
+
+def _compare(tag, got, ref, tol):
+    """got/ref: (boxes, segs) per box; returns the max gap over finite entries."""
+    worst = 0.0
+    for g, r in zip(got, ref):
+        fin = np.isfinite(r)
+        assert np.array_equal(fin, np.isfinite(g)), tag
+        if fin.any():
+            worst = max(worst, float(rel_gap(g[fin], r[fin]).max()))
+    print(f"[ct {tag}] max gap {worst:.2e}", flush=True)
+    assert worst <= tol, (tag, worst)
+    return worst
+
+
+def _flowpipe_case(tag, f, xc, xr, h, steps, intervals=1):
+    from paper_2605_25346_amd.api import dr_flowpipe_ct
+    require_gpu()
+    print(f"[ct {tag}] flowpipe n={f.n} S={len(xc)} N={steps * intervals} h={h}", flush=True)
+    boxes, segs, st = dr_flowpipe_ct(_field(f), xc, xr, h, steps, intervals)
+    torch.cuda.synchronize()
+    boxes, segs, st = boxes.cpu().numpy(), segs.cpu().numpy(), st.cpu().numpy()
+    ref = [ct.flowpipe(f, xc[s], xr[s], h, steps * intervals) for s in range(len(xc))]
+    for s, (p, g, ok) in enumerate(ref):
+        assert (st[s] == 0) == ok, (tag, s, st[s], ok)
+    _compare(tag + " points", boxes, [r[0] for r in ref], TOL64)
+    _compare(tag + " segments", segs, [r[1] for r in ref], TOL64)
+    return st
+
+
+def test_flowpipe_lotka_volterra():
+    rng = np.random.default_rng(10)
+    xc = np.array([[2.0, 1.0], [1.5, 0.8], [2.5, 1.2], [1.0, 1.0], [2.2, 0.6]])
+    xr = rng.uniform(0.01, 0.06, (5, 2))
+    st = _flowpipe_case("lv", _lv(), xc, xr, 0.02, 50)
+    assert np.all(st == 0)
+
+
+def test_flowpipe_random_quadratic_ragged_batch():
+    rng = np.random.default_rng(11)
+    f = _quad(rng, 6)
+    xc, xr = _boxes(rng, 37, 6)
+    st = _flowpipe_case("quad6", f, xc, xr, 0.02, 10, 3)
+    assert np.all(st == 0)
+
+
+def test_flowpipe_linear_max_dimension_and_constant():
+    rng = np.random.default_rng(12)
+    f = _quad(rng, 16, q=0)
+    xc, xr = _boxes(rng, 3, 16)
+    _flowpipe_case("lin16", f, xc, xr, 0.01, 20)
+    fc = ct.QuadDynamics(np.array([0.3, -0.2, 1.0]), np.zeros((3, 3)))
+    xc, xr = _boxes(rng, 2, 3)
+    _flowpipe_case("const3", fc, xc, xr, 0.1, 5)
+
+
+def test_flowpipe_blow_up_reports_unbounded():
+    """x' = x^2 from x0 in [1.9, 2.1] leaves every bounded set before t = 1/2.1: the
+    first step without a validated remainder and every box after it are unbounded on
+    both sides, with the status bit set."""
+    Q = np.zeros((1, 1, 1)); Q[0, 0, 0] = 1.0
+    f = ct.QuadDynamics(np.zeros(1), np.zeros((1, 1)), Q=Q)
+    st = _flowpipe_case("blowup", f, np.array([[2.0], [0.5]]), np.array([[0.1], [0.01]]), 0.2, 4)
+    assert st[0] != 0 and st[1] == 0
+
+
+def test_flowpipe_empty_batch_and_argument_errors():
+    from paper_2605_25346_amd.api import CtField, dr_flowpipe_ct
+    from paper_2605_25346_amd.binding import DrError
+    require_gpu()
+    f = _lv()
+    boxes, segs, st = dr_flowpipe_ct(_field(f), np.zeros((0, 2)), np.zeros((0, 2)), 0.1, 3)
+    assert boxes.shape == (0, 4, 2, 2) and st.numel() == 0
+    with pytest.raises(DrError, match="h must be"):
+        dr_flowpipe_ct(_field(f), np.ones((1, 2)), np.ones((1, 2)), 0.0, 3)
+    rng = np.random.default_rng(0)
+    g = _quad(rng, 3, n_u=1)
+    with pytest.raises(DrError, match="without an input"):
+        dr_flowpipe_ct(CtField(g.a, g.F, g.G, g.Q), np.ones((1, 3)), np.ones((1, 3)), 0.1, 3)
+
+
+def _controller_ctx(net, precision, S, margins=True):
+    from paper_2605_25346_amd.api import BoundContext
+    n_u, n = net.widths[-1], net.widths[0]
+    loop = Network(net.Ws, net.bs, np.zeros((n_u, n)), np.eye(n_u))
+    return BoundContext([loop], precision=precision, max_sub=max(S, 1), max_splits=0, margins=margins)
+
+
+def _closed_loop_case(tag, f, net, xc, xr, h, K, N, runs):
+    from paper_2605_25346_amd.api import DeviceBatch
+    require_gpu()
+    S = len(xc)
+    ref = [ct.closed_loop(f, net, xc[s], xr[s], h, K, N) for s in range(S)]
+    assert all(r[2] for r in ref)
+    field = _field(f)
+    for precision, margins in runs:
+        print(f"[ct {tag}] closed loop {precision} margins={margins} n={f.n} n_u={f.G.shape[1]} "
+              f"widths={net.widths} S={S} K={K} N={N}", flush=True)
+        ctx = _controller_ctx(net, precision, S, margins)
+        boxes, segs, st = ctx.dr_reach_ct(field, DeviceBatch.from_tensors(
+            torch.as_tensor(xc, device="cuda"), torch.as_tensor(xr, device="cuda")), h, K, N)
+        torch.cuda.synchronize()
+        boxes, segs, st = boxes.cpu().numpy(), segs.cpu().numpy(), st.cpu().numpy()
+        ctx.close()
+        assert np.all(st == 0), st
+        tol = TOL64 if precision == "f64" else (TOL32 if not margins else np.inf)
+        _compare(f"{tag} {precision} m={margins} points", boxes, [r[0] for r in ref], tol)
+        _compare(f"{tag} {precision} m={margins} segments", segs, [r[1] for r in ref], tol)
+        if precision == "f32" and margins:
+            for s in range(S):
+                _zoh_inside(f, net, xc[s], xr[s], h, K, N, boxes[s], seed=s)
+
+
+def _zoh_inside(f, net, xc, xr, h, K, N, pts, seed, n=12):
+    """Sampled closed-loop trajectories (controller evaluated exactly at every control
+    boundary, input held, ODE solved to 1e-11) lie inside every time-point box."""
+    from scipy.integrate import solve_ivp
+    rng = np.random.default_rng(seed)
+    for x0 in exact.sample_points(rng, xc, xr, n, corners=False):
+        x = x0.copy()
+        for i in range(N):
+            u = exact.forward(net, x[None, :])[0][0]
+            sol = solve_ivp(lambda t, z: f(z, u), (0, h * K), x, t_eval=np.linspace(0, h * K, K + 1),
+                            rtol=1e-11, atol=1e-13)
+            for j in range(K + 1):
+                b = pts[i * K + j]
+                assert np.all(sol.y[:, j] >= b[:, 0] - 1e-10) and np.all(sol.y[:, j] <= b[:, 1] + 1e-10), (i, j)
+            x = sol.y[:, -1]
+
+
+def _f32_net(rng, widths):
+    net = make_network(rng, widths, np.float64)
+    net.Ws = [W.astype(np.float32).astype(np.float64) for W in net.Ws]
+    net.bs = [b.astype(np.float32).astype(np.float64) for b in net.bs]
+    return net
+
+
+def test_closed_loop_small_controller():
+    rng = np.random.default_rng(20)
+    f = _quad(rng, 4, n_u=2)
+    net = _f32_net(rng, [4, 16, 16, 2])
+    xc, xr = _boxes(rng, 9, 4, radius=(0.01, 0.04))
+    _closed_loop_case("ctl4", f, net, xc, xr, 0.02, 5, 4,
+                      [("f64", True), ("f64", False), ("f32", True), ("f32", False)])
+
+
+def test_closed_loop_12d_controller_64x64():
+    rng = np.random.default_rng(21)
+    f = _quad(rng, 12, n_u=4, q=0.03)
+    net = _f32_net(rng, [12, 64, 64, 4])
+    xc, xr = _boxes(rng, 5, 12, radius=(0.005, 0.02))
+    _closed_loop_case("ctl12", f, net, xc, xr, 0.02, 5, 3, [("f64", True), ("f32", False), ("f32", True)])
+
+
+def test_closed_loop_argument_errors():
+    from paper_2605_25346_amd.api import DeviceBatch
+    from paper_2605_25346_amd.binding import DrError
+    require_gpu()
+    rng = np.random.default_rng(22)
+    f = _quad(rng, 4, n_u=2)
+    net = make_network(rng, [4, 16, 16, 3], np.float64)   # three outputs, two inputs in f
+    ctx = _controller_ctx(net, "f64", 2)
+    b = DeviceBatch.from_tensors(torch.zeros(2, 4, dtype=torch.float64, device="cuda"),
+                                 torch.full((2, 4), 0.1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(DrError, match="n_state = n_u"):
+        ctx.dr_reach_ct(_field(f), b, 0.02, 2, 2)
+    ctx.close()
