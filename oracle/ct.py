@@ -16,7 +16,9 @@ generators y in [-1, 1]^m of the step's initial set and the time s in [0, h],
 i.e. c + A z + B s z with z = (y, s).  Readings where the paper is silent:
   * dynamics: polynomial of degree <= 2 in the state and affine in the input,
     f_i(x, u) = a_i + F_i x + G_i u + x^T Q_i x (the TM arithmetic of a product is
-    exact up to the monomials outside the representation, which are bounded);
+    exact up to the monomials outside the representation, which are bounded); the
+    quadratic form is taken over its monomials x_j x_k, j <= k (coefficients
+    Q_ijk + Q_ikj off the diagonal), one TM product per monomial;
   * Picard (polynomial part, order k = 2): g_0 = c + S y, g_{j+1} = Trunc(x_0 +
     int_0^s f(g_j)); Trunc keeps the monomials {1, y, s, s y, s^2};
   * remainder (validation): with x_0 = c + S y + r_0, r_0 in I_0, the Picard image of
@@ -187,11 +189,13 @@ class QuadDynamics:
         out = QTM.const(self.a, m) + X.linmap(self.F)
         if self.G.shape[1]:
             out = out + U.linmap(self.G)
-        # quadratic terms: sum_jk Q_ijk x_j x_k, formed as products of component TMs
+        # quadratic terms: sum_jk Q_ijk x_j x_k = sum_{j <= k} Qs_ijk x_j x_k over the
+        # monomials x_j x_k (Qs_ijk = Q_ijk + Q_ikj for j < k, Q_ijj on the diagonal),
+        # each formed once as a product of component TMs
         for j in range(n):
-            for k in range(n):
-                q = self.Q[:, j, k]
-                if not np.any(q):
+            for k in range(j, n):
+                q = self.Q[:, j, k] + (self.Q[:, k, j] if k != j else 0.0)
+                if not (np.any(self.Q[:, j, k]) or np.any(self.Q[:, k, j])):
                     continue
                 xj = _pick(X, j, n); xk = _pick(X, k, n)
                 out = out + qtm_mul(xj, xk, h).scale_rows(q)
