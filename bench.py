@@ -44,6 +44,7 @@ def kernel_src_sha():
             h.update(fh.read())
     return h.hexdigest()[:16]
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
+PEAK_VALU_F64 = 78.6                          # MI355X FP64 vector peak (TFLOP/s)
 PEAK_HBM_GBS = 8000.0
 
 
@@ -398,6 +399,78 @@ def reach_gradient(torch, args, precision="f32", n_boxes=128):
     return res
 
 
+# FP64 operations of the quasi-quadratic TM arithmetic (hand count of the definitions;
+# FMA = 2, min/max = 1, |.| free): the product of two scalar models truncated to the
+# representation (kept monomials, the dropped ones and the interval parts bounded), and
+# one model scaled and accumulated (its 35 coefficients and the interval part).
+CT_PROD_FLOPS, CT_AXPY_FLOPS = 540, 74
+
+
+def ct_step_flops(F, G, Q, rounds=3):
+    """Algorithmic FP64 operations of one flowpipe step of one box (Theorem "TM flowpipe
+    step via Picard iteration" with order 2): 2 Picard iterations, one validating image
+    of the remainder and `rounds` refinements, each an evaluation of f over the models
+    (every distinct quadratic product X_j X_k once, then the sums of F, G and Q terms
+    per component), plus per image the subtraction of d/ds p and the range (84 per
+    component), the step-end model, and the preconditioning (Gauss-Jordan inversion
+    4 n^3, its check 2 n^3, the column scales and the input update)."""
+    n = F.shape[0]
+    n_u = G.shape[1] if G is not None else 0
+    pairs = {(min(j, k), max(j, k)) for (_, j, k) in zip(*np.nonzero(Q))} if Q is not None else set()
+    nnz = np.count_nonzero(F) + (np.count_nonzero(G) if G is not None else 0) + (np.count_nonzero(Q) if Q is not None else 0)
+    f_eval = len(pairs) * CT_PROD_FLOPS + nnz * CT_AXPY_FLOPS
+    images = 1 + rounds
+    return ((2 + images) * f_eval + images * 84 * n + 2 * 35 * n + 35 * n
+            + 6 * n ** 3 + 2 * n_u * n * n + 4 * n * n)
+
+
+def ct_reach(torch, args, n_sub=4096):
+    """The CT closed loop of the paper's quadrotor shape (12 states, 4 inputs, a 64x64
+    controller certified every 5 flowpipe steps of 0.02, 100 steps) on a batch of
+    initial boxes, and the open-loop flowpipe of the same field: box-steps per second
+    and the achieved FP64 rate of the flowpipe arithmetic against the vector FP64 peak
+    (the controller's CROWN chain FLOPs are counted separately)."""
+    from paper_2605_25346_amd.api import BoundContext, CtField, DeviceBatch, dr_flowpipe_ct
+    from paper_2605_25346_amd.workloads import Network, make_ct_workload
+    wl = make_ct_workload(n_sub=n_sub)
+    S, n, N = n_sub, wl.F.shape[0], wl.K * wl.N_ctl
+    n_u = wl.G.shape[1]
+    ctl = wl.controller
+    loop = Network(ctl.Ws, ctl.bs, np.zeros((n_u, n)), np.eye(n_u))
+    ctx = BoundContext([loop], precision="f32", max_sub=S)
+    field = CtField(wl.a, wl.F, wl.G, wl.Q)
+    field0 = CtField(wl.a, wl.F, None, wl.Q)
+    xc = torch.as_tensor(wl.x_center, dtype=torch.float64, device="cuda")
+    xr = torch.as_tensor(wl.x_radius, dtype=torch.float64, device="cuda")
+    db = DeviceBatch.from_tensors(xc, xr)
+    f64 = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+    out = (f64(S, N + 1, n, 2), f64(S, N, n, 2), torch.zeros(S, dtype=torch.int32, device="cuda"))
+    out0 = (f64(S, N + 1, n, 2), f64(S, N, n, 2), torch.zeros(S, dtype=torch.int32, device="cuda"))
+    reps = max(2, args.steps // 10)
+    ms_c, _ = time_graph(torch, lambda: ctx.dr_reach_ct(field, db, wl.h, wl.K, wl.N_ctl, out=out), reps, 1)
+    rows = ctx.dr_get_rows().cpu().numpy()
+    ms_f, _ = time_graph(torch, lambda: dr_flowpipe_ct(field0, xc, xr, wl.h, N, out=out0), reps, 1)
+    torch.cuda.synchronize()
+    st_c, st_f = out[2].cpu().numpy(), out0[2].cpu().numpy()
+    w = ctl.widths
+    L = len(w) - 1
+    ctl_flops = sum(int(rows[:, k - 1].sum()) * chain_flops_per_row(w, k) for k in range(2, L))
+    ctl_flops += int(rows[:, L - 1].sum()) * final_flops_per_row(w)
+    flow_c = S * N * ct_step_flops(wl.F, wl.G, wl.Q)
+    flow_f = S * N * ct_step_flops(wl.F, None, wl.Q)
+    width = lambda b: float(np.median((b[:, -1, :, 1] - b[:, -1, :, 0]).sum(axis=1)))
+    res = dict(S=S, steps=N, h=wl.h, K=wl.K, ms_closed_loop=ms_c, ms_flowpipe=ms_f,
+               box_steps_per_s=S * N / (ms_c * 1e-3), flowpipe_box_steps_per_s=S * N / (ms_f * 1e-3),
+               closed_loop_ok=int((st_c == 0).sum()), flowpipe_ok=int((st_f == 0).sum()),
+               final_width_sum_median_closed=width(out[0].cpu().numpy()),
+               final_width_sum_median_open=width(out0[0].cpu().numpy()),
+               flow_flops_per_box_step=ct_step_flops(wl.F, wl.G, wl.Q),
+               tflops_closed=(flow_c + ctl_flops) / (ms_c * 1e-3) / 1e12, ctl_chain_flops=ctl_flops,
+               tflops_flowpipe=flow_f / (ms_f * 1e-3) / 1e12)
+    ctx.close()
+    return res
+
+
 def mixed_batch(torch, args, precision="f32"):
     from paper_2605_25346_amd.api import BoundContext, DeviceBatch
     from paper_2605_25346_amd.workloads import config_workload
@@ -694,7 +767,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default="", help="comma-separated extra legs to run (for profiling one leg): "
-                    "f64,sweep,ascent,pgrad,reach,candidates,joint,reachgrad,tightness,mixed")
+                    "f64,sweep,ascent,pgrad,reach,candidates,joint,reachgrad,ct,tightness,mixed")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
@@ -791,6 +864,14 @@ def main():
         extra["reach_volume_gradient_8+4-96x3-8_S128_H10"] = dict(
             rg, roofline=dict(bound="mfma", achieved=rg["tflops"], peak=PEAK_TFLOPS["f32"], unit="TFLOP/s",
                               frac=rg["tflops"] / PEAK_TFLOPS["f32"], kernel="k_reach_dt + k_reach_grad"))
+    if leg("ct"):
+        print("bench: CT closed loop and flowpipe", file=sys.stderr, flush=True)
+        cr = ct_reach(torch, args)
+        print(f"bench: CT {cr}", file=sys.stderr, flush=True)
+        extra["ct_quadratic12+4-64x2-4_S4096_N100"] = dict(
+            cr, roofline=dict(bound="alu", achieved=cr["tflops_flowpipe"], peak=PEAK_VALU_F64, unit="TFLOP/s",
+                              frac=cr["tflops_flowpipe"] / PEAK_VALU_F64, kernel="k_flowpipe_ct",
+                              note="FP64 vector peak; closed loop: tflops_closed over both parts"))
     if leg("tightness"):
         for cfg_i, key in ((3, "equal_tightness_abcrown_8-128x4-4_vs_crown_input_splitting"),
                            (5, "equal_tightness_mixed_S16384_vs_crown_input_splitting")):

@@ -359,6 +359,8 @@ typedef struct {
  *   segments  n_sub x N K x n x 2: the box of every step's segment [t, t + h], or NULL;
  *   status    n_sub: DR_RES_* bits, or NULL.
  * Takes no context: errors are described by dr_last_error(NULL).  One wavefront per box.
+ * The quadratic form is evaluated over its monomials x_j x_k (j <= k), each Taylor-model
+ * product formed once per evaluation, with coefficient Q_ijk + Q_ikj (j < k) or Q_ijj.
  * Asynchronous on `stream`; allocates nothing. */
 dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* opt, int n_sub, const double* x_center,
                          const double* x_radius, double* boxes, double* segments, uint32_t* status,
@@ -374,8 +376,9 @@ dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* opt, int n_s
  * controller's chains run in the context's precision (rigorous margins as configured);
  * the input's model is linear over the same generators, its interval part centred.
  * Batch as for dr_reach_dt (no splits; x_center, x_radius n_sub x n); outputs as for
- * dr_flowpipe_ct; status also carries the controller step's bits.  One workgroup per
- * box.  Asynchronous on `stream`; allocates nothing. */
+ * dr_flowpipe_ct; status also carries the controller step's bits.  Up to four boxes per
+ * workgroup (one wavefront each in the flowpipe phase).  Asynchronous on `stream`;
+ * allocates nothing. */
 dr_status dr_reach_ct(dr_ctx* ctx, const dr_ct_field* f, const dr_ct_options* opt, const dr_batch* batch,
                       double* boxes, double* segments, uint32_t* status, hipStream_t stream);
 

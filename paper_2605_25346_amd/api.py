@@ -97,19 +97,25 @@ def ct_options(h, steps, intervals=1, tries=40, rounds=3, eps=1e-9) -> B.dr_ct_o
     return o
 
 
-def dr_flowpipe_ct(field: CtField, x_center, x_radius, h, steps, intervals=1, segments=True, **kw):
+def _ct_out(S, N, n, segments, dev, out):
+    if out is not None:
+        return out
+    boxes = torch.empty(S, N + 1, n, 2, dtype=torch.float64, device=dev)
+    segs = torch.empty(S, N, n, 2, dtype=torch.float64, device=dev) if segments else None
+    return boxes, segs, torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+
+
+def dr_flowpipe_ct(field: CtField, x_center, x_radius, h, steps, intervals=1, segments=True, out=None, **kw):
     """Flowpipe of x' = f(x) from the boxes [x_center - x_radius, x_center + x_radius]
     (S x n): returns (boxes S x (N K + 1) x n x 2, segments S x N K x n x 2 or None,
-    status S)."""
+    status S); `out` may give those three tensors."""
     lib = B.load()
     dev = field.F.device
     xc = torch.as_tensor(x_center, dtype=torch.float64, device=dev).contiguous()
     xr = torch.as_tensor(x_radius, dtype=torch.float64, device=dev).contiguous()
     S, n = int(xc.shape[0]), field.n
     N = int(steps) * int(intervals)
-    boxes = torch.empty(S, N + 1, n, 2, dtype=torch.float64, device=dev)
-    segs = torch.empty(S, N, n, 2, dtype=torch.float64, device=dev) if segments else None
-    status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+    boxes, segs, status = _ct_out(S, N, n, segments, dev, out)
     fs, o = field.struct(), ct_options(h, steps, intervals, **kw)
     B.check(lib.dr_flowpipe_ct(ctypes.byref(fs), ctypes.byref(o), S, _ptr(xc), _ptr(xr), _ptr(boxes), _ptr(segs),
                                _ptr(status), _stream()), None)
@@ -412,7 +418,7 @@ class BoundContext:
             dWp, dbp, _ptr(workspace), ctypes.c_size_t(workspace.numel()), _ptr(status), _stream()))
         return boxes, status[:S], grads
 
-    def dr_reach_ct(self, field: CtField, batch: DeviceBatch, h, steps, intervals, segments=True, **kw):
+    def dr_reach_ct(self, field: CtField, batch: DeviceBatch, h, steps, intervals, segments=True, out=None, **kw):
         """CT closed loop with this context's network as the controller (held over each
         control interval of `steps` flowpipe steps): returns (boxes, segments, status)
         as dr_flowpipe_ct."""
@@ -420,10 +426,7 @@ class BoundContext:
         self.generation += 1
         S, n = batch.n_sub, field.n
         N = int(steps) * int(intervals)
-        dev = self.device
-        boxes = torch.empty(S, N + 1, n, 2, dtype=torch.float64, device=dev)
-        segs = torch.empty(S, N, n, 2, dtype=torch.float64, device=dev) if segments else None
-        status = torch.zeros(max(S, 1), dtype=torch.int32, device=dev)
+        boxes, segs, status = _ct_out(S, N, n, segments, self.device, out)
         fs, o = field.struct(), ct_options(h, steps, intervals, **kw)
         b = batch.struct()
         self._batch_struct = b

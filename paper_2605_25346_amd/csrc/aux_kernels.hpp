@@ -401,24 +401,18 @@ __global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __re
 }
 
 // The flowpipe without a controller: one wavefront per box (Algorithm "Reachability of
-// CT Dynamics with TM Flowpipe").
+// CT Dynamics with TM Flowpipe"); each workgroup is one wavefront and takes boxes
+// round-robin.
 __global__ void __launch_bounds__(64) k_flowpipe_ct(CtArgs ca) {
   extern __shared__ __align__(16) char ct_raw[];
   CtLds C;
   C.carve((double*)ct_raw);
-  const int i = threadIdx.x, n = ca.dyn.n;
-  const int N = ca.n_ctl * ca.K;
+  ct_pairs(C, ca.dyn);
   for (int b = blockIdx.x; b < ca.batch.n_sub; b += gridDim.x) {
-    ct_seed(C, ca, b, n);
-    if (i < n) {
-      double lo, hi;
-      ct_point_box(C, i, lo, hi);
-      double* bo = ca.boxes + (size_t)b * (N + 1) * n * 2;
-      bo[i * 2 + 0] = lo; bo[i * 2 + 1] = hi;
-    }
+    ct_seed(C, ca, b, ca.dyn.n);
     bool ok = true;
     for (int k = 0; k < ca.n_ctl; ++k) ok = ct_steps(C, ca, false, b, k * ca.K) && ok;
-    if (i == 0 && ca.status) ca.status[b] = ok ? 0u : (uint32_t)DR_RES_NONFINITE;
+    if (threadIdx.x == 0 && ca.status) ca.status[b] = ok ? 0u : (uint32_t)DR_RES_NONFINITE;
     ct_sync();
   }
 }

@@ -5,18 +5,20 @@
 //
 // A model is the quasi-quadratic form of Section "Representation of Reachable Sets" over
 // the generators y in [-1, 1]^m (m <= 16) of the box and the time s in [0, h]:
-//     X(y, s) = c + L y + l s + s (M y) + w s^2  (+)  [lo, hi],
-// one component per lane of the first wavefront (component-parallel; n <= 16).
-// Dynamics: f_i(x, u) = a_i + F_i x + G_i u + x^T Q_i x (degree <= 2 in the state, affine
-// in the held input u).  Products keep the monomials {1, y, s, s y, s^2} and bound every
-// other one over the domain into the interval part.  The step: two Picard iterations of
-// the polynomial part from the seed c + S y; the remainder J validated by the Picard
-// image J' = I_0 + hull(0, h range(f(p + J) - d/ds p)) inside J (widening while not),
-// then refined; the step-end model c + l h + w h^2 + (L + h M) y (+) J; the remainder is
-// then absorbed into the linear part (S <- S diag(1 + |S^-1| rad J), centre += mid J)
-// when S is well conditioned, and a held input's model follows the change of generators.
-// Arithmetic is FP64 without outward rounding (the rounding of these steps is not
-// covered by a margin).
+//     X(y, s) = c + L y + l s + s (M y) + w s^2  (+)  [lo, hi].
+// One wavefront carries one box: lane i < n owns state component i (component-parallel,
+// n <= 16).  Dynamics: f_i(x, u) = a_i + F_i x + G_i u + x^T Q_i x (degree <= 2 in the
+// state, affine in the held input u).  A product keeps the monomials {1, y, s, s y, s^2}
+// and bounds every other one over the domain into the interval part.  Each evaluation of
+// f first forms every distinct quadratic monomial X_j X_k (j <= k) once, one per lane in
+// chunks of kCtChunk, then every component sums its terms (coefficient Q_ijk + Q_ikj off
+// the diagonal).  The step: two Picard iterations of the polynomial part from the seed
+// c + S y; the remainder J validated by the Picard image J' = I_0 + hull(0, h range(
+// f(p + J) - d/ds p)) inside J (widening while not), then refined; the step-end model
+// c + l h + w h^2 + (L + h M) y (+) J; the remainder is then absorbed into the linear part
+// (S <- S diag(1 + |S^-1| rad J), centre += mid J) when S is well conditioned, and a held
+// input's model follows the change of generators.  Arithmetic is FP64 without outward
+// rounding (the rounding of these steps is not covered by a margin).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -26,13 +28,15 @@
 namespace dr {
 
 constexpr int kCtMax = 16;
+constexpr int kCtChunk = 32;                               // monomials formed per pass
+constexpr int kCtPairs = kCtMax * (kCtMax + 1) / 2;        // distinct monomials x_j x_k
 
 // One component of a model in registers.
 struct QT {
   double c, L[kCtMax], l, M[kCtMax], w, lo, hi;
 };
 
-// A vector of models in LDS (structure of arrays, component-major 16 x 16 matrices).
+// A vector of `cap` models in LDS (structure of arrays; L and M are cap x 16).
 struct QTL {
   double* c;
   double* L;
@@ -41,10 +45,10 @@ struct QTL {
   double* w;
   double* lo;
   double* hi;
-  __host__ __device__ static size_t bytes() { return (size_t)(5 * kCtMax + 2 * kCtMax * kCtMax) * sizeof(double); }
-  __device__ void carve(double* base) {
-    c = base; L = c + kCtMax; l = L + kCtMax * kCtMax; M = l + kCtMax; w = M + kCtMax * kCtMax;
-    lo = w + kCtMax; hi = lo + kCtMax;
+  __host__ __device__ static constexpr size_t bytes(int cap) { return (size_t)(5 * cap + 2 * cap * kCtMax) * sizeof(double); }
+  __device__ void carve(double* base, int cap) {
+    c = base; L = c + cap; l = L + cap * kCtMax; M = l + cap; w = M + cap * kCtMax;
+    lo = w + cap; hi = lo + cap;
   }
 };
 
@@ -68,13 +72,19 @@ __device__ __forceinline__ QT qt_zero() {
   return q;
 }
 
-// Range of the polynomial part over y in [-1, 1]^m, s in [0, h] (term by term).
+// Range of the polynomial part over y in [-1, 1]^m, s in [0, h] (term by term), from
+// the constant, the absolute sums of L and M, and the s and s^2 coefficients.
+__device__ __forceinline__ void poly_range(double c, double sL, double sM, double l, double w, double h, double& lo,
+                                           double& hi) {
+  const double r = sL + h * sM;
+  lo = c - r + fmin(0.0, l * h) + fmin(0.0, w * h * h);
+  hi = c + r + fmax(0.0, l * h) + fmax(0.0, w * h * h);
+}
 __device__ __forceinline__ void qt_poly_range(const QT& q, double h, double& lo, double& hi) {
-  double r = 0.0;
+  double sL = 0.0, sM = 0.0;
 #pragma unroll
-  for (int p = 0; p < kCtMax; ++p) r += fabs(q.L[p]) + h * fabs(q.M[p]);
-  lo = q.c - r + fmin(0.0, q.l * h) + fmin(0.0, q.w * h * h);
-  hi = q.c + r + fmax(0.0, q.l * h) + fmax(0.0, q.w * h * h);
+  for (int p = 0; p < kCtMax; ++p) { sL += fabs(q.L[p]); sM += fabs(q.M[p]); }
+  poly_range(q.c, sL, sM, q.l, q.w, h, lo, hi);
 }
 
 __device__ __forceinline__ void iv_mul(double alo, double ahi, double blo, double bhi, double& lo, double& hi) {
@@ -83,47 +93,52 @@ __device__ __forceinline__ void iv_mul(double alo, double ahi, double blo, doubl
   hi = fmax(fmax(p0, p1), fmax(p2, p3));
 }
 
-// out += q * (a b) for scalar models a, b (the product truncated to the representation,
-// the dropped monomials and the interval parts bounded over the domain).
-__device__ __forceinline__ void qt_mul_acc(QT& out, const QT& a, const QT& b, double q, double h) {
-  double lo = 0.0, hi = 0.0;
+// dst[slot] = X_j X_k: the product truncated to the representation (the kept monomials
+// exactly, the dropped ones and the interval parts bounded over the domain), with both
+// factors read from LDS.
+__device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h, const QTL& dst, int slot) {
+  const double* aL = X.L + j * kCtMax;
+  const double* aM = X.M + j * kCtMax;
+  const double* bL = X.L + k * kCtMax;
+  const double* bM = X.M + k * kCtMax;
+  const double ac = X.c[j], al = X.l[j], aw = X.w[j], alo_i = X.lo[j], ahi_i = X.hi[j];
+  const double bc = X.c[k], bl = X.l[k], bw = X.w[k], blo_i = X.lo[k], bhi_i = X.hi[k];
   // (L_a y)(L_b y): y_p^2 in [0, 1], y_p y_r in [-1, 1]
   double dsum_lo = 0.0, dsum_hi = 0.0, off = 0.0, sLa = 0.0, sLb = 0.0, sMa = 0.0, sMb = 0.0;
-#pragma unroll
+  double* oL = dst.L + slot * kCtMax;
+  double* oM = dst.M + slot * kCtMax;
+#pragma unroll 4
   for (int p = 0; p < kCtMax; ++p) {
-    sLa += fabs(a.L[p]); sLb += fabs(b.L[p]); sMa += fabs(a.M[p]); sMb += fabs(b.M[p]);
-    const double d = a.L[p] * b.L[p];
+    const double la = aL[p], lb = bL[p], ma = aM[p], mb = bM[p];
+    sLa += fabs(la); sLb += fabs(lb); sMa += fabs(ma); sMb += fabs(mb);
+    const double d = la * lb;
     dsum_lo += fmin(d, 0.0); dsum_hi += fmax(d, 0.0);
     off -= fabs(d);
+    oL[p] = ac * lb + bc * la;
+    oM[p] = ac * mb + bc * ma + al * lb + bl * la;
   }
   off += sLa * sLb;
-  lo += dsum_lo - off; hi += dsum_hi + off;
+  double lo = dsum_lo - off, hi = dsum_hi + off;
   // s y y, s^2 y, s^2 y y, s^3, s^3 y, s^4
   const double t1 = h * (sLa * sMb + sMa * sLb);
-  const double t2 = h * h * (fabs(a.l) * sMb + fabs(b.l) * sMa + fabs(a.w) * sLb + fabs(b.w) * sLa);
+  const double t2 = h * h * (fabs(al) * sMb + fabs(bl) * sMa + fabs(aw) * sLb + fabs(bw) * sLa);
   const double t3 = h * h * sMa * sMb;
-  const double t4 = h * h * h * (fabs(a.w) * sMb + fabs(b.w) * sMa);
+  const double t4 = h * h * h * (fabs(aw) * sMb + fabs(bw) * sMa);
   lo -= t1 + t2 + t3 + t4; hi += t1 + t2 + t3 + t4;
-  const double s3 = (a.l * b.w + a.w * b.l) * h * h * h, s4 = a.w * b.w * h * h * h * h;
+  const double s3 = (al * bw + aw * bl) * h * h * h, s4 = aw * bw * h * h * h * h;
   lo += fmin(0.0, s3) + fmin(0.0, s4); hi += fmax(0.0, s3) + fmax(0.0, s4);
   // interval parts
   double alo, ahi, blo, bhi, x0, x1;
-  qt_poly_range(a, h, alo, ahi);
-  qt_poly_range(b, h, blo, bhi);
-  iv_mul(a.lo, a.hi, blo, bhi, x0, x1); lo += x0; hi += x1;
-  iv_mul(b.lo, b.hi, alo, ahi, x0, x1); lo += x0; hi += x1;
-  iv_mul(a.lo, a.hi, b.lo, b.hi, x0, x1); lo += x0; hi += x1;
-  // kept monomials, scaled by q
-  out.c += q * (a.c * b.c);
-  out.l += q * (a.c * b.l + b.c * a.l);
-  out.w += q * (a.c * b.w + b.c * a.w + a.l * b.l);
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) {
-    out.L[p] += q * (a.c * b.L[p] + b.c * a.L[p]);
-    out.M[p] += q * (a.c * b.M[p] + b.c * a.M[p] + a.l * b.L[p] + b.l * a.L[p]);
-  }
-  const double ql = q * lo, qh = q * hi;
-  out.lo += fmin(ql, qh); out.hi += fmax(ql, qh);
+  poly_range(ac, sLa, sMa, al, aw, h, alo, ahi);
+  poly_range(bc, sLb, sMb, bl, bw, h, blo, bhi);
+  iv_mul(alo_i, ahi_i, blo, bhi, x0, x1); lo += x0; hi += x1;
+  iv_mul(blo_i, bhi_i, alo, ahi, x0, x1); lo += x0; hi += x1;
+  iv_mul(alo_i, ahi_i, blo_i, bhi_i, x0, x1); lo += x0; hi += x1;
+  dst.c[slot] = ac * bc;
+  dst.l[slot] = ac * bl + bc * al;
+  dst.w[slot] = ac * bw + bc * aw + al * bl;
+  dst.lo[slot] = lo;
+  dst.hi[slot] = hi;
 }
 
 // out += F x for a scalar weight F (the interval part by its sign).
@@ -143,55 +158,36 @@ struct CtDyn {
   const double* Q;     // n x n x n (or null)
 };
 
-// Component i of f over the state models X and the held input models U (U may be null).
-__device__ __forceinline__ QT qt_f(int i, const QTL& X, const QTL* U, const CtDyn& d, double h) {
-  QT out = qt_zero();
-  out.c = d.a[i];
-  for (int j = 0; j < d.n; ++j) {
-    const double Fv = d.F[(size_t)i * d.n + j];
-    if (Fv != 0.0) qt_axpy(out, Fv, qt_get(X, j));
-  }
-  if (U && d.G) {
-    for (int k = 0; k < d.n_u; ++k) {
-      const double Gv = d.G[(size_t)i * d.n_u + k];
-      if (Gv != 0.0) qt_axpy(out, Gv, qt_get(*U, k));
-    }
-  }
-  if (d.Q) {
-    for (int j = 0; j < d.n; ++j)
-      for (int k = 0; k < d.n; ++k) {
-        const double q = d.Q[((size_t)i * d.n + j) * d.n + k];
-        if (q != 0.0) qt_mul_acc(out, qt_get(X, j), qt_get(X, k), q, h);
-      }
-  }
-  return out;
-}
-
-// Per-box LDS of the flowpipe: the seed, the Picard iterate / polynomial part, the
-// model used for the remainder images, the held input, work space.
+// Per-box LDS of the flowpipe (one wavefront): the model f is evaluated over (the Picard
+// iterate, then the remainder's trial models), the held input, a chunk of quadratic
+// monomials, the seed, the inversion work space and the list of monomials of the field.
 struct CtLds {
-  QTL G, X, U;
+  QTL X, U, P;
   double* S;        // 16 x 16 seed linear part (the state model c + S y + [lo, hi])
   double* c;        // 16
   double* lo;       // 16
   double* hi;       // 16
-  double* Si;       // 16 x 16 inverse of S (preconditioning)
   double* aux;      // 16: column scales of the preconditioning
-  double* aug;      // 16 x 32: [S | I] during the inversion
-  __host__ __device__ static size_t bytes() {
-    return 3 * QTL::bytes() + (size_t)(2 * kCtMax * kCtMax + 4 * kCtMax + 2 * kCtMax * kCtMax) * sizeof(double);
+  double* aug;      // 16 x 32: [S | I] during the inversion, then S^-1 in the right half
+  int* pairs;       // (j << 8) | k of the monomials x_j x_k (j <= k) with a nonzero coefficient
+  int* n_pairs;
+  __host__ __device__ static constexpr size_t bytes() {
+    return 2 * QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) +
+           (size_t)(kCtMax * kCtMax + 4 * kCtMax + 2 * kCtMax * kCtMax) * sizeof(double) +
+           (size_t)(kCtPairs + 8) * sizeof(int);
   }
   __device__ void carve(double* base) {
-    G.carve(base); base += QTL::bytes() / sizeof(double);
-    X.carve(base); base += QTL::bytes() / sizeof(double);
-    U.carve(base); base += QTL::bytes() / sizeof(double);
+    X.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
+    U.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
+    P.carve(base, kCtChunk); base += QTL::bytes(kCtChunk) / sizeof(double);
     S = base; base += kCtMax * kCtMax;
     c = base; base += kCtMax;
     lo = base; base += kCtMax;
     hi = base; base += kCtMax;
-    Si = base; base += kCtMax * kCtMax;
     aux = base; base += kCtMax;
-    aug = base;
+    aug = base; base += 2 * kCtMax * kCtMax;
+    pairs = (int*)base;
+    n_pairs = pairs + kCtPairs;
   }
 };
 
@@ -200,74 +196,121 @@ __device__ __forceinline__ void ct_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// One flowpipe step on the first wavefront (lanes < n own a component): seed
+// The monomials x_j x_k (j <= k, in order of j then k) whose coefficient is nonzero in
+// some component (the wavefront of the box).
+__device__ __forceinline__ void ct_pairs(const CtLds& C, const CtDyn& d) {
+  const int lane = threadIdx.x & 63, n = d.n;
+  int count = 0;
+  if (d.Q) {
+    for (int e0 = 0; e0 < n * n; e0 += 64) {
+      const int e = e0 + lane;
+      const int j = e / n, k = e % n;
+      bool use = false;
+      if (e < n * n && j <= k)
+        for (int i = 0; i < n; ++i)
+          use = use || d.Q[((size_t)i * n + j) * n + k] != 0.0 || d.Q[((size_t)i * n + k) * n + j] != 0.0;
+      const unsigned long long m = __ballot(use);
+      if (use) C.pairs[count + __popcll(m & ((1ull << lane) - 1ull))] = (j << 8) | k;
+      count += __popcll(m);
+    }
+  }
+  if (lane == 0) C.n_pairs[0] = count;
+  ct_sync();
+}
+
+// f over the models in C.X (and the held input C.U): every lane of the wavefront calls
+// it; lane i < n returns component i.  Ends with the wavefront synchronised.
+__device__ __forceinline__ QT ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
+  const int i = threadIdx.x & 63, n = d.n;
+  const bool act = i < n;
+  QT out = qt_zero();
+  if (act) {
+    out.c = d.a[i];
+    for (int j = 0; j < n; ++j) {
+      const double Fv = d.F[(size_t)i * n + j];
+      if (Fv != 0.0) qt_axpy(out, Fv, qt_get(C.X, j));
+    }
+    if (ctrl && d.G) {
+      for (int k = 0; k < d.n_u; ++k) {
+        const double Gv = d.G[(size_t)i * d.n_u + k];
+        if (Gv != 0.0) qt_axpy(out, Gv, qt_get(C.U, k));
+      }
+    }
+  }
+  const int np = C.n_pairs[0];
+  for (int p0 = 0; p0 < np; p0 += kCtChunk) {
+    const int cnt = min(kCtChunk, np - p0);
+    if (i < cnt) {
+      const int pr = C.pairs[p0 + i];
+      qt_product(C.X, pr >> 8, pr & 255, h, C.P, i);
+    }
+    ct_sync();
+    if (act) {
+      for (int q = 0; q < cnt; ++q) {
+        const int pr = C.pairs[p0 + q];
+        const int j = pr >> 8, k = pr & 255;
+        const double coef = d.Q[((size_t)i * n + j) * n + k] + (j != k ? d.Q[((size_t)i * n + k) * n + j] : 0.0);
+        if (coef != 0.0) qt_axpy(out, coef, qt_get(C.P, q));
+      }
+    }
+    ct_sync();
+  }
+  ct_sync();
+  return out;
+}
+
+// One flowpipe step of the wavefront's box (lanes < n own a component): seed
 // (C.c, C.S, C.lo, C.hi), held input C.U (if `ctrl`).  On return the step-end model is
-// the new seed (preconditioned), seg (per lane) the box of the segment, and the return
-// value says whether a contractive remainder was found (the same on every lane).
+// the new seed (not yet preconditioned), seg (per lane) the box of the segment, and the
+// return value says whether a contractive remainder was found (the same on every lane).
 __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctrl, double h, int tries, int rounds,
                                         double eps, double& seg_lo, double& seg_hi) {
-  const int i = threadIdx.x;          // component (lanes of wave 0)
+  const int i = threadIdx.x & 63;     // component
   const int n = d.n;
   const bool act = i < n;
-  const QTL* U = ctrl ? &C.U : nullptr;
-  // ---- polynomial Picard: g_0 = c + S y, g_{j+1} = x_0 + trunc(int f(g_j))
-  QT x0 = qt_zero();
+  // ---- polynomial Picard: g_0 = c + S y, g_{j+1} = x_0 + trunc(int f(g_j)); x_0 is
+  // re-read from the seed, so only f's model is held in registers
   if (act) {
-    x0.c = C.c[i];
+    C.X.c[i] = C.c[i]; C.X.l[i] = 0.0; C.X.w[i] = 0.0; C.X.lo[i] = 0.0; C.X.hi[i] = 0.0;
 #pragma unroll
-    for (int p = 0; p < kCtMax; ++p) x0.L[p] = C.S[i * kCtMax + p];
-    qt_put(C.G, i, x0);
+    for (int q = 0; q < kCtMax; ++q) { C.X.L[i * kCtMax + q] = C.S[i * kCtMax + q]; C.X.M[i * kCtMax + q] = 0.0; }
   }
   ct_sync();
   for (int it = 0; it < 2; ++it) {
-    QT g = qt_zero();
+    const QT fx = ct_f(C, d, ctrl, h);
     if (act) {
-      const QT fx = qt_f(i, C.G, U, d, h);
-      g = x0;
-      g.l += fx.c;
-      g.w += 0.5 * fx.l;
+      C.X.l[i] = fx.c;
+      C.X.w[i] = 0.5 * fx.l;
 #pragma unroll
-      for (int p = 0; p < kCtMax; ++p) g.M[p] += fx.L[p];
-      g.lo = 0.0; g.hi = 0.0;
+      for (int q = 0; q < kCtMax; ++q) C.X.M[i * kCtMax + q] = fx.L[q];
     }
-    ct_sync();
-    if (act) qt_put(C.G, i, g);
     ct_sync();
   }
-  // p is in C.G; d/ds p = l + M y + 2 w s
-  QT p = act ? qt_get(C.G, i) : qt_zero();
-  QT dp = qt_zero();
-  dp.c = p.l; dp.l = 2.0 * p.w;
-#pragma unroll
-  for (int q = 0; q < kCtMax; ++q) dp.L[q] = p.M[q];
+  // p is the polynomial part of C.X from here on (the trial remainders only change its
+  // interval part); d/ds p = l + M y + 2 w s
   const double I0lo = act ? C.lo[i] : 0.0, I0hi = act ? C.hi[i] : 0.0;
-  auto image = [&](double Jlo, double Jhi, double& nlo, double& nhi) {
-    if (act) {
-      QT xj = p;
-      xj.lo = Jlo; xj.hi = Jhi;
-      qt_put(C.X, i, xj);
-    }
+  double Jlo = I0lo - eps, Jhi = I0hi + eps, nlo = 0.0, nhi = 0.0;
+  // the Picard image of p + J: trial model p (+) J in C.X, then f over it minus d/ds p
+  auto picard_image = [&]() {
+    if (act) { C.X.lo[i] = Jlo; C.X.hi[i] = Jhi; }
     ct_sync();
+    QT D = ct_f(C, d, ctrl, h);
     nlo = 0.0; nhi = 0.0;
     if (act) {
-      QT D = qt_f(i, C.X, U, d, h);
-      // D - dp (dp has no interval part)
-      D.c -= dp.c; D.l -= dp.l;
+      D.c -= C.X.l[i]; D.l -= 2.0 * C.X.w[i];
 #pragma unroll
-      for (int q = 0; q < kCtMax; ++q) D.L[q] -= dp.L[q];
+      for (int q = 0; q < kCtMax; ++q) D.L[q] -= C.X.M[i * kCtMax + q];
       double plo, phi;
       qt_poly_range(D, h, plo, phi);
       nlo = I0lo + fmin(0.0, h * (plo + D.lo));
       nhi = I0hi + fmax(0.0, h * (phi + D.hi));
     }
-    ct_sync();
   };
-  double Jlo = I0lo - eps, Jhi = I0hi + eps, nlo, nhi;
   bool ok = false;
   // an unbounded initial set has no bounded remainder
   const int ntry = __any(!(fabs(I0lo) < INFINITY) || !(fabs(I0hi) < INFINITY)) ? 0 : tries;
   for (int t = 0; t < ntry; ++t) {
-    image(Jlo, Jhi, nlo, nhi);
+    picard_image();
     const bool in = !act || (nlo >= Jlo && nhi <= Jhi);
     if (__all(in)) {
       ok = true;
@@ -282,7 +325,7 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
   }
   if (ok) {
     for (int r = 0; r < rounds; ++r) {
-      image(Jlo, Jhi, nlo, nhi);
+      picard_image();
       Jlo = fmax(Jlo, nlo); Jhi = fmin(Jhi, nhi);
     }
   } else {
@@ -290,12 +333,18 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
   }
   // segment box, step-end model
   if (act) {
-    double plo, phi;
-    qt_poly_range(p, h, plo, phi);
-    seg_lo = plo + Jlo; seg_hi = phi + Jhi;
-    C.c[i] = p.c + p.l * h + p.w * h * h;
+    double sL = 0.0, sM = 0.0;
 #pragma unroll
-    for (int q = 0; q < kCtMax; ++q) C.S[i * kCtMax + q] = p.L[q] + h * p.M[q];
+    for (int q = 0; q < kCtMax; ++q) {
+      const double Lq = C.X.L[i * kCtMax + q], Mq = C.X.M[i * kCtMax + q];
+      sL += fabs(Lq); sM += fabs(Mq);
+      C.S[i * kCtMax + q] = Lq + h * Mq;
+    }
+    const double pc = C.X.c[i], pl = C.X.l[i], pw = C.X.w[i];
+    double plo, phi;
+    poly_range(pc, sL, sM, pl, pw, h, plo, phi);
+    seg_lo = plo + Jlo; seg_hi = phi + Jhi;
+    C.c[i] = pc + pl * h + pw * h * h;
     C.lo[i] = Jlo; C.hi[i] = Jhi;
   }
   ct_sync();
@@ -303,10 +352,11 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
 }
 
 // Step (A): absorb the remainder into the linear part when S is well conditioned; the
-// held input follows.  Wave 0: S^-1 by Gauss-Jordan with partial pivoting (first largest
-// pivot) on the augmented matrix [S | I] in LDS, one column per lane.
+// held input follows.  The wavefront of the box: S^-1 by Gauss-Jordan with partial
+// pivoting (first largest pivot) on the augmented matrix [S | I] in LDS, one column per
+// lane; S^-1 is then the right half.
 __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, bool ctrl) {
-  const int i = threadIdx.x;
+  const int i = threadIdx.x & 63;
   double* aug = C.aug;   // n x 2n, row stride 2 kCtMax
   constexpr int ld = 2 * kCtMax;
   bool fin = true;
@@ -342,20 +392,16 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
     }
     ct_sync();
   }
-  // S^-1 and the check of S^-1 S against the identity
+  const double* Si = aug + n;   // S^-1 (row stride ld)
+  // check S^-1 S against the identity
   double err = 0.0;
   if (good) {
     for (int e = i; e < n * n; e += 64) {
       const int r = e / n, q = e % n;
-      C.Si[r * kCtMax + q] = aug[r * ld + n + q];
-    }
-    ct_sync();
-    for (int e = i; e < n * n; e += 64) {
-      const int r = e / n, q = e % n;
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += C.Si[r * kCtMax + k] * C.S[k * kCtMax + q];
-      const double d = fabs(v - (r == q ? 1.0 : 0.0));
-      if (!(d <= err)) err = d;
+      for (int k = 0; k < n; ++k) v += Si[r * ld + k] * C.S[k * kCtMax + q];
+      const double dv = fabs(v - (r == q ? 1.0 : 0.0));
+      if (!(dv <= err)) err = dv;
     }
   }
   good = good && !__any(!(err <= 1e-9));
@@ -364,14 +410,14 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
   double Dj = 1.0;
   if (i < n) {
     double dl = 0.0;
-    for (int k = 0; k < n; ++k) dl += fabs(C.Si[i * kCtMax + k]) * 0.5 * (C.hi[k] - C.lo[k]);
+    for (int k = 0; k < n; ++k) dl += fabs(Si[i * ld + k]) * 0.5 * (C.hi[k] - C.lo[k]);
     Dj = 1.0 + dl;
   }
   double extra = 0.0;
   if (ctrl && i < n_u) {
     for (int j = 0; j < n; ++j) {
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += C.U.L[i * kCtMax + k] * C.Si[k * kCtMax + j];
+      for (int k = 0; k < n; ++k) v += C.U.L[i * kCtMax + k] * Si[k * ld + j];
       extra += fabs(v) * 0.5 * (C.hi[j] - C.lo[j]);
     }
   }
@@ -390,10 +436,6 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
   ct_sync();
 }
 
-}  // namespace dr
-
-namespace dr {
-
 struct CtArgs {
   BatchDev batch;
   Scratch sc;
@@ -403,6 +445,7 @@ struct CtArgs {
   int n_ctl;         // control intervals (without a controller: one interval of K steps each)
   int tries, rounds;
   double eps;
+  int boxes_per_wg;  // k_reach_ct: boxes of a workgroup (one per wavefront in the flowpipe phase)
   double* boxes;     // S x (n_ctl K + 1) x n x 2: time points
   double* segs;      // S x n_ctl K x n x 2: segments (nullable)
   uint32_t* status;
@@ -416,9 +459,11 @@ __device__ __forceinline__ void ct_point_box(const CtLds& C, int i, double& lo, 
   hi = C.c[i] + r + C.hi[i];
 }
 
-// The seed of box b: c = centre, S = diag(radius), no remainder (wave 0).
+// The seed of box b: c = centre, S = diag(radius), no remainder; writes the box of time
+// point 0 (the wavefront of the box).
 __device__ __forceinline__ void ct_seed(const CtLds& C, const CtArgs& ca, int b, int n0) {
-  const int i = threadIdx.x, n = ca.dyn.n;
+  const int i = threadIdx.x & 63, n = ca.dyn.n;
+  const int N = ca.n_ctl * ca.K;
   if (i < kCtMax) {
     C.c[i] = i < n ? ca.batch.xc[(size_t)b * n0 + i] : 0.0;
     C.lo[i] = 0.0; C.hi[i] = 0.0;
@@ -428,13 +473,19 @@ __device__ __forceinline__ void ct_seed(const CtLds& C, const CtArgs& ca, int b,
     C.S[e] = (r == q && r < n) ? ca.batch.xr[(size_t)b * n0 + r] : 0.0;
   }
   ct_sync();
+  if (i < n) {
+    double lo, hi;
+    ct_point_box(C, i, lo, hi);
+    double* bo = ca.boxes + (size_t)b * (N + 1) * n * 2;
+    bo[i * 2 + 0] = lo; bo[i * 2 + 1] = hi;
+  }
 }
 
-// K flowpipe steps from the current seed (wave 0), writing time-point boxes t0+1 ..
-// t0+K and segment boxes t0 .. t0+K-1; returns false if a step found no contractive
-// remainder.
+// K flowpipe steps from the current seed (the wavefront of the box), writing time-point
+// boxes t0+1 .. t0+K and segment boxes t0 .. t0+K-1; returns false if a step found no
+// contractive remainder.
 __device__ __forceinline__ bool ct_steps(const CtLds& C, const CtArgs& ca, bool ctrl, int b, int t0) {
-  const int i = threadIdx.x, n = ca.dyn.n;
+  const int i = threadIdx.x & 63, n = ca.dyn.n;
   const int N = ca.n_ctl * ca.K;
   bool ok_all = true;
   for (int j = 0; j < ca.K; ++j) {

@@ -78,9 +78,9 @@ struct dr_ctx {
   const void* rg_fn = nullptr;      // k_reach_grad instance (same contexts), its LDS and full grid
   size_t rg_lds = 0;
   int rg_grid = 0;
-  const void* ct_fn = nullptr;      // k_reach_ct instance (the context's network as a CT controller)
-  size_t ct_lds = 0;
-  int ct_grid = 0;
+  const void* ct_fn = nullptr;      // k_reach_ct instance (the context's network as a CT controller),
+  size_t ct_lds = 0;                //   its LDS, full grid and boxes per workgroup
+  int ct_grid = 0, ct_boxes = 0;
   std::string err;
 };
 
@@ -564,9 +564,12 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
       c->rg_fn = nullptr;
     }
     // the CT closed loop: the stepwise reach's on-chip state plus the flowpipe's
+    // (one flowpipe state per box: four boxes per workgroup when they fit, else two or one)
     c->ct_fn = kernel_for(c, DR_KIND_CT, nd.NT, 0);
-    c->ct_lds = lds_bytes(c, Q_REACH, nd) - (size_t)nd.Hp * tsz + (((size_t)nd.Hp * tsz + 15) & ~(size_t)15) +
-                dr::CtLds::bytes();
+    const size_t ct_base = lds_bytes(c, Q_REACH, nd) - (size_t)nd.Hp * tsz + (((size_t)nd.Hp * tsz + 15) & ~(size_t)15);
+    for (c->ct_boxes = dr::kWavesPerWG; c->ct_boxes > 1; c->ct_boxes /= 2)
+      if (ct_base + c->ct_boxes * dr::CtLds::bytes() + 16 <= kMaxLds) break;
+    c->ct_lds = ct_base + c->ct_boxes * dr::CtLds::bytes() + 16;
     if (c->ct_fn && c->ct_lds <= kMaxLds) {
       if ((e = hipFuncSetAttribute(c->ct_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->ct_lds)) != hipSuccess)
         return bail(hip_fail(c, e, "hipFuncSetAttribute"));
@@ -1104,6 +1107,7 @@ dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* o, int n_sub
   if (!xc || !xr || !boxes) return fail(nullptr, DR_EINVAL, "x_center, x_radius and boxes are required");
   dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
   ca.batch.n_sub = n_sub; ca.batch.xc = xc; ca.batch.xr = xr;
+  ca.boxes_per_wg = 1;
   int dev = 0, cus = 0, nb = 0;
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
@@ -1145,9 +1149,11 @@ dr_status dr_reach_ct(dr_ctx* c, const dr_ct_field* f, const dr_ct_options* o, c
   if (b->n_sub == 0) return DR_OK;
   dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
   ca.batch = c->batch; ca.sc = c->sc; ca.sc.st_out = nullptr;
+  ca.boxes_per_wg = c->ct_boxes;
   int net_index = 0;
   void* args[] = {&c->dnet, &net_index, &ca};
-  return launch(c, c->ct_fn, std::min(c->ct_grid, b->n_sub), c->ct_lds, args, stream);
+  const int groups = (b->n_sub + c->ct_boxes - 1) / c->ct_boxes;
+  return launch(c, c->ct_fn, std::min(c->ct_grid, groups), c->ct_lds, args, stream);
 }
 
 dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {

@@ -33,6 +33,7 @@ import numpy as np
 __all__ = [
     "Network", "Batch", "Workload", "make_network", "make_workload",
     "CONFIGS", "config_workload", "pack_splits", "unpack_splits", "random_duals",
+    "CtWorkload", "make_ct_workload",
 ]
 
 
@@ -279,3 +280,63 @@ def random_duals(seed, n_sub, n_rows, n_hidden, n_beta, beta_scale=1.0):
     beta = rng.uniform(0.0, beta_scale, size=(n_sub, n_rows, n_beta))
     # FP32-representable values, so an FP32 consumer sees the same numbers.
     return alpha.astype(np.float32).astype(np.float64), beta.astype(np.float32).astype(np.float64)
+
+
+@dataclass
+class CtWorkload:
+    """A continuous-time closed loop: the vector field f_i(x, u) = a_i + F_i x + G_i u +
+    x^T Q_i x as arrays, a network controller (plain MLP: state in, input out), the
+    initial boxes and the flowpipe schedule (step h, K steps per control interval,
+    N_ctl intervals)."""
+    name: str
+    a: np.ndarray
+    F: np.ndarray
+    G: np.ndarray
+    Q: np.ndarray
+    controller: Network
+    x_center: np.ndarray
+    x_radius: np.ndarray
+    h: float
+    K: int
+    N_ctl: int
+
+
+def make_ct_workload(seed=0, n_sub=4096, hidden=(64, 64), h=0.02, K=5, N_ctl=20, radius=(0.005, 0.02),
+                     q_scale=0.05, out_scale=0.05, name=None) -> CtWorkload:
+    """The 12-state, 4-input rigid-body shape of the paper's CT quadrotor (state:
+    position, velocity, attitude angles, body rates; inputs: thrust and three torques;
+    a 64x64 controller; 100 steps of 0.02) as a quadratic field: the kinematic chain
+    position' = velocity, velocity' = gravity-tilt coupling of the angles (+ thrust on
+    the vertical axis) with light drag, angles' = body rates, rates' = torques with
+    damping, plus small random quadratic couplings (N(0, q_scale^2), on the velocity,
+    angle and rate rows, over the angle and rate states) standing in for the
+    trigonometric and gyroscopic terms.  Initial boxes: centres N(0, 0.1^2) per state,
+    radii uniform in `radius`.  The controller is a random MLP (make_network) whose
+    output layer is scaled by `out_scale`."""
+    rng = np.random.default_rng(seed)
+    n, n_u = 12, 4
+    P, V, TH, W = slice(0, 3), slice(3, 6), slice(6, 9), slice(9, 12)
+    F = np.zeros((n, n))
+    F[P, V] = np.eye(3)
+    F[V, V] = -0.1 * np.eye(3)
+    F[3, 7], F[4, 6] = 0.981, -0.981            # tilt couples gravity into horizontal velocity
+    F[TH, W] = np.eye(3)
+    F[W, W] = -0.5 * np.eye(3)
+    G = np.zeros((n, n_u))
+    G[5, 0] = 1.0                               # thrust deviation on the vertical velocity
+    G[W, 1:] = np.eye(3)                        # torques on the body rates
+    Q = np.zeros((n, n, n))
+    ang = list(range(6, 12))
+    for i in range(3, 12):
+        for j in ang:
+            for k in ang:
+                if k >= j:
+                    Q[i, j, k] = rng.normal(0.0, q_scale)
+    a = np.zeros(n)
+    ctl = make_network(rng, [n, *hidden, n_u], np.float32)
+    ctl.Ws[-1] = (ctl.Ws[-1] * out_scale).astype(np.float32).astype(np.float64)
+    ctl.bs[-1] = (ctl.bs[-1] * out_scale).astype(np.float32).astype(np.float64)
+    xc = rng.normal(0.0, 0.1, (n_sub, n))
+    xr = rng.uniform(radius[0], radius[1], (n_sub, n))
+    return CtWorkload(name or f"ct_quadratic12+4-{hidden[0]}x{len(hidden)}-4_S{n_sub}_N{K * N_ctl}", a, F, G, Q, ctl,
+                      xc, xr, h, K, N_ctl)
