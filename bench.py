@@ -740,6 +740,8 @@ def gap_to_oracle(lb, ub, margin, ref):
     is what the tests check, on sampled points).  Subdomains whose oracle run is within
     floating-point reach of a discrete decision (adaptive slope, stability) are counted
     apart: either decision is valid there."""
+    if ref is None:
+        return None
     idx = ref["idx"]
     ok = (ref["status"] == 0) & ~ref["tie"]
     g_lb, g_ub = lb[idx][ok], ub[idx][ok]
@@ -768,7 +770,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default="", help="comma-separated extra legs to run (for profiling one leg): "
                     "f64,sweep,ascent,pgrad,reach,candidates,joint,reachgrad,ct,tightness,mixed")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of host work for the cpu_baseline leg (0: skip it, for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -777,7 +780,7 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
     cb = ref = None
-    if not args.copy_calibration:
+    if not args.copy_calibration and args.cpu_budget > 0:
         # the host baseline first: its worker processes are forked before the GPU is touched
         from paper_2605_25346_amd.workloads import config_workload
         print("bench: cpu baseline", file=sys.stderr, flush=True)

@@ -28,15 +28,15 @@
 namespace dr {
 
 constexpr int kCtMax = 16;
+constexpr int kCtLd = kCtMax + 1;                          // row stride of L, M and S in LDS (odd: rows
+                                                           // read one per lane fall in distinct banks)
+constexpr int kCtAug = 2 * kCtMax + 1;                     // row stride of [S | I] in the inversion
 constexpr int kCtChunk = 32;                               // monomials formed per pass
+constexpr int kCtBlk = 8;                                  // coefficients fetched per block
 constexpr int kCtPairs = kCtMax * (kCtMax + 1) / 2;        // distinct monomials x_j x_k
 
-// One component of a model in registers.
-struct QT {
-  double c, L[kCtMax], l, M[kCtMax], w, lo, hi;
-};
-
-// A vector of `cap` models in LDS (structure of arrays; L and M are cap x 16).
+// A vector of `cap` models in LDS (structure of arrays; L and M are cap x 16 with row
+// stride kCtLd).
 struct QTL {
   double* c;
   double* L;
@@ -45,32 +45,12 @@ struct QTL {
   double* w;
   double* lo;
   double* hi;
-  __host__ __device__ static constexpr size_t bytes(int cap) { return (size_t)(5 * cap + 2 * cap * kCtMax) * sizeof(double); }
+  __host__ __device__ static constexpr size_t bytes(int cap) { return (size_t)(5 * cap + 2 * cap * kCtLd) * sizeof(double); }
   __device__ void carve(double* base, int cap) {
-    c = base; L = c + cap; l = L + cap * kCtMax; M = l + cap; w = M + cap * kCtMax;
+    c = base; L = c + cap; l = L + cap * kCtLd; M = l + cap; w = M + cap * kCtLd;
     lo = w + cap; hi = lo + cap;
   }
 };
-
-__device__ __forceinline__ QT qt_get(const QTL& t, int i) {
-  QT q;
-  q.c = t.c[i]; q.l = t.l[i]; q.w = t.w[i]; q.lo = t.lo[i]; q.hi = t.hi[i];
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) { q.L[p] = t.L[i * kCtMax + p]; q.M[p] = t.M[i * kCtMax + p]; }
-  return q;
-}
-__device__ __forceinline__ void qt_put(const QTL& t, int i, const QT& q) {
-  t.c[i] = q.c; t.l[i] = q.l; t.w[i] = q.w; t.lo[i] = q.lo; t.hi[i] = q.hi;
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) { t.L[i * kCtMax + p] = q.L[p]; t.M[i * kCtMax + p] = q.M[p]; }
-}
-__device__ __forceinline__ QT qt_zero() {
-  QT q;
-  q.c = q.l = q.w = q.lo = q.hi = 0.0;
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) { q.L[p] = 0.0; q.M[p] = 0.0; }
-  return q;
-}
 
 // Range of the polynomial part over y in [-1, 1]^m, s in [0, h] (term by term), from
 // the constant, the absolute sums of L and M, and the s and s^2 coefficients.
@@ -80,13 +60,6 @@ __device__ __forceinline__ void poly_range(double c, double sL, double sM, doubl
   lo = c - r + fmin(0.0, l * h) + fmin(0.0, w * h * h);
   hi = c + r + fmax(0.0, l * h) + fmax(0.0, w * h * h);
 }
-__device__ __forceinline__ void qt_poly_range(const QT& q, double h, double& lo, double& hi) {
-  double sL = 0.0, sM = 0.0;
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) { sL += fabs(q.L[p]); sM += fabs(q.M[p]); }
-  poly_range(q.c, sL, sM, q.l, q.w, h, lo, hi);
-}
-
 __device__ __forceinline__ void iv_mul(double alo, double ahi, double blo, double bhi, double& lo, double& hi) {
   const double p0 = alo * blo, p1 = alo * bhi, p2 = ahi * blo, p3 = ahi * bhi;
   lo = fmin(fmin(p0, p1), fmin(p2, p3));
@@ -97,16 +70,16 @@ __device__ __forceinline__ void iv_mul(double alo, double ahi, double blo, doubl
 // exactly, the dropped ones and the interval parts bounded over the domain), with both
 // factors read from LDS.
 __device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h, const QTL& dst, int slot) {
-  const double* aL = X.L + j * kCtMax;
-  const double* aM = X.M + j * kCtMax;
-  const double* bL = X.L + k * kCtMax;
-  const double* bM = X.M + k * kCtMax;
+  const double* aL = X.L + j * kCtLd;
+  const double* aM = X.M + j * kCtLd;
+  const double* bL = X.L + k * kCtLd;
+  const double* bM = X.M + k * kCtLd;
   const double ac = X.c[j], al = X.l[j], aw = X.w[j], alo_i = X.lo[j], ahi_i = X.hi[j];
   const double bc = X.c[k], bl = X.l[k], bw = X.w[k], blo_i = X.lo[k], bhi_i = X.hi[k];
   // (L_a y)(L_b y): y_p^2 in [0, 1], y_p y_r in [-1, 1]
   double dsum_lo = 0.0, dsum_hi = 0.0, off = 0.0, sLa = 0.0, sLb = 0.0, sMa = 0.0, sMb = 0.0;
-  double* oL = dst.L + slot * kCtMax;
-  double* oM = dst.M + slot * kCtMax;
+  double* oL = dst.L + slot * kCtLd;
+  double* oM = dst.M + slot * kCtLd;
 #pragma unroll 4
   for (int p = 0; p < kCtMax; ++p) {
     const double la = aL[p], lb = bL[p], ma = aM[p], mb = bM[p];
@@ -141,15 +114,6 @@ __device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h,
   dst.hi[slot] = hi;
 }
 
-// out += F x for a scalar weight F (the interval part by its sign).
-__device__ __forceinline__ void qt_axpy(QT& out, double F, const QT& x) {
-  out.c += F * x.c; out.l += F * x.l; out.w += F * x.w;
-#pragma unroll
-  for (int p = 0; p < kCtMax; ++p) { out.L[p] += F * x.L[p]; out.M[p] += F * x.M[p]; }
-  if (F >= 0.0) { out.lo += F * x.lo; out.hi += F * x.hi; }
-  else { out.lo += F * x.hi; out.hi += F * x.lo; }
-}
-
 struct CtDyn {
   int n, n_u;
   const double* a;     // n
@@ -163,31 +127,32 @@ struct CtDyn {
 // monomials, the seed, the inversion work space and the list of monomials of the field.
 struct CtLds {
   QTL X, U, P;
-  double* S;        // 16 x 16 seed linear part (the state model c + S y + [lo, hi])
+  double* S;        // 16 x 16 seed linear part, row stride kCtLd (the state model c + S y + [lo, hi])
   double* c;        // 16
   double* lo;       // 16
   double* hi;       // 16
   double* aux;      // 16: column scales of the preconditioning
-  double* aug;      // 16 x 32: [S | I] during the inversion, then S^-1 in the right half
+  double* aug;      // 16 x 32 (row stride kCtAug): [S | I] during the inversion, then S^-1 in the right half
   int* pairs;       // (j << 8) | k of the monomials x_j x_k (j <= k) with a nonzero coefficient
   int* n_pairs;
-  __host__ __device__ static constexpr size_t bytes() {
-    return 2 * QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) +
-           (size_t)(kCtMax * kCtMax + 4 * kCtMax + 2 * kCtMax * kCtMax) * sizeof(double) +
-           (size_t)(kCtPairs + 8) * sizeof(int);
+  // the held input's models come last: a flowpipe without input leaves them out
+  __host__ __device__ static constexpr size_t bytes(bool ctrl = true) {
+    return QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) +
+           (size_t)(kCtMax * kCtLd + 4 * kCtMax + kCtMax * kCtAug) * sizeof(double) +
+           (size_t)(kCtPairs + 8) * sizeof(int) + (ctrl ? QTL::bytes(kCtMax) : 0);
   }
   __device__ void carve(double* base) {
     X.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
-    U.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
     P.carve(base, kCtChunk); base += QTL::bytes(kCtChunk) / sizeof(double);
-    S = base; base += kCtMax * kCtMax;
+    S = base; base += kCtMax * kCtLd;
     c = base; base += kCtMax;
     lo = base; base += kCtMax;
     hi = base; base += kCtMax;
     aux = base; base += kCtMax;
-    aug = base; base += 2 * kCtMax * kCtMax;
+    aug = base; base += kCtMax * kCtAug;
     pairs = (int*)base;
     n_pairs = pairs + kCtPairs;
+    U.carve((double*)(n_pairs + 8), kCtMax);
   }
 };
 
@@ -218,40 +183,92 @@ __device__ __forceinline__ void ct_pairs(const CtLds& C, const CtDyn& d) {
   ct_sync();
 }
 
+// A quarter of one component's model in registers: lane 16 g + i holds the scalar
+// coefficients and the interval part of component i (the same in every group) and
+// L, M at generators 4 g .. 4 g + 3.
+struct QTq {
+  double c, l, w, lo, hi, L[4], M[4];
+};
+
+__device__ __forceinline__ QTq qq_zero() {
+  QTq q;
+  q.c = q.l = q.w = q.lo = q.hi = 0.0;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) { q.L[p] = 0.0; q.M[p] = 0.0; }
+  return q;
+}
+
+// out += F T[row] on this lane's quarter (the interval part by the sign of F).
+__device__ __forceinline__ void qq_axpy(QTq& out, double F, const QTL& T, int row, int g) {
+  const double* Lr = T.L + row * kCtLd + 4 * g;
+  const double* Mr = T.M + row * kCtLd + 4 * g;
+  out.c += F * T.c[row]; out.l += F * T.l[row]; out.w += F * T.w[row];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) { out.L[p] += F * Lr[p]; out.M[p] += F * Mr[p]; }
+  const double lo = T.lo[row], hi = T.hi[row];
+  if (F >= 0.0) { out.lo += F * lo; out.hi += F * hi; }
+  else { out.lo += F * hi; out.hi += F * lo; }
+}
+
+// Sum over the four lane groups of a component (bit-identical on every lane: the two
+// pairwise sums commute).
+__device__ __forceinline__ double group_sum(double v) {
+  v += __shfl_xor(v, 16);
+  return v + __shfl_xor(v, 32);
+}
+
 // f over the models in C.X (and the held input C.U): every lane of the wavefront calls
-// it; lane i < n returns component i.  Ends with the wavefront synchronised.
-__device__ __forceinline__ QT ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
-  const int i = threadIdx.x & 63, n = d.n;
+// it; lane 16 g + i (i < n) returns its quarter of component i.  The distinct monomials
+// are formed first, one per lane; then each component's terms are summed, the
+// coefficients split over the four lane groups.  Ends with the wavefront synchronised.
+__device__ __forceinline__ QTq ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
+  const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4, n = d.n;
   const bool act = i < n;
-  QT out = qt_zero();
-  if (act) {
-    out.c = d.a[i];
-    for (int j = 0; j < n; ++j) {
-      const double Fv = d.F[(size_t)i * n + j];
-      if (Fv != 0.0) qt_axpy(out, Fv, qt_get(C.X, j));
-    }
-    if (ctrl && d.G) {
-      for (int k = 0; k < d.n_u; ++k) {
-        const double Gv = d.G[(size_t)i * d.n_u + k];
-        if (Gv != 0.0) qt_axpy(out, Gv, qt_get(C.U, k));
-      }
+  // coefficients are fetched kCtBlk at a time (independent loads, one latency) before
+  // their terms; a lane skips its zero terms (an unbounded model then stays out of them)
+  QTq out = qq_zero();
+  const int ic = act ? i : 0;
+  out.c = act ? d.a[ic] : 0.0;
+  for (int j0 = 0; j0 < n; j0 += kCtBlk) {
+    double cf[kCtBlk];
+#pragma unroll
+    for (int u = 0; u < kCtBlk; ++u) cf[u] = (act && j0 + u < n) ? d.F[(size_t)ic * n + j0 + u] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kCtBlk; ++u)
+      if (cf[u] != 0.0) qq_axpy(out, cf[u], C.X, j0 + u, g);
+  }
+  if (ctrl && d.G) {
+    for (int k0 = 0; k0 < d.n_u; k0 += kCtBlk) {
+      double cf[kCtBlk];
+#pragma unroll
+      for (int u = 0; u < kCtBlk; ++u) cf[u] = (act && k0 + u < d.n_u) ? d.G[(size_t)ic * d.n_u + k0 + u] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kCtBlk; ++u)
+        if (cf[u] != 0.0) qq_axpy(out, cf[u], C.U, k0 + u, g);
     }
   }
   const int np = C.n_pairs[0];
   for (int p0 = 0; p0 < np; p0 += kCtChunk) {
     const int cnt = min(kCtChunk, np - p0);
-    if (i < cnt) {
-      const int pr = C.pairs[p0 + i];
-      qt_product(C.X, pr >> 8, pr & 255, h, C.P, i);
+    if (lane < cnt) {
+      const int pr = C.pairs[p0 + lane];
+      qt_product(C.X, pr >> 8, pr & 255, h, C.P, lane);
     }
     ct_sync();
-    if (act) {
-      for (int q = 0; q < cnt; ++q) {
-        const int pr = C.pairs[p0 + q];
-        const int j = pr >> 8, k = pr & 255;
-        const double coef = d.Q[((size_t)i * n + j) * n + k] + (j != k ? d.Q[((size_t)i * n + k) * n + j] : 0.0);
-        if (coef != 0.0) qt_axpy(out, coef, qt_get(C.P, q));
+    for (int q0 = 0; q0 < cnt; q0 += kCtBlk) {
+      double cf[kCtBlk];
+#pragma unroll
+      for (int u = 0; u < kCtBlk; ++u) {
+        cf[u] = 0.0;
+        if (act && q0 + u < cnt) {
+          const int pr = C.pairs[p0 + q0 + u];
+          const int j = pr >> 8, k = pr & 255;
+          cf[u] = d.Q[((size_t)ic * n + j) * n + k] + (j != k ? d.Q[((size_t)ic * n + k) * n + j] : 0.0);
+        }
       }
+#pragma unroll
+      for (int u = 0; u < kCtBlk; ++u)
+        if (cf[u] != 0.0) qq_axpy(out, cf[u], C.P, q0 + u, g);
     }
     ct_sync();
   }
@@ -259,30 +276,33 @@ __device__ __forceinline__ QT ct_f(const CtLds& C, const CtDyn& d, bool ctrl, do
   return out;
 }
 
-// One flowpipe step of the wavefront's box (lanes < n own a component): seed
-// (C.c, C.S, C.lo, C.hi), held input C.U (if `ctrl`).  On return the step-end model is
-// the new seed (not yet preconditioned), seg (per lane) the box of the segment, and the
-// return value says whether a contractive remainder was found (the same on every lane).
+// One flowpipe step of the wavefront's box (lane 16 g + i, i < n, works on component i):
+// seed (C.c, C.S, C.lo, C.hi), held input C.U (if `ctrl`).  On return the step-end model
+// is the new seed (not yet preconditioned), seg (per lane, for its component) the box of
+// the segment, and the return value says whether a contractive remainder was found (the
+// same on every lane).
 __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctrl, double h, int tries, int rounds,
                                         double eps, double& seg_lo, double& seg_hi) {
-  const int i = threadIdx.x & 63;     // component
+  const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4;
   const int n = d.n;
   const bool act = i < n;
   // ---- polynomial Picard: g_0 = c + S y, g_{j+1} = x_0 + trunc(int f(g_j)); x_0 is
-  // re-read from the seed, so only f's model is held in registers
+  // re-read from the seed
   if (act) {
-    C.X.c[i] = C.c[i]; C.X.l[i] = 0.0; C.X.w[i] = 0.0; C.X.lo[i] = 0.0; C.X.hi[i] = 0.0;
+    if (g == 0) { C.X.c[i] = C.c[i]; C.X.l[i] = 0.0; C.X.w[i] = 0.0; C.X.lo[i] = 0.0; C.X.hi[i] = 0.0; }
 #pragma unroll
-    for (int q = 0; q < kCtMax; ++q) { C.X.L[i * kCtMax + q] = C.S[i * kCtMax + q]; C.X.M[i * kCtMax + q] = 0.0; }
+    for (int q = 0; q < 4; ++q) {
+      C.X.L[i * kCtLd + 4 * g + q] = C.S[i * kCtLd + 4 * g + q];
+      C.X.M[i * kCtLd + 4 * g + q] = 0.0;
+    }
   }
   ct_sync();
   for (int it = 0; it < 2; ++it) {
-    const QT fx = ct_f(C, d, ctrl, h);
+    const QTq fx = ct_f(C, d, ctrl, h);
     if (act) {
-      C.X.l[i] = fx.c;
-      C.X.w[i] = 0.5 * fx.l;
+      if (g == 0) { C.X.l[i] = fx.c; C.X.w[i] = 0.5 * fx.l; }
 #pragma unroll
-      for (int q = 0; q < kCtMax; ++q) C.X.M[i * kCtMax + q] = fx.L[q];
+      for (int q = 0; q < 4; ++q) C.X.M[i * kCtLd + 4 * g + q] = fx.L[q];
     }
     ct_sync();
   }
@@ -292,16 +312,23 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
   double Jlo = I0lo - eps, Jhi = I0hi + eps, nlo = 0.0, nhi = 0.0;
   // the Picard image of p + J: trial model p (+) J in C.X, then f over it minus d/ds p
   auto picard_image = [&]() {
-    if (act) { C.X.lo[i] = Jlo; C.X.hi[i] = Jhi; }
+    if (act && g == 0) { C.X.lo[i] = Jlo; C.X.hi[i] = Jhi; }
     ct_sync();
-    QT D = ct_f(C, d, ctrl, h);
-    nlo = 0.0; nhi = 0.0;
+    QTq D = ct_f(C, d, ctrl, h);
+    double sL = 0.0, sM = 0.0;
     if (act) {
       D.c -= C.X.l[i]; D.l -= 2.0 * C.X.w[i];
 #pragma unroll
-      for (int q = 0; q < kCtMax; ++q) D.L[q] -= C.X.M[i * kCtMax + q];
+      for (int q = 0; q < 4; ++q) {
+        D.L[q] -= C.X.M[i * kCtLd + 4 * g + q];
+        sL += fabs(D.L[q]); sM += fabs(D.M[q]);
+      }
+    }
+    sL = group_sum(sL); sM = group_sum(sM);
+    nlo = 0.0; nhi = 0.0;
+    if (act) {
       double plo, phi;
-      qt_poly_range(D, h, plo, phi);
+      poly_range(D.c, sL, sM, D.l, D.w, h, plo, phi);
       nlo = I0lo + fmin(0.0, h * (plo + D.lo));
       nhi = I0hi + fmax(0.0, h * (phi + D.hi));
     }
@@ -332,20 +359,22 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
     Jlo = -INFINITY; Jhi = INFINITY;
   }
   // segment box, step-end model
+  double sL = 0.0, sM = 0.0;
   if (act) {
-    double sL = 0.0, sM = 0.0;
 #pragma unroll
-    for (int q = 0; q < kCtMax; ++q) {
-      const double Lq = C.X.L[i * kCtMax + q], Mq = C.X.M[i * kCtMax + q];
+    for (int q = 0; q < 4; ++q) {
+      const double Lq = C.X.L[i * kCtLd + 4 * g + q], Mq = C.X.M[i * kCtLd + 4 * g + q];
       sL += fabs(Lq); sM += fabs(Mq);
-      C.S[i * kCtMax + q] = Lq + h * Mq;
+      C.S[i * kCtLd + 4 * g + q] = Lq + h * Mq;
     }
+  }
+  sL = group_sum(sL); sM = group_sum(sM);
+  if (act) {
     const double pc = C.X.c[i], pl = C.X.l[i], pw = C.X.w[i];
     double plo, phi;
     poly_range(pc, sL, sM, pl, pw, h, plo, phi);
     seg_lo = plo + Jlo; seg_hi = phi + Jhi;
-    C.c[i] = pc + pl * h + pw * h * h;
-    C.lo[i] = Jlo; C.hi[i] = Jhi;
+    if (g == 0) { C.c[i] = pc + pl * h + pw * h * h; C.lo[i] = Jlo; C.hi[i] = Jhi; }
   }
   ct_sync();
   return ok;
@@ -357,16 +386,16 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
 // lane; S^-1 is then the right half.
 __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, bool ctrl) {
   const int i = threadIdx.x & 63;
-  double* aug = C.aug;   // n x 2n, row stride 2 kCtMax
-  constexpr int ld = 2 * kCtMax;
+  double* aug = C.aug;   // n x 2n, row stride kCtAug
+  constexpr int ld = kCtAug;
   bool fin = true;
   if (i < n) {
     fin = fabs(C.lo[i]) < INFINITY && fabs(C.hi[i]) < INFINITY;
-    for (int q = 0; q < n; ++q) fin = fin && fabs(C.S[i * kCtMax + q]) < INFINITY;
+    for (int q = 0; q < n; ++q) fin = fin && fabs(C.S[i * kCtLd + q]) < INFINITY;
   }
   bool good = !__any(!fin);
   if (i < 2 * n)
-    for (int r = 0; r < n; ++r) aug[r * ld + i] = i < n ? C.S[r * kCtMax + i] : (i - n == r ? 1.0 : 0.0);
+    for (int r = 0; r < n; ++r) aug[r * ld + i] = i < n ? C.S[r * kCtLd + i] : (i - n == r ? 1.0 : 0.0);
   ct_sync();
   for (int col = 0; col < n && good; ++col) {
     int piv = col;
@@ -399,7 +428,7 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
     for (int e = i; e < n * n; e += 64) {
       const int r = e / n, q = e % n;
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += Si[r * ld + k] * C.S[k * kCtMax + q];
+      for (int k = 0; k < n; ++k) v += Si[r * ld + k] * C.S[k * kCtLd + q];
       const double dv = fabs(v - (r == q ? 1.0 : 0.0));
       if (!(dv <= err)) err = dv;
     }
@@ -417,7 +446,7 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
   if (ctrl && i < n_u) {
     for (int j = 0; j < n; ++j) {
       double v = 0.0;
-      for (int k = 0; k < n; ++k) v += C.U.L[i * kCtMax + k] * Si[k * ld + j];
+      for (int k = 0; k < n; ++k) v += C.U.L[i * kCtLd + k] * Si[k * ld + j];
       extra += fabs(v) * 0.5 * (C.hi[j] - C.lo[j]);
     }
   }
@@ -426,11 +455,11 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
   ct_sync();
   if (i < n) {
     C.c[i] += 0.5 * (C.lo[i] + C.hi[i]);
-    for (int q = 0; q < n; ++q) C.S[i * kCtMax + q] *= C.aux[q];
+    for (int q = 0; q < n; ++q) C.S[i * kCtLd + q] *= C.aux[q];
     C.lo[i] = 0.0; C.hi[i] = 0.0;
   }
   if (ctrl && i < n_u) {
-    for (int q = 0; q < n; ++q) C.U.L[i * kCtMax + q] *= C.aux[q];
+    for (int q = 0; q < n; ++q) C.U.L[i * kCtLd + q] *= C.aux[q];
     C.U.lo[i] -= extra; C.U.hi[i] += extra;
   }
   ct_sync();
@@ -454,7 +483,7 @@ struct CtArgs {
 // Box of the state model (c, S, lo, hi) for component i.
 __device__ __forceinline__ void ct_point_box(const CtLds& C, int i, double& lo, double& hi) {
   double r = 0.0;
-  for (int q = 0; q < kCtMax; ++q) r += fabs(C.S[i * kCtMax + q]);
+  for (int q = 0; q < kCtMax; ++q) r += fabs(C.S[i * kCtLd + q]);
   lo = C.c[i] - r + C.lo[i];
   hi = C.c[i] + r + C.hi[i];
 }
@@ -470,7 +499,7 @@ __device__ __forceinline__ void ct_seed(const CtLds& C, const CtArgs& ca, int b,
   }
   for (int e = i; e < kCtMax * kCtMax; e += 64) {
     const int r = e / kCtMax, q = e % kCtMax;
-    C.S[e] = (r == q && r < n) ? ca.batch.xr[(size_t)b * n0 + r] : 0.0;
+    C.S[r * kCtLd + q] = (r == q && r < n) ? ca.batch.xr[(size_t)b * n0 + r] : 0.0;
   }
   ct_sync();
   if (i < n) {
@@ -485,15 +514,15 @@ __device__ __forceinline__ void ct_seed(const CtLds& C, const CtArgs& ca, int b,
 // boxes t0+1 .. t0+K and segment boxes t0 .. t0+K-1; returns false if a step found no
 // contractive remainder.
 __device__ __forceinline__ bool ct_steps(const CtLds& C, const CtArgs& ca, bool ctrl, int b, int t0) {
-  const int i = threadIdx.x & 63, n = ca.dyn.n;
+  const int lane = threadIdx.x & 63, n = ca.dyn.n;
   const int N = ca.n_ctl * ca.K;
   bool ok_all = true;
   for (int j = 0; j < ca.K; ++j) {
     double slo = 0.0, shi = 0.0;
     const bool ok = ct_step(C, ca.dyn, ctrl, ca.h, ca.tries, ca.rounds, ca.eps, slo, shi);
     ok_all = ok_all && ok;
-    const int t = t0 + j;
-    if (i < n) {
+    const int t = t0 + j, i = lane;
+    if (lane < n) {
       double lo, hi;
       ct_point_box(C, i, lo, hi);
       double* bo = ca.boxes + ((size_t)b * (N + 1) + t + 1) * n * 2;

@@ -50,11 +50,11 @@ __global__ void __launch_bounds__(kWG) k_reach_ct(const NetDev* __restrict__ net
         // ---- the controller of box b0 + q on its state's model: tm = (c, S, lo, hi, |x| bound)
         CtLds Cq;
         Cq.carve((double*)(ct_base + (size_t)q * CtLds::bytes()));
-        for (int e = tid; e < 256; e += kWG) tm[16 + e] = Cq.S[e];
+        for (int e = tid; e < 256; e += kWG) tm[16 + e] = Cq.S[(e >> 4) * kCtLd + (e & 15)];
         if (tid < 16) {
           tm[tid] = Cq.c[tid]; tm[272 + tid] = Cq.lo[tid]; tm[288 + tid] = Cq.hi[tid];
           double a = fabs(Cq.c[tid]) + fmax(fabs(Cq.lo[tid]), fabs(Cq.hi[tid]));
-          for (int z = 0; z < n0; ++z) a += fabs(Cq.S[tid * 16 + z]);
+          for (int z = 0; z < n0; ++z) a += fabs(Cq.S[tid * kCtLd + z]);
           tm[304 + tid] = tid < n0 ? a : 0.0;
           S.xc[tid] = 0.0; S.xr[tid] = 0.0;
         }
@@ -74,8 +74,9 @@ __global__ void __launch_bounds__(kWG) k_reach_ct(const NetDev* __restrict__ net
           Cq.U.l[tid] = 0.0; Cq.U.w[tid] = 0.0;
         }
         for (int e = tid; e < 256; e += kWG) {
-          Cq.U.L[e] = (e / 16) < n_u ? tm[336 + e] : 0.0;
-          Cq.U.M[e] = 0.0;
+          const int r = e >> 4, z = e & 15;
+          Cq.U.L[r * kCtLd + z] = r < n_u ? tm[336 + e] : 0.0;
+          Cq.U.M[r * kCtLd + z] = 0.0;
         }
         if (tid == 0) box_st[q] |= S.misc[1];
         lds_barrier();

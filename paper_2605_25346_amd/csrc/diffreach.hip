@@ -1113,7 +1113,7 @@ dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* o, int n_sub
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hip_fail(nullptr, e, "device query");
-  const size_t lds = dr::CtLds::bytes();
+  const size_t lds = dr::CtLds::bytes(false);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)dr::k_flowpipe_ct, 64, lds) != hipSuccess || nb < 1)
     nb = 1;
   const int grid = (int)std::min<long long>((long long)nb * std::max(cus, 1), n_sub);
