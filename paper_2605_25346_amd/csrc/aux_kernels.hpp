@@ -406,7 +406,7 @@ __global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __re
 __global__ void __launch_bounds__(64) k_flowpipe_ct(CtArgs ca) {
   extern __shared__ __align__(16) char ct_raw[];
   CtLds C;
-  C.carve((double*)ct_raw);
+  C.carve((double*)ct_raw, false);
   ct_pairs(C, ca.dyn);
   for (int b = blockIdx.x; b < ca.batch.n_sub; b += gridDim.x) {
     ct_seed(C, ca, b, ca.dyn.n);

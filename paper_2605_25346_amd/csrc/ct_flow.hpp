@@ -11,7 +11,7 @@
 // state, affine in the held input u).  A product keeps the monomials {1, y, s, s y, s^2}
 // and bounds every other one over the domain into the interval part.  Each evaluation of
 // f first forms every distinct quadratic monomial X_j X_k (j <= k) once, one per lane in
-// chunks of kCtChunk, then every component sums its terms (coefficient Q_ijk + Q_ikj off
+// chunks of 16 or 32, then every component sums its terms (coefficient Q_ijk + Q_ikj off
 // the diagonal).  The step: two Picard iterations of the polynomial part from the seed
 // c + S y; the remainder J validated by the Picard image J' = I_0 + hull(0, h range(
 // f(p + J) - d/ds p)) inside J (widening while not), then refined; the step-end model
@@ -31,7 +31,8 @@ constexpr int kCtMax = 16;
 constexpr int kCtLd = kCtMax + 1;                          // row stride of L, M and S in LDS (odd: rows
                                                            // read one per lane fall in distinct banks)
 constexpr int kCtAug = 2 * kCtMax + 1;                     // row stride of [S | I] in the inversion
-constexpr int kCtChunk = 32;                               // monomials formed per pass
+constexpr int kCtChunkOpen = 16;                           // monomials formed per pass: the open
+constexpr int kCtChunkLoop = 32;                           // flowpipe (more waves per CU), the loop
 constexpr int kCtBlk = 8;                                  // coefficients fetched per block
 constexpr int kCtPairs = kCtMax * (kCtMax + 1) / 2;        // distinct monomials x_j x_k
 
@@ -132,24 +133,29 @@ struct CtLds {
   double* lo;       // 16
   double* hi;       // 16
   double* aux;      // 16: column scales of the preconditioning
-  double* aug;      // 16 x 32 (row stride kCtAug): [S | I] during the inversion, then S^-1 in the right half
+  double* aug;      // 16 x 32 (row stride kCtAug): [S | I] during the inversion, then S^-1 in the
+                    // right half (in the space of the monomial chunk P)
   int* pairs;       // (j << 8) | k of the monomials x_j x_k (j <= k) with a nonzero coefficient
   int* n_pairs;
   // the held input's models come last: a flowpipe without input leaves them out
-  __host__ __device__ static constexpr size_t bytes(bool ctrl = true) {
-    return QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) +
-           (size_t)(kCtMax * kCtLd + 4 * kCtMax + kCtMax * kCtAug) * sizeof(double) +
-           (size_t)(kCtPairs + 8) * sizeof(int) + (ctrl ? QTL::bytes(kCtMax) : 0);
+  // the inversion's [S | I] shares the monomials' space (never live together)
+  static_assert(QTL::bytes(kCtChunkOpen) >= (size_t)kCtMax * kCtAug * sizeof(double), "[S | I] must fit the chunk");
+  int chunk;        // monomials per pass (capacity of P)
+  __host__ __device__ static constexpr size_t bytes(bool ctrl) {
+    return QTL::bytes(kCtMax) + QTL::bytes(ctrl ? kCtChunkLoop : kCtChunkOpen) +
+           (size_t)(kCtMax * kCtLd + 4 * kCtMax) * sizeof(double) + (size_t)(kCtPairs + 8) * sizeof(int) +
+           (ctrl ? QTL::bytes(kCtMax) : 0);
   }
-  __device__ void carve(double* base) {
+  __device__ void carve(double* base, bool ctrl) {
+    chunk = ctrl ? kCtChunkLoop : kCtChunkOpen;
     X.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
-    P.carve(base, kCtChunk); base += QTL::bytes(kCtChunk) / sizeof(double);
+    P.carve(base, chunk);
+    aug = base; base += QTL::bytes(chunk) / sizeof(double);
     S = base; base += kCtMax * kCtLd;
     c = base; base += kCtMax;
     lo = base; base += kCtMax;
     hi = base; base += kCtMax;
     aux = base; base += kCtMax;
-    aug = base; base += kCtMax * kCtAug;
     pairs = (int*)base;
     n_pairs = pairs + kCtPairs;
     U.carve((double*)(n_pairs + 8), kCtMax);
@@ -248,8 +254,8 @@ __device__ __forceinline__ QTq ct_f(const CtLds& C, const CtDyn& d, bool ctrl, d
     }
   }
   const int np = C.n_pairs[0];
-  for (int p0 = 0; p0 < np; p0 += kCtChunk) {
-    const int cnt = min(kCtChunk, np - p0);
+  for (int p0 = 0; p0 < np; p0 += C.chunk) {
+    const int cnt = min(C.chunk, np - p0);
     if (lane < cnt) {
       const int pr = C.pairs[p0 + lane];
       qt_product(C.X, pr >> 8, pr & 255, h, C.P, lane);

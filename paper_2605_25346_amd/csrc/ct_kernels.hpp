@@ -34,8 +34,8 @@ __global__ void __launch_bounds__(kWG) k_reach_ct(const NetDev* __restrict__ net
   char* ct_base = lds_base + SubLds<T>::bytes(Hp, NT) + kReachExtraLds + ct_bias_bytes<T>(Hp);
   const int nb = ca.boxes_per_wg;
   CtLds C;   // the flowpipe state of this wavefront's box
-  C.carve((double*)(ct_base + (size_t)min(wid, nb - 1) * CtLds::bytes()));
-  int* box_st = (int*)(ct_base + (size_t)nb * CtLds::bytes());   // status bits per box
+  C.carve((double*)(ct_base + (size_t)min(wid, nb - 1) * CtLds::bytes(true)), true);
+  int* box_st = (int*)(ct_base + (size_t)nb * CtLds::bytes(true));   // status bits per box
   const int n = ca.dyn.n, n_u = ca.dyn.n_u, n0 = net.n[0];
   if (wid < nb) ct_pairs(C, ca.dyn);
   for (int b0 = blockIdx.x * nb; b0 < ca.batch.n_sub; b0 += gridDim.x * nb) {
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(kWG) k_reach_ct(const NetDev* __restrict__ net
       for (int q = 0; q < nbox; ++q) {
         // ---- the controller of box b0 + q on its state's model: tm = (c, S, lo, hi, |x| bound)
         CtLds Cq;
-        Cq.carve((double*)(ct_base + (size_t)q * CtLds::bytes()));
+        Cq.carve((double*)(ct_base + (size_t)q * CtLds::bytes(true)), true);
         for (int e = tid; e < 256; e += kWG) tm[16 + e] = Cq.S[(e >> 4) * kCtLd + (e & 15)];
         if (tid < 16) {
           tm[tid] = Cq.c[tid]; tm[272 + tid] = Cq.lo[tid]; tm[288 + tid] = Cq.hi[tid];

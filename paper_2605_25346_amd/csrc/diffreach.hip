@@ -568,8 +568,8 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     c->ct_fn = kernel_for(c, DR_KIND_CT, nd.NT, 0);
     const size_t ct_base = lds_bytes(c, Q_REACH, nd) - (size_t)nd.Hp * tsz + (((size_t)nd.Hp * tsz + 15) & ~(size_t)15);
     for (c->ct_boxes = dr::kWavesPerWG; c->ct_boxes > 1; c->ct_boxes /= 2)
-      if (ct_base + c->ct_boxes * dr::CtLds::bytes() + 16 <= kMaxLds) break;
-    c->ct_lds = ct_base + c->ct_boxes * dr::CtLds::bytes() + 16;
+      if (ct_base + c->ct_boxes * dr::CtLds::bytes(true) + 16 <= kMaxLds) break;
+    c->ct_lds = ct_base + c->ct_boxes * dr::CtLds::bytes(true) + 16;
     if (c->ct_fn && c->ct_lds <= kMaxLds) {
       if ((e = hipFuncSetAttribute(c->ct_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->ct_lds)) != hipSuccess)
         return bail(hip_fail(c, e, "hipFuncSetAttribute"));
