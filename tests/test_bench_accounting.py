@@ -45,3 +45,19 @@ def test_joint_flops_hand_count():
     rows[0, :3] = [0, 6, 4]
     rows[1, :3] = [2, 6, 4]
     assert bench.joint_flops([3, 4, 5, 2], 2, rows) == 1952
+
+
+def test_ct_step_flops_hand_count():
+    """Two states, no input, F with two nonzero entries, one monomial x_0 x_1 that both
+    components use (Q_001 = 1, Q_110 = 2): an evaluation of f is one product (540) and
+    four scaled terms (4 x 74) = 836; a step makes 2 Picard + 1 validating + 3 refining
+    evaluations (5016), four images of 84 per component (672), the Picard and step-end
+    updates (140 + 70) and the preconditioning (6 n^3 + 4 n^2 = 48 + 16) -> 5962."""
+    import numpy as np
+    F = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    Q = np.zeros((2, 2, 2)); Q[0, 0, 1] = 1.0; Q[1, 1, 0] = 2.0
+    assert bench.ct_step_flops(F, None, Q) == 5962
+    # the same monomial written on either side counts once; an input adds its terms and
+    # the update of the held input's model (2 n_u n^2)
+    G = np.array([[1.0], [0.0]])
+    assert bench.ct_step_flops(F, G, Q) == 5962 + 6 * 74 + 2 * 1 * 4
