@@ -33,7 +33,7 @@ if ROOT not in sys.path:
 METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain
 # copy of known size (see profiles/); valid only for the kernel sources they were taken with.
-TRAFFIC = {"src_sha": "47ac3b3d65b14d21", "k_bound_init_bytes": 2.13e6 + 30.75e6}
+TRAFFIC = {"src_sha": "9391eb300feb41bf", "k_bound_init_bytes": 2.13e6 + 30.75e6}
 
 
 def kernel_src_sha():
