@@ -376,9 +376,11 @@ dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* opt, int n_s
  * controller's chains run in the context's precision (rigorous margins as configured);
  * the input's model is linear over the same generators, its interval part centred.
  * Batch as for dr_reach_dt (no splits; x_center, x_radius n_sub x n); outputs as for
- * dr_flowpipe_ct; status also carries the controller step's bits.  Up to four boxes per
- * workgroup (one wavefront each in the flowpipe phase).  Asynchronous on `stream`;
- * allocates nothing. */
+ * dr_flowpipe_ct; status also carries the controller step's bits.  Two launches per
+ * control interval: the controllers of all boxes (one workgroup per box), then their
+ * flowpipes (one wavefront per box); each box's state waits in between in a buffer that
+ * dr_create allocates for closed-loop contexts (max_sub boxes), so calls that overlap on
+ * one context race.  Asynchronous on `stream`; allocates nothing. */
 dr_status dr_reach_ct(dr_ctx* ctx, const dr_ct_field* f, const dr_ct_options* opt, const dr_batch* batch,
                       double* boxes, double* segments, uint32_t* status, hipStream_t stream);
 

@@ -406,13 +406,50 @@ __global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __re
 __global__ void __launch_bounds__(64) k_flowpipe_ct(CtArgs ca) {
   extern __shared__ __align__(16) char ct_raw[];
   CtLds C;
-  C.carve((double*)ct_raw, false);
+  C.carve((double*)ct_raw, 0);
   ct_pairs(C, ca.dyn);
   for (int b = blockIdx.x; b < ca.batch.n_sub; b += gridDim.x) {
     ct_seed(C, ca, b, ca.dyn.n);
     bool ok = true;
     for (int k = 0; k < ca.n_ctl; ++k) ok = ct_steps(C, ca, false, b, k * ca.K) && ok;
     if (threadIdx.x == 0 && ca.status) ca.status[b] = ok ? 0u : (uint32_t)DR_RES_NONFINITE;
+    ct_sync();
+  }
+}
+
+// K flowpipe steps of every box of the closed loop with its input held (interval
+// `interval` of Algorithm "Reachability of CT NN Control Systems"): the box's state and
+// the input's model come from the state buffer (written by k_ct_control) and go back
+// there; one wavefront per box.
+__global__ void __launch_bounds__(64) k_flowpipe_ct_held(CtArgs ca, int interval) {
+  extern __shared__ __align__(16) char ct_raw[];
+  CtLds C;
+  C.carve((double*)ct_raw, ca.dyn.n_u);
+  ct_pairs(C, ca.dyn);
+  const int lane = threadIdx.x;
+  for (int b = blockIdx.x; b < ca.batch.n_sub; b += gridDim.x) {
+    double* st = ca.state + (size_t)b * kCtState;
+    const int n_u = ca.dyn.n_u;
+    if (lane < kCtMax) { C.c[lane] = st[lane]; C.lo[lane] = st[272 + lane]; C.hi[lane] = st[288 + lane]; }
+    if (lane < n_u) {
+      C.U.c[lane] = st[304 + lane]; C.U.lo[lane] = st[576 + lane]; C.U.hi[lane] = st[592 + lane];
+      C.U.l[lane] = 0.0; C.U.w[lane] = 0.0;
+    }
+    for (int e = lane; e < kCtMax * kCtMax; e += 64) {
+      const int r = e >> 4, z = e & 15;
+      C.S[r * kCtLd + z] = st[16 + e];
+      if (r < n_u) { C.U.L[r * kCtLd + z] = st[320 + e]; C.U.M[r * kCtLd + z] = 0.0; }
+    }
+    ct_sync();
+    const bool ok = ct_steps(C, ca, true, b, interval * ca.K);
+    if (lane < kCtMax) { st[lane] = C.c[lane]; st[272 + lane] = C.lo[lane]; st[288 + lane] = C.hi[lane]; }
+    if (lane < n_u) { st[576 + lane] = C.U.lo[lane]; st[592 + lane] = C.U.hi[lane]; }
+    for (int e = lane; e < kCtMax * kCtMax; e += 64) {
+      const int r = e >> 4, z = e & 15;
+      st[16 + e] = C.S[r * kCtLd + z];
+      if (r < n_u) st[320 + e] = C.U.L[r * kCtLd + z];
+    }
+    if (lane == 0 && !ok && ca.status) ca.status[b] |= (uint32_t)DR_RES_NONFINITE;
     ct_sync();
   }
 }

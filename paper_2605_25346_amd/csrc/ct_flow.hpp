@@ -11,7 +11,7 @@
 // state, affine in the held input u).  A product keeps the monomials {1, y, s, s y, s^2}
 // and bounds every other one over the domain into the interval part.  Each evaluation of
 // f first forms every distinct quadratic monomial X_j X_k (j <= k) once, one per lane in
-// chunks of 16 or 32, then every component sums its terms (coefficient Q_ijk + Q_ikj off
+// chunks of 16, then every component sums its terms (coefficient Q_ijk + Q_ikj off
 // the diagonal).  The step: two Picard iterations of the polynomial part from the seed
 // c + S y; the remainder J validated by the Picard image J' = I_0 + hull(0, h range(
 // f(p + J) - d/ds p)) inside J (widening while not), then refined; the step-end model
@@ -31,8 +31,7 @@ constexpr int kCtMax = 16;
 constexpr int kCtLd = kCtMax + 1;                          // row stride of L, M and S in LDS (odd: rows
                                                            // read one per lane fall in distinct banks)
 constexpr int kCtAug = 2 * kCtMax + 1;                     // row stride of [S | I] in the inversion
-constexpr int kCtChunkOpen = 16;                           // monomials formed per pass: the open
-constexpr int kCtChunkLoop = 32;                           // flowpipe (more waves per CU), the loop
+constexpr int kCtChunk = 16;                               // monomials formed per pass
 constexpr int kCtBlk = 8;                                  // coefficients fetched per block
 constexpr int kCtPairs = kCtMax * (kCtMax + 1) / 2;        // distinct monomials x_j x_k
 
@@ -137,20 +136,17 @@ struct CtLds {
                     // right half (in the space of the monomial chunk P)
   int* pairs;       // (j << 8) | k of the monomials x_j x_k (j <= k) with a nonzero coefficient
   int* n_pairs;
-  // the held input's models come last: a flowpipe without input leaves them out
+  // the held input's models come last, n_u of them (none for a flowpipe without input);
   // the inversion's [S | I] shares the monomials' space (never live together)
-  static_assert(QTL::bytes(kCtChunkOpen) >= (size_t)kCtMax * kCtAug * sizeof(double), "[S | I] must fit the chunk");
-  int chunk;        // monomials per pass (capacity of P)
-  __host__ __device__ static constexpr size_t bytes(bool ctrl) {
-    return QTL::bytes(kCtMax) + QTL::bytes(ctrl ? kCtChunkLoop : kCtChunkOpen) +
-           (size_t)(kCtMax * kCtLd + 4 * kCtMax) * sizeof(double) + (size_t)(kCtPairs + 8) * sizeof(int) +
-           (ctrl ? QTL::bytes(kCtMax) : 0);
+  static_assert(QTL::bytes(kCtChunk) >= (size_t)kCtMax * kCtAug * sizeof(double), "[S | I] must fit the chunk");
+  __host__ __device__ static constexpr size_t bytes(int n_u) {
+    return QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) + (size_t)(kCtMax * kCtLd + 4 * kCtMax) * sizeof(double) +
+           (size_t)(kCtPairs + 8) * sizeof(int) + (n_u > 0 ? QTL::bytes(n_u) : 0);
   }
-  __device__ void carve(double* base, bool ctrl) {
-    chunk = ctrl ? kCtChunkLoop : kCtChunkOpen;
+  __device__ void carve(double* base, int n_u) {
     X.carve(base, kCtMax); base += QTL::bytes(kCtMax) / sizeof(double);
-    P.carve(base, chunk);
-    aug = base; base += QTL::bytes(chunk) / sizeof(double);
+    P.carve(base, kCtChunk);
+    aug = base; base += QTL::bytes(kCtChunk) / sizeof(double);
     S = base; base += kCtMax * kCtLd;
     c = base; base += kCtMax;
     lo = base; base += kCtMax;
@@ -158,7 +154,7 @@ struct CtLds {
     aux = base; base += kCtMax;
     pairs = (int*)base;
     n_pairs = pairs + kCtPairs;
-    U.carve((double*)(n_pairs + 8), kCtMax);
+    U.carve((double*)(n_pairs + 8), n_u > 0 ? n_u : 1);
   }
 };
 
@@ -254,8 +250,8 @@ __device__ __forceinline__ QTq ct_f(const CtLds& C, const CtDyn& d, bool ctrl, d
     }
   }
   const int np = C.n_pairs[0];
-  for (int p0 = 0; p0 < np; p0 += C.chunk) {
-    const int cnt = min(C.chunk, np - p0);
+  for (int p0 = 0; p0 < np; p0 += kCtChunk) {
+    const int cnt = min(kCtChunk, np - p0);
     if (lane < cnt) {
       const int pr = C.pairs[p0 + lane];
       qt_product(C.X, pr >> 8, pr & 255, h, C.P, lane);
@@ -471,6 +467,11 @@ __device__ __forceinline__ void ct_precondition(const CtLds& C, int n, int n_u, 
   ct_sync();
 }
 
+// A box's state between the launches of the closed loop (FP64, global memory): the state
+// model c (16), S (16 x 16, row-major), I_lo (16), I_hi (16), then the held input's model
+// c_u (16), P_u (16 x 16), its interval lo (16), hi (16).
+constexpr int kCtState = 608;
+
 struct CtArgs {
   BatchDev batch;
   Scratch sc;
@@ -480,7 +481,7 @@ struct CtArgs {
   int n_ctl;         // control intervals (without a controller: one interval of K steps each)
   int tries, rounds;
   double eps;
-  int boxes_per_wg;  // k_reach_ct: boxes of a workgroup (one per wavefront in the flowpipe phase)
+  double* state;     // closed loop: S x kCtState, each box's state between the launches
   double* boxes;     // S x (n_ctl K + 1) x n x 2: time points
   double* segs;      // S x n_ctl K x n x 2: segments (nullable)
   uint32_t* status;

@@ -78,9 +78,10 @@ struct dr_ctx {
   const void* rg_fn = nullptr;      // k_reach_grad instance (same contexts), its LDS and full grid
   size_t rg_lds = 0;
   int rg_grid = 0;
-  const void* ct_fn = nullptr;      // k_reach_ct instance (the context's network as a CT controller),
-  size_t ct_lds = 0;                //   its LDS, full grid and boxes per workgroup
-  int ct_grid = 0, ct_boxes = 0;
+  const void* ct_fn = nullptr;      // k_ct_control instance (the context's network as a CT controller),
+  size_t ct_lds = 0;                //   its LDS and full grid
+  int ct_grid = 0;
+  double* ct_state = nullptr;       // max_sub x kCtState: each box's state between the CT launches
   std::string err;
 };
 
@@ -563,17 +564,16 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     } else {
       c->rg_fn = nullptr;
     }
-    // the CT closed loop: the stepwise reach's on-chip state plus the flowpipe's
-    // (one flowpipe state per box: four boxes per workgroup when they fit, else two or one)
-    c->ct_fn = kernel_for(c, DR_KIND_CT, nd.NT, 0);
-    const size_t ct_base = lds_bytes(c, Q_REACH, nd) - (size_t)nd.Hp * tsz + (((size_t)nd.Hp * tsz + 15) & ~(size_t)15);
-    for (c->ct_boxes = dr::kWavesPerWG; c->ct_boxes > 1; c->ct_boxes /= 2)
-      if (ct_base + c->ct_boxes * dr::CtLds::bytes(true) + 16 <= kMaxLds) break;
-    c->ct_lds = ct_base + c->ct_boxes * dr::CtLds::bytes(true) + 16;
+    // the CT closed loop: the controller step has the stepwise reach's on-chip state; each
+    // box's state between the launches (n_0 <= 16 states)
+    c->ct_fn = nd.n[0] <= dr::kCtMax ? kernel_for(c, DR_KIND_CT, nd.NT, 0) : nullptr;
+    c->ct_lds = lds_bytes(c, Q_REACH, nd);
     if (c->ct_fn && c->ct_lds <= kMaxLds) {
       if ((e = hipFuncSetAttribute(c->ct_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c->ct_lds)) != hipSuccess)
         return bail(hip_fail(c, e, "hipFuncSetAttribute"));
       c->ct_grid = persistent_grid(c, c->ct_fn, c->ct_lds, Q_REACH);
+      if ((e = ctx_alloc(c, &c->ct_state, sizeof(double) * dr::kCtState * std::max(c->max_sub, 1))) != hipSuccess)
+        return bail(hip_fail(c, e, "hipMalloc CT state"));
     } else {
       c->ct_fn = nullptr;
     }
@@ -1107,13 +1107,12 @@ dr_status dr_flowpipe_ct(const dr_ct_field* f, const dr_ct_options* o, int n_sub
   if (!xc || !xr || !boxes) return fail(nullptr, DR_EINVAL, "x_center, x_radius and boxes are required");
   dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
   ca.batch.n_sub = n_sub; ca.batch.xc = xc; ca.batch.xr = xr;
-  ca.boxes_per_wg = 1;
   int dev = 0, cus = 0, nb = 0;
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess ||
       (e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return hip_fail(nullptr, e, "device query");
-  const size_t lds = dr::CtLds::bytes(false);
+  const size_t lds = dr::CtLds::bytes(0);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)dr::k_flowpipe_ct, 64, lds) != hipSuccess || nb < 1)
     nb = 1;
   const int grid = (int)std::min<long long>((long long)nb * std::max(cus, 1), n_sub);
@@ -1149,11 +1148,27 @@ dr_status dr_reach_ct(dr_ctx* c, const dr_ct_field* f, const dr_ct_options* o, c
   if (b->n_sub == 0) return DR_OK;
   dr::CtArgs ca = ct_args(f, o, boxes, segs, status);
   ca.batch = c->batch; ca.sc = c->sc; ca.sc.st_out = nullptr;
-  ca.boxes_per_wg = c->ct_boxes;
+  ca.state = c->ct_state;
+  // per control interval: certify every box's controller, then K held-input flowpipe
+  // steps of every box (the state stays in c->ct_state between the launches)
+  int nb = 0;
+  const size_t flds = dr::CtLds::bytes(f->n_u);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)dr::k_flowpipe_ct_held, 64, flds) != hipSuccess ||
+      nb < 1)
+    nb = 1;
+  const int fgrid = (int)std::min<long long>((long long)nb * c->cus, b->n_sub);
+  const int cgrid = std::min(c->ct_grid, b->n_sub);
   int net_index = 0;
-  void* args[] = {&c->dnet, &net_index, &ca};
-  const int groups = (b->n_sub + c->ct_boxes - 1) / c->ct_boxes;
-  return launch(c, c->ct_fn, std::min(c->ct_grid, groups), c->ct_lds, args, stream);
+  for (int k = 0; k < std::max(o->intervals, 1); ++k) {
+    int seed = k == 0 ? 1 : 0, control = o->intervals > 0 ? 1 : 0;
+    void* args[] = {&c->dnet, &net_index, &ca, &seed, &control};
+    if ((st = launch(c, c->ct_fn, cgrid, c->ct_lds, args, stream)) != DR_OK) return st;
+    if (!control) break;
+    hipLaunchKernelGGL(dr::k_flowpipe_ct_held, dim3(fgrid), dim3(64), flds, stream, ca, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(c, e, "kernel launch");
+  }
+  return DR_OK;
 }
 
 dr_status dr_get_bounds(dr_ctx* c, double* l, double* u, hipStream_t stream) {

@@ -10,7 +10,7 @@ enum {
   DR_KIND_PGRAD = 4,   // k_final, dual adjoint with parameter-gradient tapes (variant 1: item copy)
   DR_KIND_JOINT = 5,   // k_reach_joint (CROWN through the unrolled closed loop)
   DR_KIND_RGRAD = 6,   // k_reach_grad (reverse pass through the stepwise reach)
-  DR_KIND_CT = 7       // k_reach_ct (continuous-time closed loop with the controller of the context)
+  DR_KIND_CT = 7       // k_ct_control (controller step of the continuous-time closed loop)
 };
 
 #define DR_DECLARE_INSTANCE(T, NT) const void* dr_instance_##T##_##NT(int kind, int variant);

@@ -46,7 +46,7 @@ const void* DR_CAT(dr_instance_, DR_T, DR_NT)(int kind, int variant) {
       return variant ? (const void*)&dr::k_final<T, NT, true, true, true> : (const void*)&dr::k_final<T, NT, true, false, true>;
     case DR_KIND_JOINT: return variant ? nullptr : (const void*)&dr::k_reach_joint<T, NT>;
     case DR_KIND_RGRAD: return variant ? nullptr : (const void*)&dr::k_reach_grad<T, NT>;
-    case DR_KIND_CT: return variant ? nullptr : (const void*)&dr::k_reach_ct<T, NT>;
+    case DR_KIND_CT: return variant ? nullptr : (const void*)&dr::k_ct_control<T, NT>;
     default: return nullptr;
   }
 }
