@@ -213,3 +213,88 @@ def test_closed_loop_argument_errors():
     with pytest.raises(DrError, match="n_state = n_u"):
         ctx.dr_reach_ct(_field(f), b, 0.02, 2, 2)
     ctx.close()
+
+
+def test_ct_full_size_sampled():
+    """The benchmarked launches (the 12-state quadrotor-shaped field, 4096 boxes, 100
+    steps, a 64x64 controller every 5 steps) on sampled boxes: the open flowpipe and the
+    FP64-controller loop against the oracle (1e-9), the FP32 rigorous loop (the bench's
+    mode) with simulated zero-order-hold trajectories inside its boxes."""
+    from paper_2605_25346_amd.api import DeviceBatch, dr_flowpipe_ct
+    from paper_2605_25346_amd.workloads import make_ct_workload
+    require_gpu()
+    wl = make_ct_workload()
+    S, N = wl.x_center.shape[0], wl.K * wl.N_ctl
+    f = ct.QuadDynamics(wl.a, wl.F, wl.G, wl.Q)
+    f0 = ct.QuadDynamics(wl.a, wl.F, None, wl.Q)
+    print(f"[ct full] S={S} N={N}", flush=True)
+    boxes, segs, st = dr_flowpipe_ct(_field(f0), wl.x_center, wl.x_radius, wl.h, N)
+    torch.cuda.synchronize()
+    boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    for s in (0, 2047, S - 1):
+        ref = ct.flowpipe(f0, wl.x_center[s], wl.x_radius[s], wl.h, N)
+        _compare(f"full open box {s}", [boxes[s]], [ref[0]], TOL64)
+    xc = torch.as_tensor(wl.x_center, device="cuda")
+    xr = torch.as_tensor(wl.x_radius, device="cuda")
+    for precision in ("f64", "f32"):
+        ctx = _controller_ctx(wl.controller, precision, S, margins=True)
+        boxes, segs, st = ctx.dr_reach_ct(_field(f), DeviceBatch.from_tensors(xc, xr), wl.h, wl.K, wl.N_ctl)
+        torch.cuda.synchronize()
+        boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+        ctx.close()
+        assert np.all(st == 0), precision
+        for s in (1, S - 2):
+            if precision == "f64":
+                ref = ct.closed_loop(f, wl.controller, wl.x_center[s], wl.x_radius[s], wl.h, wl.K, wl.N_ctl)
+                _compare(f"full loop f64 box {s}", [boxes[s]], [ref[0]], TOL64)
+            else:
+                _zoh_inside(f, wl.controller, wl.x_center[s], wl.x_radius[s], wl.h, wl.K, wl.N_ctl, boxes[s], seed=s,
+                            n=6)
+
+
+def test_ct_graph_replay():
+    """dr_flowpipe_ct and dr_reach_ct captured into one HIP graph and replayed three times
+    (the program's own eager work between the replays): every replay equals the eager
+    result bit for bit."""
+    from paper_2605_25346_amd.api import DeviceBatch, dr_flowpipe_ct
+    require_gpu()
+    rng = np.random.default_rng(30)
+    f = _quad(rng, 4, n_u=2)
+    f0 = _quad(rng, 5)
+    net = _f32_net(rng, [4, 16, 16, 2])
+    xc, xr = _boxes(rng, 40, 4, radius=(0.01, 0.04))
+    xc0, xr0 = (torch.as_tensor(a, device="cuda") for a in _boxes(rng, 40, 5))
+    ctx = _controller_ctx(net, "f32", 40)
+    batch = DeviceBatch.from_tensors(torch.as_tensor(xc, device="cuda"), torch.as_tensor(xr, device="cuda"))
+    field, field0 = _field(f), _field(f0)
+    f64 = lambda *sh: torch.zeros(*sh, dtype=torch.float64, device="cuda")
+    out = (f64(40, 13, 4, 2), f64(40, 12, 4, 2), torch.zeros(40, dtype=torch.int32, device="cuda"))
+    out0 = (f64(40, 9, 5, 2), f64(40, 8, 5, 2), torch.zeros(40, dtype=torch.int32, device="cuda"))
+
+    def step():
+        ctx.dr_reach_ct(field, batch, 0.02, 4, 3, out=out)
+        dr_flowpipe_ct(field0, xc0, xr0, 0.02, 8, out=out0)
+
+    step()
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in out + out0]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    for rep in range(3):
+        for t in out + out0:
+            t.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(out + out0, eager):
+            assert torch.equal(a, b), rep
+        _ = torch.ones(1000, device="cuda").sum().item()   # eager work between the replays
+    ctx.close()
