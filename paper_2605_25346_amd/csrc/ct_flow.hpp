@@ -6,18 +6,19 @@
 // A model is the quasi-quadratic form of Section "Representation of Reachable Sets" over
 // the generators y in [-1, 1]^m (m <= 16) of the box and the time s in [0, h]:
 //     X(y, s) = c + L y + l s + s (M y) + w s^2  (+)  [lo, hi].
-// One wavefront carries one box: lane i < n owns state component i (component-parallel,
-// n <= 16).  Dynamics: f_i(x, u) = a_i + F_i x + G_i u + x^T Q_i x (degree <= 2 in the
-// state, affine in the held input u).  A product keeps the monomials {1, y, s, s y, s^2}
-// and bounds every other one over the domain into the interval part.  Each evaluation of
-// f first forms every distinct quadratic monomial X_j X_k (j <= k) once, one per lane in
-// chunks of 16, then every component sums its terms (coefficient Q_ijk + Q_ikj off
-// the diagonal).  The step: two Picard iterations of the polynomial part from the seed
-// c + S y; the remainder J validated by the Picard image J' = I_0 + hull(0, h range(
-// f(p + J) - d/ds p)) inside J (widening while not), then refined; the step-end model
-// c + l h + w h^2 + (L + h M) y (+) J; the remainder is then absorbed into the linear part
-// (S <- S diag(1 + |S^-1| rad J), centre += mid J) when S is well conditioned, and a held
-// input's model follows the change of generators.  Arithmetic is FP64 without outward
+// One wavefront carries one box (n <= 16 state components).  Dynamics: f_i(x, u) = a_i +
+// F_i x + G_i u + x^T Q_i x (degree <= 2 in the state, affine in the held input u).  A
+// product keeps the monomials {1, y, s, s y, s^2} and bounds every other one over the
+// domain into the interval part.  Each evaluation of f first forms every distinct
+// quadratic monomial X_j X_k (j <= k) once, one per lane in chunks of 16; the sum of all
+// terms (coefficient Q_ijk + Q_ikj off the diagonal) is then a product of the coefficient
+// matrix with the terms' models on the FP64 matrix cores (their L and M parts), the
+// scalar and interval parts on the vector units.  The step: two Picard iterations of the
+// polynomial part from the seed c + S y; the remainder J validated by the Picard image
+// J' = I_0 + hull(0, h range(f(p + J) - d/ds p)) inside J (widening while not), then
+// refined; the step-end model c + l h + w h^2 + (L + h M) y (+) J; the remainder is then
+// absorbed into the linear part (S <- S diag(1 + |S^-1| rad J), centre += mid J) when S is
+// well conditioned, and a held input's model follows the change of generators.  Arithmetic is FP64 without outward
 // rounding (the rounding of these steps is not covered by a margin).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -32,7 +33,6 @@ constexpr int kCtLd = kCtMax + 1;                          // row stride of L, M
                                                            // read one per lane fall in distinct banks)
 constexpr int kCtAug = 2 * kCtMax + 1;                     // row stride of [S | I] in the inversion
 constexpr int kCtChunk = 16;                               // monomials formed per pass
-constexpr int kCtBlk = 8;                                  // coefficients fetched per block
 constexpr int kCtPairs = kCtMax * (kCtMax + 1) / 2;        // distinct monomials x_j x_k
 
 // A vector of `cap` models in LDS (structure of arrays; L and M are cap x 16 with row
@@ -132,6 +132,7 @@ struct CtLds {
   double* lo;       // 16
   double* hi;       // 16
   double* aux;      // 16: column scales of the preconditioning
+  double* sums;     // 32: per-component sums of magnitudes (L, M) of an image
   double* aug;      // 16 x 32 (row stride kCtAug): [S | I] during the inversion, then S^-1 in the
                     // right half (in the space of the monomial chunk P)
   int* pairs;       // (j << 8) | k of the monomials x_j x_k (j <= k) with a nonzero coefficient
@@ -140,7 +141,7 @@ struct CtLds {
   // the inversion's [S | I] shares the monomials' space (never live together)
   static_assert(QTL::bytes(kCtChunk) >= (size_t)kCtMax * kCtAug * sizeof(double), "[S | I] must fit the chunk");
   __host__ __device__ static constexpr size_t bytes(int n_u) {
-    return QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) + (size_t)(kCtMax * kCtLd + 4 * kCtMax) * sizeof(double) +
+    return QTL::bytes(kCtMax) + QTL::bytes(kCtChunk) + (size_t)(kCtMax * kCtLd + 6 * kCtMax) * sizeof(double) +
            (size_t)(kCtPairs + 8) * sizeof(int) + (n_u > 0 ? QTL::bytes(n_u) : 0);
   }
   __device__ void carve(double* base, int n_u) {
@@ -152,6 +153,7 @@ struct CtLds {
     lo = base; base += kCtMax;
     hi = base; base += kCtMax;
     aux = base; base += kCtMax;
+    sums = base; base += 2 * kCtMax;
     pairs = (int*)base;
     n_pairs = pairs + kCtPairs;
     U.carve((double*)(n_pairs + 8), n_u > 0 ? n_u : 1);
@@ -185,32 +187,14 @@ __device__ __forceinline__ void ct_pairs(const CtLds& C, const CtDyn& d) {
   ct_sync();
 }
 
-// A quarter of one component's model in registers: lane 16 g + i holds the scalar
-// coefficients and the interval part of component i (the same in every group) and
-// L, M at generators 4 g .. 4 g + 3.
-struct QTq {
-  double c, l, w, lo, hi, L[4], M[4];
+// An evaluation of f: the scalar part (c, l, w and the interval part) of component
+// i = lane & 15 on every lane of the component, and the L and M coefficients in the
+// output layout of the FP64 matrix cores: lane 16 g + n holds those of components
+// 4 r + g (r = 0..3) at generator n.
+struct QTd {
+  double c, l, w, lo, hi;
+  V4<double> L, M;
 };
-
-__device__ __forceinline__ QTq qq_zero() {
-  QTq q;
-  q.c = q.l = q.w = q.lo = q.hi = 0.0;
-#pragma unroll
-  for (int p = 0; p < 4; ++p) { q.L[p] = 0.0; q.M[p] = 0.0; }
-  return q;
-}
-
-// out += F T[row] on this lane's quarter (the interval part by the sign of F).
-__device__ __forceinline__ void qq_axpy(QTq& out, double F, const QTL& T, int row, int g) {
-  const double* Lr = T.L + row * kCtLd + 4 * g;
-  const double* Mr = T.M + row * kCtLd + 4 * g;
-  out.c += F * T.c[row]; out.l += F * T.l[row]; out.w += F * T.w[row];
-#pragma unroll
-  for (int p = 0; p < 4; ++p) { out.L[p] += F * Lr[p]; out.M[p] += F * Mr[p]; }
-  const double lo = T.lo[row], hi = T.hi[row];
-  if (F >= 0.0) { out.lo += F * lo; out.hi += F * hi; }
-  else { out.lo += F * hi; out.hi += F * lo; }
-}
 
 // Sum over the four lane groups of a component (bit-identical on every lane: the two
 // pairwise sums commute).
@@ -218,37 +202,70 @@ __device__ __forceinline__ double group_sum(double v) {
   v += __shfl_xor(v, 16);
   return v + __shfl_xor(v, 32);
 }
+// Sum over the 16 lanes of a lane group (butterfly: the same on every lane of the group).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  return v + __shfl_xor(v, 8);
+}
 
 // f over the models in C.X (and the held input C.U): every lane of the wavefront calls
-// it; lane 16 g + i (i < n) returns its quarter of component i.  The distinct monomials
-// are formed first, one per lane; then each component's terms are summed, the
-// coefficients split over the four lane groups.  Ends with the wavefront synchronised.
-__device__ __forceinline__ QTq ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
+// it.  The distinct monomials are formed first, one per lane; then the sum over all terms
+// (F_ij X_j, G_ik U_k, Qs_ijk X_j X_k) is one product coefficients x term models on the
+// matrix cores for the L and M parts (a 16 x 4 block of coefficients -- components x four
+// terms -- against those terms' rows, 16x16x4 FP64 steps), and for the scalar and interval
+// parts a per-lane sum over every fourth term (lane group g takes the terms 4 s + g) added
+// over the four groups.  A lane skips the interval part of its zero terms (an unbounded
+// model then stays out of the components that do not use it).  Ends with the wavefront
+// synchronised.
+__device__ __forceinline__ QTd ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4, n = d.n;
   const bool act = i < n;
-  // coefficients are fetched kCtBlk at a time (independent loads, one latency) before
-  // their terms; a lane skips its zero terms (an unbounded model then stays out of them)
-  QTq out = qq_zero();
   const int ic = act ? i : 0;
-  out.c = act ? d.a[ic] : 0.0;
-  for (int j0 = 0; j0 < n; j0 += kCtBlk) {
-    double cf[kCtBlk];
+  QTd out;
+  out.c = (act && g == 0) ? d.a[ic] : 0.0;
+  out.l = out.w = out.lo = out.hi = 0.0;
+  out.L = V4<double>{0.0, 0.0, 0.0, 0.0};
+  out.M = V4<double>{0.0, 0.0, 0.0, 0.0};
+  // one matrix-core step over four terms: this lane's term (row `row` of T, coefficient
+  // cf for component i; cf = 0 and no row when the lane has no term)
+  auto kstep = [&](double cf, const QTL& T, int row, bool valid) {
+    const int rr = valid ? row : 0;
+    const double bL = valid ? T.L[rr * kCtLd + i] : 0.0, bM = valid ? T.M[rr * kCtLd + i] : 0.0;
+    out.L = mfma16(cf, bL, out.L);
+    out.M = mfma16(cf, bM, out.M);
+    if (cf != 0.0) {
+      out.c += cf * T.c[rr]; out.l += cf * T.l[rr]; out.w += cf * T.w[rr];
+      const double lo = T.lo[rr], hi = T.hi[rr];
+      if (cf >= 0.0) { out.lo += cf * lo; out.hi += cf * hi; }
+      else { out.lo += cf * hi; out.hi += cf * lo; }
+    }
+  };
+  // linear terms: F_ij X_j, then G_ik U_k (coefficients fetched before their steps)
+  {
+    double cf[kCtMax / 4];
 #pragma unroll
-    for (int u = 0; u < kCtBlk; ++u) cf[u] = (act && j0 + u < n) ? d.F[(size_t)ic * n + j0 + u] : 0.0;
+    for (int s = 0; s < kCtMax / 4; ++s) {
+      const int t = 4 * s + g;
+      cf[s] = (act && t < n) ? d.F[(size_t)ic * n + t] : 0.0;
+    }
 #pragma unroll
-    for (int u = 0; u < kCtBlk; ++u)
-      if (cf[u] != 0.0) qq_axpy(out, cf[u], C.X, j0 + u, g);
+    for (int s = 0; s < kCtMax / 4; ++s)
+      if (4 * s < n) kstep(cf[s], C.X, 4 * s + g, 4 * s + g < n);
   }
   if (ctrl && d.G) {
-    for (int k0 = 0; k0 < d.n_u; k0 += kCtBlk) {
-      double cf[kCtBlk];
+    double cf[kCtMax / 4];
 #pragma unroll
-      for (int u = 0; u < kCtBlk; ++u) cf[u] = (act && k0 + u < d.n_u) ? d.G[(size_t)ic * d.n_u + k0 + u] : 0.0;
-#pragma unroll
-      for (int u = 0; u < kCtBlk; ++u)
-        if (cf[u] != 0.0) qq_axpy(out, cf[u], C.U, k0 + u, g);
+    for (int s = 0; s < kCtMax / 4; ++s) {
+      const int t = 4 * s + g;
+      cf[s] = (act && t < d.n_u) ? d.G[(size_t)ic * d.n_u + t] : 0.0;
     }
+#pragma unroll
+    for (int s = 0; s < kCtMax / 4; ++s)
+      if (4 * s < d.n_u) kstep(cf[s], C.U, 4 * s + g, 4 * s + g < d.n_u);
   }
+  // quadratic terms, a chunk of monomials at a time
   const int np = C.n_pairs[0];
   for (int p0 = 0; p0 < np; p0 += kCtChunk) {
     const int cnt = min(kCtChunk, np - p0);
@@ -256,24 +273,25 @@ __device__ __forceinline__ QTq ct_f(const CtLds& C, const CtDyn& d, bool ctrl, d
       const int pr = C.pairs[p0 + lane];
       qt_product(C.X, pr >> 8, pr & 255, h, C.P, lane);
     }
-    ct_sync();
-    for (int q0 = 0; q0 < cnt; q0 += kCtBlk) {
-      double cf[kCtBlk];
+    double cf[kCtChunk / 4];
 #pragma unroll
-      for (int u = 0; u < kCtBlk; ++u) {
-        cf[u] = 0.0;
-        if (act && q0 + u < cnt) {
-          const int pr = C.pairs[p0 + q0 + u];
-          const int j = pr >> 8, k = pr & 255;
-          cf[u] = d.Q[((size_t)ic * n + j) * n + k] + (j != k ? d.Q[((size_t)ic * n + k) * n + j] : 0.0);
-        }
+    for (int s = 0; s < kCtChunk / 4; ++s) {
+      const int t = 4 * s + g;
+      cf[s] = 0.0;
+      if (act && t < cnt) {
+        const int pr = C.pairs[p0 + t];
+        const int j = pr >> 8, k = pr & 255;
+        cf[s] = d.Q[((size_t)ic * n + j) * n + k] + (j != k ? d.Q[((size_t)ic * n + k) * n + j] : 0.0);
       }
-#pragma unroll
-      for (int u = 0; u < kCtBlk; ++u)
-        if (cf[u] != 0.0) qq_axpy(out, cf[u], C.P, q0 + u, g);
     }
     ct_sync();
+#pragma unroll
+    for (int s = 0; s < kCtChunk / 4; ++s)
+      if (4 * s < cnt) kstep(cf[s], C.P, 4 * s + g, 4 * s + g < cnt);
+    ct_sync();
   }
+  out.c = group_sum(out.c); out.l = group_sum(out.l); out.w = group_sum(out.w);
+  out.lo = group_sum(out.lo); out.hi = group_sum(out.hi);
   ct_sync();
   return out;
 }
@@ -300,12 +318,11 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
   }
   ct_sync();
   for (int it = 0; it < 2; ++it) {
-    const QTq fx = ct_f(C, d, ctrl, h);
-    if (act) {
-      if (g == 0) { C.X.l[i] = fx.c; C.X.w[i] = 0.5 * fx.l; }
+    const QTd fx = ct_f(C, d, ctrl, h);
+    if (act && g == 0) { C.X.l[i] = fx.c; C.X.w[i] = 0.5 * fx.l; }
+    // M of component 4 r + g at generator i (rows n.. of the product are zero)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) C.X.M[i * kCtLd + 4 * g + q] = fx.L[q];
-    }
+    for (int r = 0; r < 4; ++r) C.X.M[(4 * r + g) * kCtLd + i] = fx.L[r];
     ct_sync();
   }
   // p is the polynomial part of C.X from here on (the trial remainders only change its
@@ -316,24 +333,30 @@ __device__ __forceinline__ bool ct_step(const CtLds& C, const CtDyn& d, bool ctr
   auto picard_image = [&]() {
     if (act && g == 0) { C.X.lo[i] = Jlo; C.X.hi[i] = Jhi; }
     ct_sync();
-    QTq D = ct_f(C, d, ctrl, h);
-    double sL = 0.0, sM = 0.0;
-    if (act) {
-      D.c -= C.X.l[i]; D.l -= 2.0 * C.X.w[i];
+    const QTd D = ct_f(C, d, ctrl, h);
+    // sums of |L - M_p| and |M| over the generators, per component (matrix-core layout:
+    // a lane group's 16 lanes are the generators of components 4 r + g)
+    double aL[4], aM[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        D.L[q] -= C.X.M[i * kCtLd + 4 * g + q];
-        sL += fabs(D.L[q]); sM += fabs(D.M[q]);
-      }
+    for (int r = 0; r < 4; ++r) {
+      aL[r] = row16_sum(fabs(D.L[r] - C.X.M[(4 * r + g) * kCtLd + i]));
+      aM[r] = row16_sum(fabs(D.M[r]));
     }
-    sL = group_sum(sL); sM = group_sum(sM);
+    if (i == 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) { C.sums[4 * r + g] = aL[r]; C.sums[kCtMax + 4 * r + g] = aM[r]; }
+    }
+    ct_sync();
+    const double sL = C.sums[i], sM = C.sums[kCtMax + i];
     nlo = 0.0; nhi = 0.0;
     if (act) {
+      const double Dc = D.c - C.X.l[i], Dl = D.l - 2.0 * C.X.w[i];
       double plo, phi;
-      poly_range(D.c, sL, sM, D.l, D.w, h, plo, phi);
+      poly_range(Dc, sL, sM, Dl, D.w, h, plo, phi);
       nlo = I0lo + fmin(0.0, h * (plo + D.lo));
       nhi = I0hi + fmax(0.0, h * (phi + D.hi));
     }
+    ct_sync();
   };
   bool ok = false;
   // an unbounded initial set has no bounded remainder
