@@ -874,7 +874,8 @@ def main():
         extra["ct_quadratic12+4-64x2-4_S4096_N100"] = dict(
             cr, roofline=dict(bound="alu", achieved=cr["tflops_flowpipe"], peak=PEAK_VALU_F64, unit="TFLOP/s",
                               frac=cr["tflops_flowpipe"] / PEAK_VALU_F64, kernel="k_flowpipe_ct",
-                              note="FP64 vector peak; closed loop: tflops_closed over both parts"))
+                              note="FP64 peak (vector and matrix cores alike: the term sums run on the "
+                                   "matrix cores); closed loop: tflops_closed over both parts"))
     if leg("tightness"):
         for cfg_i, key in ((3, "equal_tightness_abcrown_8-128x4-4_vs_crown_input_splitting"),
                            (5, "equal_tightness_mixed_S16384_vs_crown_input_splitting")):
