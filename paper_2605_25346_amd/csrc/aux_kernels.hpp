@@ -403,7 +403,7 @@ __global__ void k_export_bounds(int S, int Hp_max, int H_max, const NetDev* __re
 // The flowpipe without a controller: one wavefront per box (Algorithm "Reachability of
 // CT Dynamics with TM Flowpipe"); each workgroup is one wavefront and takes boxes
 // round-robin.
-__global__ void __launch_bounds__(64) k_flowpipe_ct(CtArgs ca) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3))) k_flowpipe_ct(CtArgs ca) {
   extern __shared__ __align__(16) char ct_raw[];
   CtLds C;
   C.carve((double*)ct_raw, 0);

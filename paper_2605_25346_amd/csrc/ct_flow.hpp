@@ -10,10 +10,10 @@
 // F_i x + G_i u + x^T Q_i x (degree <= 2 in the state, affine in the held input u).  A
 // product keeps the monomials {1, y, s, s y, s^2} and bounds every other one over the
 // domain into the interval part.  Each evaluation of f first forms every distinct
-// quadratic monomial X_j X_k (j <= k) once, one per lane in chunks of 16; the sum of all
-// terms (coefficient Q_ijk + Q_ikj off the diagonal) is then a product of the coefficient
-// matrix with the terms' models on the FP64 matrix cores (their L and M parts), the
-// scalar and interval parts on the vector units.  The step: two Picard iterations of the
+// quadratic monomial X_j X_k (j <= k) once, one per quad of lanes in chunks of 16; the
+// sum of all terms (coefficient Q_ijk + Q_ikj off the diagonal) is then a product of the
+// coefficient matrix with the terms' models on the FP64 matrix cores (their L and M
+// parts), the scalar and interval parts on the vector units.  The step: two Picard iterations of the
 // polynomial part from the seed c + S y; the remainder J validated by the Picard image
 // J' = I_0 + hull(0, h range(f(p + J) - d/ds p)) inside J (widening while not), then
 // refined; the step-end model c + l h + w h^2 + (L + h M) y (+) J; the remainder is then
@@ -66,31 +66,45 @@ __device__ __forceinline__ void iv_mul(double alo, double ahi, double blo, doubl
   hi = fmax(fmax(p0, p1), fmax(p2, p3));
 }
 
+// Sum over the four lanes of a quad (the same on each of them).
+__device__ __forceinline__ double quad_sum(double v) {
+  v += __shfl_xor(v, 1);
+  return v + __shfl_xor(v, 2);
+}
+
 // dst[slot] = X_j X_k: the product truncated to the representation (the kept monomials
 // exactly, the dropped ones and the interval parts bounded over the domain), with both
-// factors read from LDS.
-__device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h, const QTL& dst, int slot) {
-  const double* aL = X.L + j * kCtLd;
-  const double* aM = X.M + j * kCtLd;
-  const double* bL = X.L + k * kCtLd;
-  const double* bM = X.M + k * kCtLd;
+// factors read from LDS.  Four lanes (a quad, `part` = 0..3) form one product: each takes
+// the generators 4 part .. 4 part + 3, the sums over the generators are combined over the
+// quad, and every lane of the quad derives the same scalar and interval parts (part 0
+// stores them).  `store` = false: the quad only takes part in the lane exchanges.
+__device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h, const QTL& dst, int slot, int part,
+                                           bool store) {
+  const double* aL = X.L + j * kCtLd + 4 * part;
+  const double* aM = X.M + j * kCtLd + 4 * part;
+  const double* bL = X.L + k * kCtLd + 4 * part;
+  const double* bM = X.M + k * kCtLd + 4 * part;
   const double ac = X.c[j], al = X.l[j], aw = X.w[j], alo_i = X.lo[j], ahi_i = X.hi[j];
   const double bc = X.c[k], bl = X.l[k], bw = X.w[k], blo_i = X.lo[k], bhi_i = X.hi[k];
   // (L_a y)(L_b y): y_p^2 in [0, 1], y_p y_r in [-1, 1]
-  double dsum_lo = 0.0, dsum_hi = 0.0, off = 0.0, sLa = 0.0, sLb = 0.0, sMa = 0.0, sMb = 0.0;
-  double* oL = dst.L + slot * kCtLd;
-  double* oM = dst.M + slot * kCtLd;
-#pragma unroll 4
-  for (int p = 0; p < kCtMax; ++p) {
+  double dsum_lo = 0.0, dsum_hi = 0.0, sd = 0.0, sLa = 0.0, sLb = 0.0, sMa = 0.0, sMb = 0.0;
+  double* oL = dst.L + slot * kCtLd + 4 * part;
+  double* oM = dst.M + slot * kCtLd + 4 * part;
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
     const double la = aL[p], lb = bL[p], ma = aM[p], mb = bM[p];
     sLa += fabs(la); sLb += fabs(lb); sMa += fabs(ma); sMb += fabs(mb);
     const double d = la * lb;
     dsum_lo += fmin(d, 0.0); dsum_hi += fmax(d, 0.0);
-    off -= fabs(d);
-    oL[p] = ac * lb + bc * la;
-    oM[p] = ac * mb + bc * ma + al * lb + bl * la;
+    sd += fabs(d);
+    if (store) {
+      oL[p] = ac * lb + bc * la;
+      oM[p] = ac * mb + bc * ma + al * lb + bl * la;
+    }
   }
-  off += sLa * sLb;
+  sLa = quad_sum(sLa); sLb = quad_sum(sLb); sMa = quad_sum(sMa); sMb = quad_sum(sMb);
+  dsum_lo = quad_sum(dsum_lo); dsum_hi = quad_sum(dsum_hi); sd = quad_sum(sd);
+  const double off = sLa * sLb - sd;
   double lo = dsum_lo - off, hi = dsum_hi + off;
   // s y y, s^2 y, s^2 y y, s^3, s^3 y, s^4
   const double t1 = h * (sLa * sMb + sMa * sLb);
@@ -107,11 +121,13 @@ __device__ __forceinline__ void qt_product(const QTL& X, int j, int k, double h,
   iv_mul(alo_i, ahi_i, blo, bhi, x0, x1); lo += x0; hi += x1;
   iv_mul(blo_i, bhi_i, alo, ahi, x0, x1); lo += x0; hi += x1;
   iv_mul(alo_i, ahi_i, blo_i, bhi_i, x0, x1); lo += x0; hi += x1;
-  dst.c[slot] = ac * bc;
-  dst.l[slot] = ac * bl + bc * al;
-  dst.w[slot] = ac * bw + bc * aw + al * bl;
-  dst.lo[slot] = lo;
-  dst.hi[slot] = hi;
+  if (store && part == 0) {
+    dst.c[slot] = ac * bc;
+    dst.l[slot] = ac * bl + bc * al;
+    dst.w[slot] = ac * bw + bc * aw + al * bl;
+    dst.lo[slot] = lo;
+    dst.hi[slot] = hi;
+  }
 }
 
 struct CtDyn {
@@ -211,14 +227,14 @@ __device__ __forceinline__ double row16_sum(double v) {
 }
 
 // f over the models in C.X (and the held input C.U): every lane of the wavefront calls
-// it.  The distinct monomials are formed first, one per lane; then the sum over all terms
-// (F_ij X_j, G_ik U_k, Qs_ijk X_j X_k) is one product coefficients x term models on the
-// matrix cores for the L and M parts (a 16 x 4 block of coefficients -- components x four
-// terms -- against those terms' rows, 16x16x4 FP64 steps), and for the scalar and interval
-// parts a per-lane sum over every fourth term (lane group g takes the terms 4 s + g) added
-// over the four groups.  A lane skips the interval part of its zero terms (an unbounded
-// model then stays out of the components that do not use it).  Ends with the wavefront
-// synchronised.
+// it.  The distinct monomials are formed first, one per quad of lanes; then the sum over
+// all terms (F_ij X_j, G_ik U_k, Qs_ijk X_j X_k) is one product coefficients x term models
+// on the matrix cores for the L and M parts (a 16 x 4 block of coefficients -- components
+// x four terms -- against those terms' rows, 16x16x4 FP64 steps), and for the scalar and
+// interval parts a per-lane sum over every fourth term (lane group g takes the terms
+// 4 s + g) added over the four groups.  A lane skips the interval part of its zero terms
+// (an unbounded model then stays out of the components that do not use it).  Ends with
+// the wavefront synchronised.
 __device__ __forceinline__ QTd ct_f(const CtLds& C, const CtDyn& d, bool ctrl, double h) {
   const int lane = threadIdx.x & 63, i = lane & 15, g = lane >> 4, n = d.n;
   const bool act = i < n;
@@ -269,9 +285,12 @@ __device__ __forceinline__ QTd ct_f(const CtLds& C, const CtDyn& d, bool ctrl, d
   const int np = C.n_pairs[0];
   for (int p0 = 0; p0 < np; p0 += kCtChunk) {
     const int cnt = min(kCtChunk, np - p0);
-    if (lane < cnt) {
-      const int pr = C.pairs[p0 + lane];
-      qt_product(C.X, pr >> 8, pr & 255, h, C.P, lane);
+    {
+      // one quad of lanes per monomial (every quad takes part; those beyond the chunk
+      // repeat its last monomial without storing it)
+      const int q = lane >> 2, qq = q < cnt ? q : cnt - 1;
+      const int pr = C.pairs[p0 + qq];
+      qt_product(C.X, pr >> 8, pr & 255, h, C.P, qq, lane & 3, q < cnt);
     }
     double cf[kCtChunk / 4];
 #pragma unroll
