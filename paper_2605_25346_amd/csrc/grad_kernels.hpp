@@ -52,9 +52,10 @@ struct WgradTile {
 };
 
 // dW_k += sum_r a(r, i) b(r, j) (and db_k += sum_r rho_r a(r, i) when `bias`): the tile's
-// rows are the summation index; blocks of 16 x 16 outputs are formed from LDS copies of
-// a 16 x 16 block of a and of b (each lane stages its own four values of a block), the
-// lane holding outputs (4 g + c, r) of the block, and added atomically to the region.
+// rows are the summation index; each 16 x 16 block of outputs is one product a^T b on the
+// matrix cores (four 16x16x4 steps over the 16 rows) from LDS copies of a 16 x 16 block
+// of a and of b (each lane stages its own four values of a block), the lane then holding
+// outputs (nrn(g, c), r) of the block, added atomically to the region.
 template <typename T, typename FA, typename FB>
 __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int ld, int ti, int tj, int ni, int nj,
                                              FA a_of, FB b_of, bool bias, int lane) {
@@ -67,15 +68,17 @@ __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int l
 #pragma unroll
       for (int i = 0; i < 4; ++i) W.B[r * 16 + nrn<T>(g, i)] = b_of(jt, i);
       sub_sync<64>();
-      T acc[4] = {0, 0, 0, 0};
-      for (int rr = 0; rr < 16; ++rr) {
-        const T bj = W.B[rr * 16 + r];
+      // D[i][j] = sum_rows A[row][i] B[row][j]: in step s lane group g brings row 4 s + g
+      // (output r of A, input r of B)
+      V4<T> acc{0, 0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] += W.A[rr * 16 + 4 * g + c] * bj;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int row = 4 * s4 + g;
+        acc = mfma16(W.A[row * 16 + r], W.B[row * 16 + r], acc);
       }
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
-        const int i = it * 16 + 4 * g + c, j = jt * 16 + r;
+        const int i = it * 16 + nrn<T>(g, c), j = jt * 16 + r;
         if (i < ni && j < nj && acc[c] != (T)0) atomicAdd(reg + (size_t)i * ld + j, acc[c]);
       }
       if (bias && jt == 0 && r == 0) {
