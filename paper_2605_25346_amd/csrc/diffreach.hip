@@ -557,7 +557,7 @@ dr_status dr_create(dr_ctx** out, const dr_network* nets, int n_nets, const dr_o
     const int tsz = c->prec == DR_PREC_F64 ? 8 : 4;
     c->rg_lds = (size_t)dr::kWavesPerWG * dr::stage_bytes_rt(tsz, nd.NT, false) +
                 (c->prec == DR_PREC_F64 ? dr::GradLds<double>::bytes(nd.Hp, nd.NT) : dr::GradLds<float>::bytes(nd.Hp, nd.NT));
-    if (c->rg_fn && c->rg_lds <= kMaxLds) {
+    if (c->rg_fn && c->rg_lds <= kMaxLds && dr::rg_slots(nd.L, nd.NT) <= dr::kRgMaxSlots && nd.np[0] == 16) {
       if ((e = hipFuncSetAttribute(c->rg_fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLds)) != hipSuccess)
         return bail(hip_fail(c, e, "hipFuncSetAttribute"));
       c->rg_grid = persistent_grid(c, c->rg_fn, c->rg_lds, Q_REACH);
@@ -939,11 +939,11 @@ static dr_status reach_joint(dr_ctx* c, const dr_batch* b, int horizon, const do
   return launch(c, c->joint_fn, grid, lds, args, stream);
 }
 
-// Workspace of dr_reach_dt_grad: the forward record of every box, the per-wave chain
-// records and cotangent buffers of the reverse kernel, then one weight-gradient region
-// per workgroup.
+// Workspace of dr_reach_dt_grad: the forward record of every box, the row-tile records
+// of one step per workgroup of the reverse kernel, then one weight-gradient region per
+// workgroup.
 struct ReachGradLayout {
-  size_t gtape_off = 0, dgb_off = 0, wreg_off = 0, total = 0, wstride = 0;
+  size_t gtape_off = 0, wreg_off = 0, total = 0, wstride = 0;
   size_t woff[dr::kMaxL] = {};
   int grid = 0;
 };
@@ -953,10 +953,8 @@ static ReachGradLayout reach_grad_layout(const dr_ctx* c, int S, int horizon) {
   const size_t tsz = c->prec == DR_PREC_F64 ? sizeof(double) : sizeof(float);
   auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
   g.grid = std::max(1, std::min(c->rg_grid, std::max(S, 1)));
-  const size_t waves = (size_t)g.grid * dr::kWavesPerWG;
   g.gtape_off = al((size_t)std::max(S, 1) * dr::reach_tape_doubles(horizon, nd.Hp) * sizeof(double));
-  g.dgb_off = g.gtape_off + waves * (nd.L - 1) * nd.NT * 256 * tsz;   // contiguous with the chain records
-  g.wreg_off = al(g.dgb_off + waves * nd.NT * 256 * tsz);
+  g.wreg_off = al(g.gtape_off + (size_t)g.grid * dr::rg_slots(nd.L, nd.NT) * dr::rg_slot_elems(nd.L, nd.NT) * tsz);
   size_t w = 0;
   for (int k = 1; k <= nd.L; ++k) {
     g.woff[k - 1] = w;

@@ -38,18 +38,28 @@ __device__ __forceinline__ double sum16(double v) {
   return v;
 }
 
-// Weight gradient of one row tile: the workgroup's region (null when not asked for),
-// the wave's LDS blocks and row cotangents, and the wave's buffer of the current layer's
-// cotangents (each lane reads back only its own entries).
+// Weight gradient: the workgroup's region (null when not asked for), and the wave's LDS
+// blocks and row cotangents for the products of one row tile.
 template <typename T>
 struct WgradTile {
-  T* reg;             // LDS accumulator or global region (generic address)
+  T* reg;             // LDS accumulator or global region
+  bool lds;           // reg is the LDS accumulator
   const size_t* woff;
   lmut<T> A;          // 16 rows x 16 outputs of W_k
   lmut<T> B;          // 16 rows x 16 inputs of W_k
   lmut<double> rho;   // 16: the rows' offset cotangents (both offsets)
-  gmut<T> dgb;        // NT x 256: cotangent over the current layer, chain layout
 };
+
+// reg[off] += v with the address space spelled out, so that the LDS accumulator takes
+// the LDS unit's atomic and the global region the global one (a generic pointer would
+// take the flat path for both)
+template <typename T>
+__device__ __forceinline__ void wacc_add(const WgradTile<T>& W, size_t off, T v) {
+  if (W.lds)
+    __hip_atomic_fetch_add((lmut<T>)(W.reg + off), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  else
+    __hip_atomic_fetch_add((gmut<T>)(W.reg + off), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // dW_k += sum_r a(r, i) b(r, j) (and db_k += sum_r rho_r a(r, i) when `bias`): the tile's
 // rows are the summation index; each 16 x 16 block of outputs is one product a^T b on the
@@ -60,7 +70,7 @@ template <typename T, typename FA, typename FB>
 __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int ld, int ti, int tj, int ni, int nj,
                                              FA a_of, FB b_of, bool bias, int lane) {
   const int r = lane & 15, g = lane >> 4;
-  T* reg = W.reg + W.woff[k - 1];
+  const size_t reg = W.woff[k - 1];
   for (int it = 0; it < ti; ++it) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) W.A[r * 16 + nrn<T>(g, i)] = a_of(it, i);
@@ -79,7 +89,7 @@ __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int l
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int i = it * 16 + nrn<T>(g, c), j = jt * 16 + r;
-        if (i < ni && j < nj && acc[c] != (T)0) atomicAdd(reg + (size_t)i * ld + j, acc[c]);
+        if (i < ni && j < nj && acc[c] != (T)0) wacc_add(W, reg + (size_t)i * ld + j, acc[c]);
       }
       if (bias && jt == 0 && r == 0) {
 #pragma unroll
@@ -87,7 +97,7 @@ __device__ __forceinline__ void wgrad_blocks(const WgradTile<T>& W, int k, int l
           double bsum = 0.0;
           for (int rr = 0; rr < 16; ++rr) bsum += W.rho[rr] * (double)W.A[rr * 16 + 4 * g + c];
           const int i = it * 16 + 4 * g + c;
-          if (i < ni && bsum != 0.0) atomicAdd(reg + (size_t)i * ld + (ld - 1), (T)bsum);
+          if (i < ni && bsum != 0.0) wacc_add(W, reg + (size_t)i * ld + (ld - 1), (T)bsum);
         }
       }
       sub_sync<64>();
@@ -123,29 +133,25 @@ __device__ __forceinline__ void chain_recorded(const NetDev& net, int K, Stage& 
 // inputs) and the row's offset cotangents rlo, rhi (of the lower / upper offset sums)
 // go back through layers 1 .. K-1; the relaxed neurons of every layer add d/ds and d/dt
 // to the step's accumulators (summed over the tile's rows); on return st holds the
-// cotangent of the seed multipliers over h_{K-1}.
+// cotangent of the seed multipliers over h_{K-1}.  The tile's record (slot, rg_slot_*
+// layout) holds the forward multipliers; when weight gradients are asked for, the
+// cotangents over every layer's input and the rows' offset cotangents are added to it
+// for the step's contraction (step_wgrad).
 template <typename T, int NT, typename Stage>
 __device__ __forceinline__ void chain_reverse(const NetDev& net, int K, Stage& st, const GradLds<T>& G,
-                                              const T (&dw)[1][4], double rlo, double rhi, int lane, gmut<T> tape,
+                                              const T (&dw)[1][4], double rlo, double rhi, int lane, gmut<T> slot,
                                               const WgradTile<T>& W) {
-  const int gq = lane >> 4;
+  const int gq = lane >> 4, L = net.L;
   const double rsum = rlo + rhi;
   const bool wg = W.reg != nullptr;
-  auto tape_g = [&](int layer, int t, int i) { return tape[(((size_t)layer * NT + t) * 4 + i) * 64 + lane]; };
-  // a'^(k) of this lane's row: the slope times the recorded multiplier
-  auto a_of_layer = [&](int k) {
-    return [&, k](int t, int i) {
-      const V4<T> rr = G.rel[(k - 1) * 16 * NT + t * 16 + gq * 4 + i];
-      return rr[0] * tape_g(k - 1, t, i);
-    };
-  };
-  auto b_buf = [&](int t, int i) { return W.dgb[((size_t)t * 4 + i) * 64 + lane]; };
+  auto tape_g = [&](int layer, int t, int i) { return slot[(((size_t)layer * NT + t) * 4 + i) * 64 + lane]; };
   if (wg) {
-    if ((lane & 15) == lane) W.rho[lane] = rsum;
+    if ((lane & 15) == lane) {
+      W.rho[lane] = rsum;
+      slot[rg_slot_rho(L, NT) + lane] = (T)rsum;
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) W.dgb[(size_t)i * 64 + lane] = dw[0][i];
-    // dW_1 += a'^(1) (x) dw, db_1 += rho a'^(1)
-    wgrad_blocks<T>(W, 1, net.np[0] + 1, NT, 1, net.n[1], net.n[0], a_of_layer(1), b_buf, true, lane);
+    for (int i = 0; i < 4; ++i) slot[rg_slot_dg(0, L, NT) + (size_t)i * 64 + lane] = dw[0][i];
   }
   {
     T dlt[NT][4];
@@ -177,15 +183,102 @@ __device__ __forceinline__ void chain_reverse(const NetDev& net, int K, Stage& s
           atomicAdd(&G.dt[base + c], dtv);
         }
         st.set(t, i, (T)dg);
-        if (wg) W.dgb[((size_t)t * 4 + i) * 64 + lane] = (T)dg;
+        if (wg) slot[rg_slot_dg(k, L, NT) + ((size_t)t * 4 + i) * 64 + lane] = (T)dg;
       }
       tile_fence<T, NT>();
     }
-    if (k < K - 1) {
-      // dW_{k+1} += a'^(k+1) (x) dg^(k), db_{k+1} += rho a'^(k+1)
-      if (wg)
-        wgrad_blocks<T>(W, k + 1, 16 * NT + 1, NT, NT, net.n[k + 1], net.n[k], a_of_layer(k + 1), b_buf, true, lane);
-      gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
+    if (k < K - 1) gemm_inplace<T, NT>(as_global(uniform_ptr((const V4<T>*)net.Wa[k])), st, lane);
+  }
+}
+
+// The weight gradients of one step from the records of its row tiles (every record
+// written and visible): for hidden layer j, dW_j[i][m] += s_i sum_rows g_j[row][i]
+// dg_{j-1}[row][m] and db_j[i] += s_i sum_rows g_j[row][i] rho[row] (a' = s g with the
+// step's shared slope s_i of neuron i), the rows being those of every record whose
+// chain passes layer j.  Items (layer j, 16-row tile of dW_j, 16-column tile or the bias
+// column) are dealt to the waves in groups of GI; for every record a lane loads four
+// rows of its column of each operand with one vector load, the next record's loads
+// issued before the current record's 16x16x4 products; each item's sums are scaled by
+// the slopes and added to the region once.
+template <typename T, int NT>
+__device__ __forceinline__ void step_wgrad(const NetDev& net, const GradLds<T>& G, const WgradTile<T>& W, gmut<T> slots,
+                                        int wid, int lane) {
+  constexpr int GI = sizeof(T) == 4 ? 8 : 4;
+  const int L = net.L, g = lane >> 4, l = lane & 15;
+  const int n_slots = rg_slots(L, NT);
+  const size_t ssz = rg_slot_elems(L, NT);
+  // column l of a 16-wide block: lane group gl, element il of the lane-major layout
+  const int pl = pos_of<T>(l), gl = pl >> 2, il = pl & 3;
+  const size_t col_off = (size_t)il * 64 + 16 * gl + 4 * g;
+  const int n_items = 2 * NT + (L - 2) * NT * (NT + 1);
+  auto next_used = [&](int s) {
+    for (++s; s < n_slots; ++s)
+      if (G.sused[s]) break;
+    return s;
+  };
+  for (int it0 = wid * GI; it0 < n_items; it0 += kWavesPerWG * GI) {
+    int jq[GI], mq[GI], tq[GI];
+#pragma unroll
+    for (int q = 0; q < GI; ++q) {
+      const int it = it0 + q;
+      if (it >= n_items) { jq[q] = L; mq[q] = 0; tq[q] = 0; continue; }   // L: no record covers it
+      if (it < 2 * NT) { jq[q] = 1; mq[q] = it >> 1; tq[q] = it & 1; }     // JT = 1 (the input tile), bias = 1
+      else {
+        const int r = it - 2 * NT;
+        jq[q] = 2 + r / (NT * (NT + 1));
+        mq[q] = (r % (NT * (NT + 1))) / (NT + 1);
+        tq[q] = r % (NT + 1);                                             // NT: the bias column
+      }
+    }
+    V4<T> acc[GI], a_c[GI], b_c[GI], a_n[GI], b_n[GI];
+#pragma unroll
+    for (int q = 0; q < GI; ++q) acc[q] = V4<T>{0, 0, 0, 0};
+    auto load = [&](int s, V4<T> (&av)[GI], V4<T> (&bv)[GI]) {
+      gmut<T> sp = slots + (size_t)s * ssz;
+#pragma unroll
+      for (int q = 0; q < GI; ++q) {
+        const int j = jq[q] < L ? jq[q] : 1;
+        const int jt_bias = j == 1 ? 1 : NT;
+        av[q] = *(gmut<V4<T>>)(sp + rg_slot_g(j, NT) + (size_t)mq[q] * 256 + col_off);
+        if (tq[q] == jt_bias)
+          bv[q] = *(gmut<V4<T>>)(sp + rg_slot_rho(L, NT) + 4 * g);
+        else
+          bv[q] = *(gmut<V4<T>>)(sp + rg_slot_dg(j - 1, L, NT) + (size_t)tq[q] * 256 + col_off);
+      }
+    };
+    int s = next_used(-1);
+    if (s < n_slots) load(s, a_c, b_c);
+    while (s < n_slots) {
+      const int sn = next_used(s);
+      if (sn < n_slots) load(sn, a_n, b_n);
+      const int Ks = s == 0 ? L : 2 + (s - 1) / NT;   // the record's chain covers layers 1 .. Ks - 1
+#pragma unroll
+      for (int q = 0; q < GI; ++q) {
+        if (jq[q] < Ks) {
+          const bool bias = tq[q] == (jq[q] == 1 ? 1 : NT);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[q] = mfma16(a_c[q][v], (bias && l != 0) ? (T)0 : b_c[q][v], acc[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < GI; ++q) { a_c[q] = a_n[q]; b_c[q] = b_n[q]; }
+      s = sn;
+    }
+#pragma unroll
+    for (int q = 0; q < GI; ++q) {
+      const int j = jq[q];
+      if (j >= L) continue;
+      const bool bias = tq[q] == (j == 1 ? 1 : NT);
+      const int nj = net.n[j], nm = net.n[j - 1], ld = net.np[j - 1] + 1;
+      const int col = bias ? ld - 1 : tq[q] * 16 + l;
+      const bool col_ok = bias ? l == 0 : col < nm;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = mq[q] * 16 + nrn<T>(g, c);
+        const T sl = G.rel[(j - 1) * 16 * NT + mq[q] * 16 + 4 * g + c][0];
+        const T v = acc[q][c] * sl;
+        if (col_ok && i < nj && v != (T)0) wacc_add(W, W.woff[j - 1] + (size_t)i * ld + col, v);
+      }
     }
   }
 }
@@ -205,24 +298,25 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
   }
   const int n0 = net.n[0], ns = net.n_state, nx = n0 - ns, n1 = net.n[1];
   const int S = ga.batch.n_sub;
-  const int wave_global = blockIdx.x * kWavesPerWG + wid;
-  gmut<T> tape = as_global_mut((T*)ga.gtape + (size_t)wave_global * (L - 1) * NT * 256);
+  // this workgroup's row-tile records of the current step
+  const int n_slots = rg_slots(L, NT);
+  gmut<T> slots = as_global_mut((T*)ga.gtape + (size_t)blockIdx.x * n_slots * rg_slot_elems(L, NT));
+  auto slot_of = [&](int sl) { return slots + (size_t)sl * rg_slot_elems(L, NT); };
   WgradTile<T> W;
   T* wglob = ga.wreg ? (T*)ga.wreg + (size_t)blockIdx.x * ga.wreg_stride : nullptr;
   if (ga.wreg && ga.wacc_lds) {
     for (size_t e = tid; e < ga.wreg_stride; e += kWG) G.wacc[e] = (T)0;
   }
   W.reg = ga.wreg ? (ga.wacc_lds ? G.wacc : wglob) : nullptr;
+  W.lds = ga.wacc_lds;
   W.woff = ga.woff;
   W.A = (lmut<T>)(G.ob + wid * 512);
   W.B = (lmut<T>)(G.ob + wid * 512 + 256);
   W.rho = (lmut<double>)(G.orho + wid * 16);
-  W.dgb = as_global_mut((T*)ga.gtape + (size_t)gridDim.x * kWavesPerWG * (L - 1) * NT * 256 +
-                        (size_t)wave_global * NT * 256);
   const bool wg = W.reg != nullptr;
   // atomic add into this workgroup's weight-gradient region: layer k, entry (i, j)
   auto wadd = [&](int k, int i, int j, double v) {
-    if (v != 0.0) atomicAdd(W.reg + ga.woff[k - 1] + (size_t)i * (net.np[k - 1] + 1) + j, (T)v);
+    if (v != 0.0) wacc_add(W, ga.woff[k - 1] + (size_t)i * (net.np[k - 1] + 1) + j, (T)v);
   };
   const double* c = G.tm;
   const double* Pm = G.tm + 16;
@@ -258,6 +352,9 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
         for (int e = tid; e < Hp; e += kWG) {
           G.l[e] = tl[e]; G.u[e] = tl[Hp + e]; G.ibl[e] = tl[2 * Hp + e]; G.ibu[e] = tl[3 * Hp + e];
           G.ds[e] = 0.0; G.dt[e] = 0.0; G.dl[e] = 0.0; G.du[e] = 0.0;
+        }
+        for (int e = tid; e < n_slots; e += kWG) G.sused[e] = 0;
+        for (int e = tid; e < Hp; e += kWG) {
           const int k = e / (16 * NT), j = e - k * 16 * NT;
           const int p = k * 16 * NT + (j & ~15) + pos_of<T>(j & 15);
           G.rel[p] = build_relax<T>(tl[e], tl[Hp + e], 0.0, 0.0, false, 1, true, 0);
@@ -275,7 +372,7 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
 #pragma unroll
           for (int i = 0; i < 4; ++i) st.set(tt, i, valid ? seed[tt * 16 + nrn<T>(gq, i)] : (T)0);
         T w[1][4];
-        chain_recorded<T, NT>(net, L, st, G.rel, G.bias, w, lane, tape);
+        chain_recorded<T, NT>(net, L, st, G.rel, G.bias, w, lane, slot_of(0));
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int m = nrn<T>(gq, i);
@@ -324,14 +421,16 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
         for (int i = 0; i < 4; ++i) dw[0][i] = (T)G.dWr[r * 16 + nrn<T>(gq, i)];
         auto st = make_stage<T, NT>(stage, lane);
         const double rlo = valid ? G.rowc[r] : 0.0, rhi = valid ? G.rowc[16 + r] : 0.0;
-        chain_reverse<T, NT>(net, L, st, G, dw, rlo, rhi, lane, tape, W);
+        chain_reverse<T, NT>(net, L, st, G, dw, rlo, rhi, lane, slot_of(0), W);
+        if (lane == 0) G.sused[0] = 1;
         if (wg) {
           // the seed g = B_r W_L: dW_L += B_r (x) dg^(L-1), db_L += rho_r B_r
           const int npL = net.np[L];
           auto a_seed = [&](int it, int i) {
             return valid ? (T)net.seedA[(size_t)r * npL + it * 16 + nrn<T>(gq, i)] : (T)0;
           };
-          auto b_buf = [&](int t, int i) { return W.dgb[((size_t)t * 4 + i) * 64 + lane]; };
+          gmut<T> dgl = slot_of(0) + rg_slot_dg(L - 1, L, NT);
+          auto b_buf = [&](int t, int i) { return dgl[((size_t)t * 4 + i) * 64 + lane]; };
           wgrad_blocks<T>(W, L, net.np[L - 1] + 1, npL / 16, NT, net.n[L], net.n[L - 1], a_seed, b_buf, true, lane);
         }
         // the seed g = B_r W_L (and the offset B_r b_L): d/dB_r
@@ -386,7 +485,8 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
 #pragma unroll
               for (int i = 0; i < 4; ++i) st.set(tt, i, valid ? Wrow[tt * 16 + nrn<T>(gq, i)] : (T)0);
             T w[1][4];
-            chain_recorded<T, NT>(net, k, st, G.rel, G.bias, w, lane, tape);
+            const int sl = 1 + (k - 2) * NT + tile;
+            chain_recorded<T, NT>(net, k, st, G.rel, G.bias, w, lane, slot_of(sl));
             // (w P)_z over the row, for the sign of each radius term
             double wv[4], wp[16];
 #pragma unroll
@@ -427,7 +527,8 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
                 if ((lane & 15) == 0) atomicAdd(&G.dI[16 + m * 16 + z], vp);
               }
             }
-            chain_reverse<T, NT>(net, k, st, G, dw, rlo, rhi, lane, tape, W);
+            chain_reverse<T, NT>(net, k, st, G, dw, rlo, rhi, lane, slot_of(sl), W);
+            if (lane == 0) G.sused[sl] = 1;
             if (wg && valid) {
               // the seed is row `neuron` of W_k (and its bias): dW_k[neuron, :] += dg^(k-1)
 #pragma unroll
@@ -435,7 +536,8 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                   const int m = tt * 16 + nrn<T>(gq, i);
-                  if (m < net.n[k - 1]) wadd(k, neuron, m, (double)W.dgb[((size_t)tt * 4 + i) * 64 + lane]);
+                  if (m < net.n[k - 1])
+                    wadd(k, neuron, m, (double)slot_of(sl)[rg_slot_dg(k - 1, L, NT) + ((size_t)tt * 4 + i) * 64 + lane]);
                 }
               if (gq == 0) wadd(k, neuron, net.np[k - 1], rlo + rhi);
             }
@@ -517,6 +619,13 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
           }
           lds_barrier();
         }
+      }
+      // ---- the step's weight gradients from its row-tile records (global memory written by
+      // every wave: a full barrier; the next step rewrites the records only after the
+      // barriers that end this one)
+      if (wg) {
+        __syncthreads();
+        step_wgrad<T, NT>(net, G, W, slots, wid, lane);
       }
       // ---- the incoming model's cotangent: actions, and the previous step's output
       if (tid < 16 && tid >= ns && tid < n0 && ga.du) ga.du[((size_t)b * H + t) * nx + (tid - ns)] = G.dI[tid];

@@ -574,6 +574,21 @@ struct JointLds {
   }
 };
 
+// Row-tile records of one step of the reverse reach pass (chain type, per workgroup): slot 0
+// holds the output rows, slot 1 + (k - 2) NT + tile the CROWN rows of hidden layer k.  A slot
+// holds, in the lane-major layout of a chain state (entry (row, 16 t + nrn(g, i)) of a
+// 16-row tile at (t 4 + i) 64 + 16 g + row): the multipliers g over h_j of every relaxed
+// layer j = 1 .. L-1 (NT tiles each), the cotangent over the input (one tile) and over
+// h_k for k = 1 .. L-1 (NT tiles each), then the rows' offset cotangents (16, padded).
+__host__ __device__ constexpr int rg_slots(int L, int NT) { return 1 + (L - 2) * NT; }
+__host__ __device__ constexpr size_t rg_slot_g(int j, int NT) { return (size_t)(j - 1) * NT * 256; }
+__host__ __device__ constexpr size_t rg_slot_dg(int k, int L, int NT) {
+  return (size_t)(L - 1) * NT * 256 + (k == 0 ? 0 : 256 + (size_t)(k - 1) * NT * 256);
+}
+__host__ __device__ constexpr size_t rg_slot_rho(int L, int NT) { return (size_t)2 * (L - 1) * NT * 256 + 256; }
+__host__ __device__ constexpr size_t rg_slot_elems(int L, int NT) { return rg_slot_rho(L, NT) + 64; }
+constexpr int kRgMaxSlots = 128;
+
 // Arguments and per-box LDS state of k_reach_grad (reverse pass through the stepwise reach).
 struct ReachGradArgs {
   BatchDev batch;
@@ -581,7 +596,7 @@ struct ReachGradArgs {
   int horizon;
   const double* tape;       // per box reach_tape_doubles(H, Hp) doubles
   const double* gV;         // S: dJ/dV_s
-  void* gtape;              // per wave: (L - 1) x NT x 256 chain-type values (multipliers g of a row tile)
+  void* gtape;              // per workgroup: rg_slots x rg_slot_elems chain-type values (row-tile records of a step)
   double* du;               // S x H x (n_0 - n_state) or null
   double* dxc;              // S x n_state or null
   double* dxr;              // S x n_state or null
@@ -621,6 +636,7 @@ struct GradLds {
   T* bias;        // Hp: hidden biases in the chain type
   int* U;         // 16 NT
   int* misc;      // 8
+  int* sused;     // kRgMaxSlots: the step's row-tile records that were written
   T* wacc;        // the workgroup's weight-gradient accumulator (when it fits in LDS)
   __host__ __device__ static size_t r16(size_t n) { return (n + 15) & ~(size_t)15; }
   __host__ __device__ static size_t bytes(int Hp, int NT) {
@@ -628,7 +644,8 @@ struct GradLds {
     return r16((size_t)Hp * sizeof(V4<T>)) + 8 * r16((size_t)Hp * sizeof(double)) + 3 * r16(304 * sizeof(double)) +
            2 * r16(256 * sizeof(double)) + r16(32 * sizeof(double)) + r16(2 * n16 * sizeof(double)) +
            r16(n16 * 16) + r16(kWavesPerWG * 512 * sizeof(T)) + r16(kWavesPerWG * 16 * sizeof(double)) +
-           r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) + r16(8 * sizeof(int));
+           r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) + r16(8 * sizeof(int)) +
+           r16(kRgMaxSlots * sizeof(int));
   }
   __device__ void carve(char* base, int Hp, int NT) {
     auto take = [&](size_t n) { char* p = base; base += r16(n); return p; };
@@ -655,6 +672,7 @@ struct GradLds {
     bias = (T*)take((size_t)Hp * sizeof(T));
     U = (int*)take(n16 * sizeof(int));
     misc = (int*)take(8 * sizeof(int));
+    sused = (int*)take(kRgMaxSlots * sizeof(int));
     wacc = (T*)base;    // beyond bytes(): present when the launch added its size
   }
 };
