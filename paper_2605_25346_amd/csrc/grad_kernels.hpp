@@ -542,54 +542,67 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
               if (gq == 0) wadd(k, neuron, net.np[k - 1], rlo + rhi);
             }
           }
-          // interval bounds in reverse: li = W relu-centre + b - |W| relu-radius, ui = ... +
-          for (int m = tid; m < 16 * NT; m += kWG) {
-            double dhc = 0.0, dhr = 0.0;
-            if (m < net.n[k - 1]) {
-              // relu centre / radius of input m (layer k-1's final bounds)
-              const double la = fmax(G.l[base - 16 * NT + m], 0.0), ub = fmax(G.u[base - 16 * NT + m], 0.0);
-              const double hc = 0.5 * (la + ub), hr = 0.5 * (ub - la);
-              for (int j = 0; j < nk; ++j) {
-                const int e = base + j;
-                const bool cu = G.ibl[e] < 0.0 && G.ibu[e] > 0.0;
-                const double dli = (cu && G.l[e] > G.ibl[e]) ? 0.0 : G.dl[e];
-                const double dui = (cu && G.u[e] < G.ibu[e]) ? 0.0 : G.du[e];
-                const double wv = (double)((const T*)net.Wn[k - 1])[(size_t)j * net.np[k - 1] + m];
-                dhc += wv * (dli + dui);
-                dhr += fabs(wv) * (dui - dli);
-                if (wg) {
-                  const double sw = wv > 0.0 ? 1.0 : (wv < 0.0 ? -1.0 : 0.0);
-                  wadd(k, j, m, (dli + dui) * hc + (dui - dli) * sw * hr);
-                  if (m == 0) wadd(k, j, net.np[k - 1], dli + dui);
+          // interval bounds in reverse: li = W relu-centre + b - |W| relu-radius, ui = ... +;
+          // the sum over the neurons j of layer k is split into P parts (thread (part, m)),
+          // whose partial sums go to the output rows' buffers Wr, dWr (512 contiguous
+          // doubles, unused in this phase) and are added in a fixed order
+          const int n16 = 16 * NT, P = kWG / n16;
+          double* hpart = G.Wr;   // P x 2 x n16 <= 512
+          {
+            const int m = tid % n16, part = tid / n16;
+            if (part < P) {
+              double dhc = 0.0, dhr = 0.0;
+              if (m < net.n[k - 1]) {
+                // relu centre / radius of input m (layer k-1's final bounds)
+                const double la = fmax(G.l[base - n16 + m], 0.0), ub = fmax(G.u[base - n16 + m], 0.0);
+                const double hc = 0.5 * (la + ub), hr = 0.5 * (ub - la);
+                const int chunk = (nk + P - 1) / P, j0 = part * chunk, j1 = min(nk, j0 + chunk);
+                for (int j = j0; j < j1; ++j) {
+                  const int e = base + j;
+                  const bool cu = G.ibl[e] < 0.0 && G.ibu[e] > 0.0;
+                  const double dli = (cu && G.l[e] > G.ibl[e]) ? 0.0 : G.dl[e];
+                  const double dui = (cu && G.u[e] < G.ibu[e]) ? 0.0 : G.du[e];
+                  const double wv = (double)((const T*)net.Wn[k - 1])[(size_t)j * net.np[k - 1] + m];
+                  dhc += wv * (dli + dui);
+                  dhr += fabs(wv) * (dui - dli);
+                  if (wg) {
+                    const double sw = wv > 0.0 ? 1.0 : (wv < 0.0 ? -1.0 : 0.0);
+                    wadd(k, j, m, (dli + dui) * hc + (dui - dli) * sw * hr);
+                    if (m == 0) wadd(k, j, net.np[k - 1], dli + dui);
+                  }
                 }
               }
+              hpart[(size_t)(2 * part) * n16 + m] = dhc;
+              hpart[(size_t)(2 * part + 1) * n16 + m] = dhr;
             }
-            G.hcr[m] = dhc;
-            G.hcr[16 * NT + m] = dhr;
           }
           lds_barrier();
-          for (int m = tid; m < 16 * NT; m += kWG) {
-            const int e = base - 16 * NT + m;
-            const double dhc = G.hcr[m], dhr = G.hcr[16 * NT + m];
+          for (int m = tid; m < n16; m += kWG) {
+            const int e = base - n16 + m;
+            double dhc = 0.0, dhr = 0.0;
+            for (int part = 0; part < P; ++part) {
+              dhc += hpart[(size_t)(2 * part) * n16 + m];
+              dhr += hpart[(size_t)(2 * part + 1) * n16 + m];
+            }
             if (G.l[e] > 0.0) G.dl[e] += 0.5 * (dhc - dhr);
             if (G.u[e] > 0.0) G.du[e] += 0.5 * (dhc + dhr);
           }
           lds_barrier();
         } else {
           // layer 1: the exact range of W_1 over the model c + P z + [I_lo, I_hi]
-          for (int j = tid; j < n1; j += kWG) {
+          for (int e = tid; e < n1 * 16; e += kWG) {
+            const int j = e >> 4, z = e & 15;
             gconst<T> W = as_global((const T*)net.Wn[0] + (size_t)j * net.np[0]);
-            for (int z = 0; z < 16; ++z) {
-              double wpz = 0.0;
-              for (int m = 0; m < n0; ++m) wpz += (double)W[m] * Pm[m * 16 + z];
-              G.wps[j * 16 + z] = wpz > 0.0 ? 1 : (wpz < 0.0 ? -1 : 0);
-            }
+            double wpz = 0.0;
+            for (int m = 0; m < n0; ++m) wpz += (double)W[m] * Pm[m * 16 + z];
+            G.wps[j * 16 + z] = wpz > 0.0 ? 1 : (wpz < 0.0 ? -1 : 0);
           }
           lds_barrier();
           {
             const int m = tid >> 4, z = tid & 15;
             double dp = 0.0, dc = 0.0, dlo = 0.0, dhi = 0.0;
             if (m < n0) {
+#pragma unroll 4
               for (int j = 0; j < n1; ++j) {
                 const double wv = (double)((const T*)net.Wn[0])[(size_t)j * net.np[0] + m];
                 const double dzc = G.dl[j] + G.du[j], dzr = G.du[j] - G.dl[j];

@@ -627,9 +627,9 @@ struct GradLds {
   double* dO;     // 304: cotangent of the model leaving the step
   double* dI;     // 304: cotangent of the model entering the step
   double* Wr;     // 256: rows W_r = A_r + w_r of the output (r x v)
-  double* dWr;    // 256: their cotangents
+  double* dWr;    // 256: their cotangents (Wr, dWr contiguous: also the partial sums of the
+                  //      interval bounds in reverse)
   double* rowc;   // 16 x 2: per-row cotangents of the offsets (output rows)
-  double* hcr;    // 2 x 16 NT: cotangents of the centre / radius of relu(h_{k-1}) (IBP in reverse)
   signed char* wps;   // 16 NT x 16: signs of (W_1 P)_jz for layer 1 in reverse
   T* ob;          // per wave 2 x 16 x 16: blocks of an outer product over a row tile (weight gradient)
   double* orho;   // per wave 16: the rows' offset cotangents
@@ -642,9 +642,8 @@ struct GradLds {
   __host__ __device__ static size_t bytes(int Hp, int NT) {
     const size_t n16 = (size_t)16 * NT;
     return r16((size_t)Hp * sizeof(V4<T>)) + 8 * r16((size_t)Hp * sizeof(double)) + 3 * r16(304 * sizeof(double)) +
-           2 * r16(256 * sizeof(double)) + r16(32 * sizeof(double)) + r16(2 * n16 * sizeof(double)) +
-           r16(n16 * 16) + r16(kWavesPerWG * 512 * sizeof(T)) + r16(kWavesPerWG * 16 * sizeof(double)) +
-           r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) + r16(8 * sizeof(int)) +
+           2 * r16(256 * sizeof(double)) + r16(32 * sizeof(double)) + r16(n16 * 16) +
+           r16(kWavesPerWG * 512 * sizeof(T)) + r16(kWavesPerWG * 16 * sizeof(double)) + r16((size_t)Hp * sizeof(T)) + r16(n16 * sizeof(int)) + r16(8 * sizeof(int)) +
            r16(kRgMaxSlots * sizeof(int));
   }
   __device__ void carve(char* base, int Hp, int NT) {
@@ -665,7 +664,6 @@ struct GradLds {
     Wr = (double*)take(256 * sizeof(double));
     dWr = (double*)take(256 * sizeof(double));
     rowc = (double*)take(32 * sizeof(double));
-    hcr = (double*)take(2 * n16 * sizeof(double));
     wps = (signed char*)take(n16 * 16);
     ob = (T*)take(kWavesPerWG * 512 * sizeof(T));
     orho = (double*)take(kWavesPerWG * 16 * sizeof(double));
