@@ -548,6 +548,18 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
           // doubles, unused in this phase) and are added in a fixed order
           const int n16 = 16 * NT, P = kWG / n16;
           double* hpart = G.Wr;   // P x 2 x n16 <= 512
+          // the cotangents that reach each neuron's interval bounds (the side that won the
+          // intersection), into the slope / intercept cotangents of layer k (consumed by the
+          // chord step above)
+          double* dli_k = G.ds + base;
+          double* dui_k = G.dt + base;
+          for (int j = tid; j < nk; j += kWG) {
+            const int e = base + j;
+            const bool cu = G.ibl[e] < 0.0 && G.ibu[e] > 0.0;
+            dli_k[j] = (cu && G.l[e] > G.ibl[e]) ? 0.0 : G.dl[e];
+            dui_k[j] = (cu && G.u[e] < G.ibu[e]) ? 0.0 : G.du[e];
+          }
+          lds_barrier();
           {
             const int m = tid % n16, part = tid / n16;
             if (part < P) {
@@ -557,11 +569,9 @@ __global__ void __launch_bounds__(kWG) k_reach_grad(const NetDev* __restrict__ n
                 const double la = fmax(G.l[base - n16 + m], 0.0), ub = fmax(G.u[base - n16 + m], 0.0);
                 const double hc = 0.5 * (la + ub), hr = 0.5 * (ub - la);
                 const int chunk = (nk + P - 1) / P, j0 = part * chunk, j1 = min(nk, j0 + chunk);
+#pragma unroll 4
                 for (int j = j0; j < j1; ++j) {
-                  const int e = base + j;
-                  const bool cu = G.ibl[e] < 0.0 && G.ibu[e] > 0.0;
-                  const double dli = (cu && G.l[e] > G.ibl[e]) ? 0.0 : G.dl[e];
-                  const double dui = (cu && G.u[e] < G.ibu[e]) ? 0.0 : G.du[e];
+                  const double dli = dli_k[j], dui = dui_k[j];
                   const double wv = (double)((const T*)net.Wn[k - 1])[(size_t)j * net.np[k - 1] + m];
                   dhc += wv * (dli + dui);
                   dhr += fabs(wv) * (dui - dli);
