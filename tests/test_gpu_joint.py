@@ -45,32 +45,35 @@ def _rollouts_inside(net, xc, xr, u, boxes, H, seed, n=2000):
             X = V @ net.A.T + y @ net.B.T
 
 
-def _check(tag, wl, H, u, S):
+def _check(tag, wl, H, u, S, sample=None):
+    """The GPU over all S boxes; the oracle and the comparisons over `sample` (all boxes
+    by default)."""
     net = wl.nets[0]
     n = net.A.shape[0]
-    ref = [joint.reach_joint(net, wl.batch.x_center[s][:n], wl.batch.x_radius[s][:n], H,
-                             None if u is None else u[s][:H]) for s in range(S)]
+    idx = list(range(S)) if sample is None else list(sample)
+    ref = {s: joint.reach_joint(net, wl.batch.x_center[s][:n], wl.batch.x_radius[s][:n], H,
+                                None if u is None else u[s][:H]) for s in idx}
     for precision, margins in (("f64", True), ("f64", False), ("f32", False), ("f32", True)):
         if precision == "f32" and not all(np.array_equal(W, W.astype(np.float32)) for W in net.Ws + net.bs):
             continue     # FP64 weights run FP64 chains only (the network is its weights)
         boxes, st, rows = _run(wl, precision, margins, H, None if u is None else u[:, :H])
         assert np.all(st == 0), st
-        gaps = np.array([rel_gap(boxes[s], ref[s][0]) for s in range(S)])
+        gaps = np.array([rel_gap(boxes[s], ref[s][0]) for s in idx])
         print(f"[joint {tag} {precision} margins={margins}] per-step max gap "
               + " ".join(f"{v:.1e}" for v in gaps.max(axis=(0, 2, 3))), flush=True)
         tol = TOL.get((precision, margins))
         if tol is not None:
             assert np.all(gaps <= tol), (precision, margins, gaps.max(axis=(0, 2, 3)))
         if precision == "f64":
-            want = np.array([ref[s][1]["rows"] for s in range(S)])
+            want = np.array([ref[s][1]["rows"] for s in idx])
             L = net.n_layers
-            np.testing.assert_array_equal(rows[:, :H, :L], want)
+            np.testing.assert_array_equal(rows[idx, :H, :L], want)
         if margins:
-            for s in range(S):
+            for s in idx:
                 _rollouts_inside(net, wl.batch.x_center[s][:n], wl.batch.x_radius[s][:n],
                                  None if u is None else u[s][:H], boxes[s], H, s)
         if precision == "f64" and margins:
-            for s in range(S):
+            for s in idx:
                 ob = ref[s][0]
                 sl = 1e-9 * np.maximum(1, np.abs(ob))
                 assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + sl[:, :, 0])
@@ -82,6 +85,15 @@ def test_joint_candidate_dynamics():
     require_gpu()
     wl = config_workload(6, n_sub=6)
     _check("mpc 8+4-96x3-8", wl, 6, wl.meta["u"], 6)
+
+
+def test_joint_full_size_sampled():
+    """The benchmarked launch: 128 boxes x 10 steps of the 96-wide dynamics network with
+    actions (one workgroup per box, the horizon's relaxations in LDS); six boxes spread
+    over the batch against the oracle."""
+    require_gpu()
+    wl = config_workload(6, n_sub=128)
+    _check("mpc 8+4-96x3-8 S128 H10", wl, wl.horizon, wl.meta["u"], 128, sample=(0, 1, 37, 64, 101, 127))
 
 
 def test_joint_controller_loop():

@@ -80,6 +80,15 @@ def test_reach_grad_candidate_dynamics():
     _check("mpc 8+4-96x3-8", wl, 4, 4, wl.meta["u"])
 
 
+def test_reach_grad_full_size():
+    """The benchmarked launch: 128 boxes x 10 steps of the 96-wide dynamics network with
+    actions (one workgroup per box, the weight-gradient accumulators in LDS), every
+    gradient against the oracle over all 128 boxes."""
+    require_gpu()
+    wl = config_workload(6, n_sub=128)
+    _check("mpc 8+4-96x3-8 S128 H10", wl, 128, wl.horizon, wl.meta["u"], precisions=(("f64", True), ("f32", False)))
+
+
 def test_reach_grad_controller_loops():
     """Closed-loop controllers: a 64-wide one whose output matters and the 256-wide one."""
     require_gpu()
