@@ -168,6 +168,40 @@ def test_cfg4_reach_full_size_sampled(margins):
           + " ".join(f"{v:.1e}" for v in np.median(gaps.max(axis=(2, 3)), axis=0)), flush=True)
 
 
+@pytest.mark.parametrize("margins", [True, False])
+def test_candidate_reach_full_size_sampled(margins):
+    """The benchmarked candidate-action launch: 4096 action sequences x 10 steps through
+    the 96-wide dynamics network with exogenous inputs (FP32 chains), sampled sequences
+    against the oracle at every step, with the same tolerances as the controller loop."""
+    from paper_2605_25346_amd.api import BoundContext, DeviceBatch
+    require_gpu()
+    wl = config_workload(6)
+    S, H = wl.batch.n_sub, wl.horizon
+    net = wl.nets[0]
+    u = wl.meta["u"]
+    ctx = BoundContext(wl.nets, precision="f32", max_sub=S, margins=margins, tile_cfg="auto")
+    print(f"[candidates full] S={S} horizon={H} f32 margins={margins}", flush=True)
+    boxes, st = ctx.dr_reach_dt(DeviceBatch(wl.batch), H, u=u)
+    torch.cuda.synchronize()
+    boxes, st = boxes.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st == 0)
+    gaps = []
+    for s in np.random.default_rng(6).choice(S, 24, replace=False):
+        ob, _ = tm.reach_dt(net, wl.batch.x_center[s], wl.batch.x_radius[s], H, u[s])
+        g = rel_gap(boxes[s], ob)
+        if margins:
+            assert np.all(boxes[s, :, :, 0] <= ob[:, :, 0] + 1e-9 * np.maximum(1, np.abs(ob[:, :, 0]))), s
+            assert np.all(boxes[s, :, :, 1] >= ob[:, :, 1] - 1e-9 * np.maximum(1, np.abs(ob[:, :, 1]))), s
+            assert np.all(g[1] <= 5e-3), (s, g[1].max())
+        else:
+            assert np.all(g <= 3e-5), (s, g.max(axis=(1, 2)))
+        gaps.append(g)
+    gaps = np.array(gaps)
+    print(f"[candidates full f32 margins={margins}] per-step max gap "
+          + " ".join(f"{v:.1e}" for v in gaps.max(axis=(0, 2, 3))), flush=True)
+    ctx.close()
+
+
 @pytest.mark.parametrize("width", [64, 256])
 def test_reach_where_the_controller_matters(width):
     """x' = A x + B f(x) with B ~ N(0, 0.3) (the recipe of the one-step closed loop) and
