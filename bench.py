@@ -33,14 +33,15 @@ if ROOT not in sys.path:
 METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain
 # copy of known size (see profiles/); valid only for the kernel sources they were taken with.
-TRAFFIC = {"src_sha": "ae91023520b95a7e", "k_bound_init_bytes": 2.13e6 + 30.74e6}
+TRAFFIC = {"src_sha": "477065ba9ebf3719", "k_bound_init_bytes": 2.12e6 + 30.74e6}
 
 
 def kernel_src_sha():
+    """Hash of what the headline kernel is built from: its sources and the build flags."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("bound_kernels.hpp", "kernels.hpp"):
-        with open(os.path.join(ROOT, "paper_2605_25346_amd", "csrc", f), "rb") as fh:
+    for f in ("csrc/bound_kernels.hpp", "csrc/kernels.hpp", "build.py"):
+        with open(os.path.join(ROOT, "paper_2605_25346_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
