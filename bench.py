@@ -33,16 +33,21 @@ if ROOT not in sys.path:
 METRIC = "bounded subdomains/sec + α/β-opt iters/sec vs plain CROWN at equal tightness"
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE/WRITE_SIZE runs, scaled by a plain
 # copy of known size (see profiles/); valid only for the kernel sources they were taken with.
-TRAFFIC = {"src_sha": "477065ba9ebf3719", "k_bound_init_bytes": 2.12e6 + 30.74e6}
+TRAFFIC = {"src_sha": "e3daff8e5d07a394", "k_bound_init_bytes": 2.12e6 + 30.74e6}
 
 
 def kernel_src_sha():
-    """Hash of what the headline kernel is built from: its sources and the build flags."""
+    """Hash of what the headline kernel is built from: its sources and the compile flags of
+    its translation unit (FP32 chains, 64-wide layers)."""
     import hashlib
+    from paper_2605_25346_amd import build as B
     h = hashlib.sha256()
-    for f in ("csrc/bound_kernels.hpp", "csrc/kernels.hpp", "build.py"):
-        with open(os.path.join(ROOT, "paper_2605_25346_amd", f), "rb") as fh:
+    for f in ("bound_kernels.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2605_25346_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    for obj, _, extra in B._units():
+        if os.path.basename(obj) == "inst_float_4.o":
+            h.update(" ".join(B.HIPCC_FLAGS + extra).encode())
     return h.hexdigest()[:16]
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X dense FP32 / FP64 matrix peaks
 PEAK_VALU_F64 = 78.6                          # MI355X FP64 vector peak (TFLOP/s)

@@ -24,10 +24,11 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 INSTANCES = [(t, nt) for t in ("float", "double") for nt in (2, 4, 6, 8, 16)]
-# Up to 128 neurons the matrix products keep their results in the architectural registers:
-# the relaxation between two products then reads them without accumulator-register moves
-# (measured: 1.5-2% faster bound, joint and reach-gradient kernels, fewer registers, no
-# spills).  The 256-wide units keep the compiler's default (the option does not build them).
+# Up to 128 neurons (and in the host unit's kernels: the flowpipes, the contraction) the
+# matrix products keep their results in the architectural registers: the VALU work between
+# two products then reads them without accumulator-register moves (measured: 1.5-2% faster
+# bound, joint, reach-gradient and held-input flowpipe kernels, fewer registers, no spills).
+# The 256-wide units keep the compiler's default (the option does not build them).
 MFMA_VGPR_FORM = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
 MFMA_VGPR_FORM_NT = (2, 4, 6, 8)
 HEADERS = ["kernels.hpp", "bound_kernels.hpp", "aux_kernels.hpp", "joint_kernels.hpp", "grad_kernels.hpp", "ct_flow.hpp", "ct_kernels.hpp",
@@ -36,7 +37,7 @@ HEADERS = ["kernels.hpp", "bound_kernels.hpp", "aux_kernels.hpp", "joint_kernels
 
 def _units():
     """(object path, source, extra flags) of every translation unit."""
-    units = [(os.path.join(OBJ, "diffreach.o"), os.path.join(CSRC, "diffreach.hip"), [])]
+    units = [(os.path.join(OBJ, "diffreach.o"), os.path.join(CSRC, "diffreach.hip"), list(MFMA_VGPR_FORM))]
     for t, nt in INSTANCES:
         units.append((os.path.join(OBJ, f"inst_{t}_{nt}.o"), os.path.join(CSRC, "instances.hip"),
                       [f"-DDR_T={t}", f"-DDR_NT={nt}"] + (MFMA_VGPR_FORM if nt in MFMA_VGPR_FORM_NT else [])))
